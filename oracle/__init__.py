@@ -1,0 +1,236 @@
+"""CPU oracle for the state-vector simulator -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  The product library never loads it, and it shares
+no code with the GPU path: it takes circuits and Pauli sums as produced by the
+``workloads`` generators and computes, one gate at a time in complex128, what
+the simulator must produce.
+
+The arithmetic lives in ``qsv_oracle.c`` (plain C, built with gcc); this file
+only marshals numpy arrays and strings calls together:
+
+* ``run``           apply a circuit's gates in order (Sec. 4.3.2: gate-level
+                    simulation of the whole state).
+* ``expectation``   sum_t c_t <psi|P_t|psi> (Pauli sums, built term by term).
+* ``measure``/``sample``/``dealloc``/``prob_bits``/``probs``: the reductions.
+* ``grad_param_shift`` / ``grad_fd``: gradients of <H> by re-running the
+  forward circuit; the shift rule is exact for exp(-i theta P / 2) gates.
+
+Parity status of every function is stated in the module docstring of the
+test that pins it (tests/test_oracle_pins.py).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qsv_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no GPU toolchain involved)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c99",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        c_d, c_i, c_u64 = ctypes.c_double, ctypes.c_int, ctypes.c_uint64
+        lib.oracle_apply.argtypes = [P(c_d), c_i, P(c_d), c_i, P(c_i), c_i, P(c_i)]
+        lib.oracle_apply.restype = c_i
+        lib.oracle_probs.argtypes = [P(c_d), c_i, P(c_d)]
+        lib.oracle_probs.restype = None
+        lib.oracle_prob_bits.argtypes = [P(c_d), c_i, c_i, P(c_i), P(c_i)]
+        lib.oracle_prob_bits.restype = c_d
+        lib.oracle_expectation.argtypes = [P(c_d), c_i, c_i, P(c_u64), P(c_u64), P(c_d),
+                                           P(c_d), P(c_d)]
+        lib.oracle_expectation.restype = c_d
+        lib.oracle_measure.argtypes = [P(c_d), c_i, c_i, c_d, P(c_d)]
+        lib.oracle_measure.restype = c_i
+        lib.oracle_sample.argtypes = [P(c_d), c_i, c_i, P(c_d), P(c_u64)]
+        lib.oracle_sample.restype = c_i
+        lib.oracle_dealloc.argtypes = [P(c_d), c_i, c_i, c_d, P(c_d)]
+        lib.oracle_dealloc.restype = c_i
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _up(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _nq(psi: np.ndarray) -> int:
+    n = int(psi.size).bit_length() - 1
+    assert psi.size == 1 << n and psi.dtype == np.complex128 and psi.flags.c_contiguous
+    return n
+
+
+def zero_state(n: int) -> np.ndarray:
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1.0
+    return psi
+
+
+def basis_state(n: int, x: int) -> np.ndarray:
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[x] = 1.0
+    return psi
+
+
+def apply(psi: np.ndarray, matrix, targets: Sequence[int], controls: Sequence[int] = ()):
+    """Apply one gate in place (qubit q = bit q)."""
+    n = _nq(psi)
+    u = np.ascontiguousarray(matrix, dtype=np.complex128)
+    k = len(targets)
+    assert u.shape == (1 << k, 1 << k)
+    t = np.ascontiguousarray(targets, dtype=np.intc)
+    c = np.ascontiguousarray(controls if len(controls) else [0], dtype=np.intc)
+    qs = list(targets) + list(controls)
+    assert len(set(qs)) == len(qs) and all(0 <= q < n for q in qs)
+    rc = _load().oracle_apply(_dp(psi.view(np.float64)), n, _dp(u.view(np.float64)), k,
+                              _ip(t), len(controls), _ip(c))
+    if rc != 0:
+        raise ValueError("oracle_apply rejected its arguments")
+    return psi
+
+
+def run(circuit, psi: Optional[np.ndarray] = None, gates: Optional[Iterable] = None):
+    """Apply every gate of ``circuit`` (in issue order) to ``psi`` (default
+    |0...0>).  Returns the state."""
+    if psi is None:
+        psi = zero_state(circuit.n)
+    for g in (circuit.gates if gates is None else gates):
+        apply(psi, g.matrix, g.targets, g.controls)
+    return psi
+
+
+def probs(psi: np.ndarray) -> np.ndarray:
+    n = _nq(psi)
+    out = np.empty(1 << n, dtype=np.float64)
+    _load().oracle_probs(_dp(psi.view(np.float64)), n, _dp(out))
+    return out
+
+
+def prob_bits(psi: np.ndarray, qubits: Sequence[int], bits: Sequence[int]) -> float:
+    n = _nq(psi)
+    q = np.ascontiguousarray(qubits if len(qubits) else [0], dtype=np.intc)
+    b = np.ascontiguousarray(bits if len(bits) else [0], dtype=np.intc)
+    return _load().oracle_prob_bits(_dp(psi.view(np.float64)), n, len(qubits), _ip(q), _ip(b))
+
+
+def norm2(psi: np.ndarray) -> float:
+    return prob_bits(psi, [], [])
+
+
+def expectation(psi: np.ndarray, ham, return_terms: bool = False):
+    """Returns (sum_t c_t Re<P_t>, sum_t c_t Im<P_t>) [, per-term complex]."""
+    n = _nq(psi)
+    x = np.ascontiguousarray(ham.xmask, dtype=np.uint64)
+    z = np.ascontiguousarray(ham.zmask, dtype=np.uint64)
+    c = np.ascontiguousarray(ham.coeff, dtype=np.float64)
+    nt = len(c)
+    terms = np.zeros(max(nt, 1), dtype=np.complex128)
+    im = ctypes.c_double(0.0)
+    re = _load().oracle_expectation(_dp(psi.view(np.float64)), n, nt, _up(x), _up(z), _dp(c),
+                                    _dp(terms.view(np.float64)), ctypes.byref(im))
+    if return_terms:
+        return re, im.value, terms[:nt]
+    return re, im.value
+
+
+def measure(psi: np.ndarray, qubit: int, u: float):
+    """Collapse ``qubit`` in place; returns (outcome, p0, p1)."""
+    n = _nq(psi)
+    pp = np.zeros(2, dtype=np.float64)
+    out = _load().oracle_measure(_dp(psi.view(np.float64)), n, int(qubit), float(u), _dp(pp))
+    return out, float(pp[0]), float(pp[1])
+
+
+def sample(psi: np.ndarray, u: np.ndarray) -> np.ndarray:
+    n = _nq(psi)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(max(len(u), 1), dtype=np.uint64)
+    rc = _load().oracle_sample(_dp(psi.view(np.float64)), n, len(u), _dp(u), _up(out))
+    if rc != 0:
+        raise MemoryError("oracle_sample")
+    return out[:len(u)]
+
+
+def dealloc(psi: np.ndarray, qubit: int, tau: float):
+    """Returns (value, compacted state) or raises ValueError when the qubit is
+    in superposition (Sec. 4.1.1)."""
+    n = _nq(psi)
+    out = np.zeros(1 << (n - 1), dtype=np.complex128)
+    v = _load().oracle_dealloc(_dp(psi.view(np.float64)), n, int(qubit), float(tau),
+                               _dp(out.view(np.float64)))
+    if v < 0:
+        raise ValueError("qubit %d is not in a classical state" % qubit)
+    return v, out
+
+
+def allocate(psi: np.ndarray, count: int = 1) -> np.ndarray:
+    """New qubits in |0> take the next highest bit positions."""
+    out = np.zeros(psi.size << count, dtype=np.complex128)
+    out[:psi.size] = psi
+    return out
+
+
+def energy(circuit, ham) -> float:
+    psi = run(circuit)
+    return expectation(psi, ham)[0]
+
+
+def grad_param_shift(circuit, ham, params: Optional[Sequence[int]] = None) -> np.ndarray:
+    """d<H>/d theta_p = [<H>(theta_p + pi/2) - <H>(theta_p - pi/2)] / 2, exact for
+    gates exp(-i theta P / 2) (each parameter used by one gate)."""
+    theta = np.asarray(circuit.theta, dtype=np.float64)
+    params = range(len(theta)) if params is None else params
+    out = []
+    for p in params:
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += math.pi / 2
+        tm[p] -= math.pi / 2
+        out.append(0.5 * (energy(circuit.with_theta(tp), ham) -
+                          energy(circuit.with_theta(tm), ham)))
+    return np.array(out)
+
+
+def grad_fd(circuit, ham, params: Optional[Sequence[int]] = None, h: float = 1e-5) -> np.ndarray:
+    """Central finite differences of <H> with step h."""
+    theta = np.asarray(circuit.theta, dtype=np.float64)
+    params = range(len(theta)) if params is None else params
+    out = []
+    for p in params:
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        out.append((energy(circuit.with_theta(tp), ham) -
+                    energy(circuit.with_theta(tm), ham)) / (2 * h))
+    return np.array(out)
