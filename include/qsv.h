@@ -1,0 +1,269 @@
+/*
+ * qsv.h -- C ABI of libqsv, a state-vector simulator core for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The operations follow the problem statement of the ProjectQ paper
+ * (Steiger, Haener, Troyer, arXiv:1612.08091):
+ *   - qubits are allocated and deallocated at any time (Sec. 4.1.1); a qubit in
+ *     superposition may not be deallocated (Sec. 4.1.1, the simulator raises);
+ *   - gates are applied to qubits, optionally conditioned on control qubits
+ *     being |1> (Sec. 4 "Gate | qubits" syntax; Sec. 4.1.3 Control);
+ *   - the simulator evaluates gates lazily and executes them on flush
+ *     (Sec. 4.1.3 eng.flush(); Sec. 4.3.2 "lazy evaluation of gates");
+ *   - measurement in the computational basis, with results read back after a
+ *     flush (Sec. 4, minimal example; App. A.1);
+ *   - probabilities, Pauli-sum expectation values and sampling of the state,
+ *     an adjoint gradient and a batched form are extensions of the same state
+ *     vector (they do not appear in the paper).
+ *
+ * Conventions
+ *   - A state of n qubits is 2^n complex amplitudes, interleaved (re, im), in
+ *     double (QSV_C128) or float (QSV_C64).  The live qubit at bit position p
+ *     is the p-th live qubit in allocation order; new qubits take the next
+ *     highest positions; deallocating a qubit removes its bit and shifts the
+ *     higher ones down.
+ *   - Qubit ids are small non-negative integers handed out by qsv_allocate
+ *     (the lowest unused id, so ids are < n_max <= 64).
+ *   - A k-qubit gate matrix is 2^k x 2^k complex128, row-major, interleaved;
+ *     bit j of its row/column index belongs to targets[j].
+ *   - Every call returns a qsv_status.  On failure the handle keeps its
+ *     previous state and qsv_last_error() describes the failure until the next
+ *     call on that handle.
+ *   - A handle is not thread-safe; distinct handles are independent.  Device
+ *     work runs asynchronously on the handle's HIP stream; faults from it are
+ *     reported as QSV_EDEVICE by the next call that synchronises.
+ *   - Ownership: callers own every array they pass; the library copies what it
+ *     keeps.  The library owns its device buffers, except a borrowed state
+ *     buffer (qsv_options.state), which the caller must keep alive until
+ *     qsv_destroy.
+ */
+#ifndef QSV_H
+#define QSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum qsv_status {
+    QSV_OK = 0,
+    QSV_EINVAL = 1,         /* bad argument: id, size, duplicate qubit, non-finite entry */
+    QSV_ENOMEM = 2,         /* state would exceed the capacity or device memory */
+    QSV_EDEVICE = 3,        /* a HIP call or kernel failed */
+    QSV_ENOTCLASSICAL = 4,  /* deallocation of a qubit in superposition */
+    QSV_ESTATE = 5,         /* NULL or destroyed handle, or a call out of order */
+    QSV_EUNSUPPORTED = 6    /* valid request that this build does not implement */
+} qsv_status;
+
+typedef enum qsv_dtype { QSV_C128 = 0, QSV_C64 = 1 } qsv_dtype;
+
+/* Execution modes of qsv_flush. */
+typedef enum qsv_mode {
+    QSV_MODE_PERGATE = 0,   /* one kernel per gate, no fusion */
+    QSV_MODE_FUSED = 1,     /* gates fused into <= k_max-qubit unitaries, one kernel each */
+    QSV_MODE_TILED = 2      /* fused gates grouped into LDS-tile passes over HBM */
+} qsv_mode;
+
+typedef struct qsv_options {
+    int32_t n_max;          /* capacity in qubits, 1..36 */
+    int32_t dtype;          /* qsv_dtype */
+    int32_t mode;           /* qsv_mode */
+    int32_t k_max;          /* fusion width 1..5 (modes FUSED and TILED) */
+    int32_t tile_bits;      /* qubits per LDS tile in mode TILED, 0 = default */
+    int32_t queue_limit;    /* flush automatically after this many queued gates, 0 = 4096 */
+    void *stream;           /* hipStream_t used for all device work; NULL = null stream */
+    void *state;            /* optional borrowed device buffer for the state */
+    uint64_t state_bytes;   /* its size in bytes (>= 2^n_max amplitudes) */
+} qsv_options;
+
+typedef struct qsv_sim qsv_sim;
+
+/* Statistics of the work enqueued since the last qsv_reset_stats. */
+typedef struct qsv_stats {
+    uint64_t gates;         /* original gates executed */
+    uint64_t fused_ops;     /* operations after fusion */
+    uint64_t passes;        /* HBM passes over the state (kernel launches on it) */
+    uint64_t kernels;       /* all kernels launched */
+    double alg_bytes;       /* algorithmic HBM bytes of those launches */
+    double alg_flops;       /* algorithmic floating-point operations */
+    double amp_gate_updates;/* sum over original gates of 2^n */
+} qsv_stats;
+
+/* Fill *opt with defaults: n_max 30, C128, mode TILED, k_max 3, tile_bits 0. */
+qsv_status qsv_options_default(qsv_options *opt);
+
+/* Create a simulator holding 0 qubits (state |>).  No device memory is
+ * touched until the first call that needs the state on the device.
+ * EINVAL on a bad option; ENOMEM if a borrowed buffer is too small. */
+qsv_status qsv_create(const qsv_options *opt, qsv_sim **out);
+
+/* Destroy a handle and free what the library allocated.  NULL is accepted. */
+qsv_status qsv_destroy(qsv_sim *sim);
+
+/* Allocate `count` qubits in |0> (Sec. 4.1.1, allocate_qureg).  Their ids are
+ * written to ids_out[count] (may be NULL).  ENOMEM if n + count > n_max. */
+qsv_status qsv_allocate(qsv_sim *sim, int32_t count, int32_t *ids_out);
+
+/* Deallocate qubit `id` (Sec. 4.1.1).  Flushes, then computes p0 and p1 of the
+ * qubit; if p1 <= tau the qubit is |0>, if p0 <= tau it is |1>, with
+ * tau = 1e-12 (C128) or 1e-6 (C64); the state is then compacted.  Otherwise
+ * ENOTCLASSICAL and nothing changes. */
+qsv_status qsv_deallocate(qsv_sim *sim, int32_t id);
+
+/* Number of live qubits, and their ids in bit-position order (ids may be NULL;
+ * it must hold n entries). */
+qsv_status qsv_qubits(const qsv_sim *sim, int32_t *n, int32_t *ids);
+
+/* Queue gate U (2^k x 2^k complex128, row-major, interleaved) on targets[k],
+ * conditioned on controls[c] all being |1> (Sec. 4.1.3 Control).  The matrix
+ * is copied.  EINVAL for k outside 1..5, unknown or repeated qubits, or
+ * non-finite entries.  Nothing runs until a flush (Sec. 4.3.2 lazy evaluation);
+ * the queue flushes itself when it reaches queue_limit gates. */
+qsv_status qsv_apply(qsv_sim *sim, const double *U, int32_t k, const int32_t *targets,
+                     int32_t c, const int32_t *controls);
+
+/* Execute every queued gate (Sec. 4.1.3 eng.flush()): plan fusion and passes,
+ * enqueue the kernels on the stream.  Asynchronous. */
+qsv_status qsv_flush(qsv_sim *sim);
+
+/* Wait for the stream; EDEVICE if any enqueued work failed. */
+qsv_status qsv_synchronize(qsv_sim *sim);
+
+/* Sum of |psi_i|^2 over the indices where qubit qubits[j] has value bits[j]
+ * for all j < m (m = 0: the squared norm).  Flushes; synchronises. */
+qsv_status qsv_get_probability(qsv_sim *sim, int32_t m, const int32_t *qubits,
+                               const int8_t *bits, double *out);
+
+/* All 2^n probabilities |psi_i|^2 as doubles into out (host memory if
+ * out_is_device == 0, else a device pointer).  Flushes; synchronises. */
+qsv_status qsv_get_probabilities(qsv_sim *sim, double *out, int32_t out_is_device);
+
+/* <psi|H|psi> for H = sum_t coeff[t] P_t; P_t has X on the qubit ids set only
+ * in xmask[t], Z on those only in zmask[t], Y on those in both (bit q of a mask
+ * is qubit id q).  Accumulated in double.  *out = the real part; EINVAL if
+ * an id is not live.  Flushes; synchronises. */
+qsv_status qsv_get_expectation(qsv_sim *sim, int32_t nterms, const uint64_t *xmask,
+                               const uint64_t *zmask, const double *coeff, double *out);
+
+/* Measure qubits[m] one after the other in list order (App. A.1), qubit j with
+ * the caller's uniform u[j] in [0,1): outcome 0 iff u*(p0+p1) < p0; the other
+ * branch is zeroed and the kept one scaled by 1/sqrt(p_outcome).  Outcomes go
+ * to bits_out[m].  Flushes; synchronises. */
+qsv_status qsv_measure(qsv_sim *sim, int32_t m, const int32_t *qubits, const double *u,
+                       int8_t *bits_out);
+
+/* Draw `shots` samples without collapse.  Shot s returns the smallest index i
+ * with C_i > u[s] * T, C the running sum of |psi|^2 in double and T its total,
+ * or the largest i with |psi_i|^2 > 0 if none.  out[s] has bit p = value of the
+ * qubit at bit position p.  Flushes; synchronises. */
+qsv_status qsv_sample(qsv_sim *sim, int32_t shots, const double *u, uint64_t *out);
+
+/* Copy the 2^n amplitudes (the handle's dtype, interleaved) to / from a host
+ * buffer (is_device == 0) or a device buffer.  get flushes first; set drops
+ * any queued gates.  Both synchronise. */
+qsv_status qsv_get_state(qsv_sim *sim, void *dst, int32_t dst_is_device);
+qsv_status qsv_set_state(qsv_sim *sim, const void *src, int32_t src_is_device);
+
+/* Gather count amplitudes psi[indices[i]] as complex128 (re, im) pairs into
+ * the host array out[2*count] (used to check sampled amplitudes of large
+ * states).  EINVAL for an index >= 2^n.  Flushes; synchronises. */
+qsv_status qsv_get_amplitudes(qsv_sim *sim, int64_t count, const uint64_t *indices,
+                              double *out);
+
+/* Device pointer of the state and the handle's stream (for callers that
+ * wrap the buffer, e.g. as a torch tensor).  Flushes. */
+qsv_status qsv_state_pointer(qsv_sim *sim, void **ptr, void **stream);
+
+qsv_status qsv_get_stats(const qsv_sim *sim, qsv_stats *out);
+qsv_status qsv_reset_stats(qsv_sim *sim);
+
+/* Run the fusion and pass planners of the handle's mode on the queued gates
+ * without executing them (the queue is kept).  Host only, no device call.
+ * Writes the number of operations and passes; if max_ops > 0, also for
+ * operation i < max_ops: its target count ks[i], its target bit positions
+ * targets[5*i + j] (bit j of its matrix index), its control positions as a
+ * mask ctrls[i], and its matrix over the targets in mats[i*2048 ...]
+ * (2^k x 2^k complex128, row-major, interleaved).  Operations come out in
+ * execution order; applying them one after the other equals applying the
+ * queued gates. */
+qsv_status qsv_plan(qsv_sim *sim, int32_t *n_ops, int32_t *n_passes, int32_t max_ops,
+                    int32_t *ks, int32_t *targets, uint64_t *ctrls, double *mats);
+
+/* ----------------------------------------------------------------------- */
+/* Circuits with parameters, Pauli sums: flat arrays used by the adjoint      */
+/* gradient and by the batched form.                                          */
+/* ----------------------------------------------------------------------- */
+typedef enum qsv_op {
+    QSV_OP_MATRIX = 0,      /* fixed matrix from `matrices` */
+    QSV_OP_RX = 1,          /* exp(-i theta X / 2), theta = params[param[g]] */
+    QSV_OP_RY = 2,
+    QSV_OP_RZ = 3
+} qsv_op;
+
+typedef struct qsv_circuit {
+    int32_t n_qubits;
+    int32_t n_gates;
+    const int32_t *op;        /* [n_gates] qsv_op */
+    const int32_t *k;         /* [n_gates] number of targets (1 for rotations) */
+    const int32_t *c;         /* [n_gates] number of controls */
+    const int32_t *qubits;    /* [n_gates * 8]: targets then controls, qubit = bit position */
+    const int64_t *mat_off;   /* [n_gates] offset (in complex entries) into matrices, QSV_OP_MATRIX */
+    const double *matrices;   /* complex128 interleaved */
+    const int32_t *param;     /* [n_gates] parameter index for rotations, -1 otherwise */
+    int32_t n_params;
+    const double *params;     /* [n_params] angles */
+} qsv_circuit;
+
+typedef struct qsv_pauli_sum {
+    int32_t n_terms;
+    const uint64_t *xmask;    /* bit p = bit position p */
+    const uint64_t *zmask;
+    const double *coeff;
+} qsv_pauli_sum;
+
+/* Adjoint differentiation (Jones and Gacon, 2020) of <0|U^dag H U|0> with
+ * U = U_G ... U_1 over the circuit's rotation angles, in the handle's dtype:
+ *   psi = U|0>, phi = H psi, value = Re<psi|phi>; then for g = G..1:
+ *   if gate g is exp(-i theta P/2): grad[param[g]] += Im<phi|P|psi>;
+ *   psi <- U_g^dag psi; phi <- U_g^dag phi.
+ * Uses three library-owned vectors of 2^n_qubits amplitudes (the handle's own
+ * state is not touched).  grad_out has n_params entries.  Synchronises. */
+qsv_status qsv_adjoint_gradient(qsv_sim *sim, const qsv_circuit *circ,
+                                const qsv_pauli_sum *ham, double *value_out,
+                                double *grad_out);
+
+/* Batched expectation values: circuit b (gates only RX/RY/RZ/fixed matrices
+ * on <= 2 qubits) and its Pauli sum give out[b] = <0|U_b^dag H_b U_b|0>.
+ * A plan uploads the circuits once and holds an instantiated HIP graph of
+ * the persistent launch; qsv_batch_run replays it. */
+typedef struct qsv_batch qsv_batch;
+
+typedef struct qsv_batch_options {
+    int32_t dtype;            /* QSV_C64 or QSV_C128 */
+    int32_t autotune;         /* 1: time candidate tile shapes on the first run */
+    int32_t tile_bits;        /* 0 = default/autotuned */
+    int32_t use_graph;        /* 1: capture the launch in a HIP graph */
+    void *stream;
+    const char *tune_cache;   /* JSON cache path, NULL = none */
+} qsv_batch_options;
+
+qsv_status qsv_batch_create(int32_t count, const qsv_circuit *circuits,
+                            const qsv_pauli_sum *hams, const qsv_batch_options *opt,
+                            qsv_batch **out);
+qsv_status qsv_batch_run(qsv_batch *b, double *out_host);
+qsv_status qsv_batch_info(const qsv_batch *b, int32_t *tile_bits, int32_t *wg_size,
+                          double *last_ms);
+qsv_status qsv_batch_destroy(qsv_batch *b);
+
+/* Message for the last failure on `sim` (or of the last qsv_create /
+ * qsv_batch_* call when sim is NULL).  Valid until the next call. */
+const char *qsv_last_error(const qsv_sim *sim);
+
+const char *qsv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSV_H */

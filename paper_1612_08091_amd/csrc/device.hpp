@@ -1,0 +1,115 @@
+// Plain-data descriptors passed from the host runtime to the HIP kernels, and
+// the launcher entry points (implemented in the .hip files).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace qsv {
+namespace dev {
+
+// Index expansion: a group id g becomes an amplitude index by inserting a 0
+// bit at each of the npos sorted positions, then OR-ing `ones`.
+struct IndexArgs {
+    uint64_t ones = 0;
+    int32_t npos = 0;
+    uint8_t pos[64] = {};
+};
+
+// Dense k-qubit matrix for the per-gate kernels, k <= 3, passed by value.
+struct DenseArgs {
+    double mr[64];    // row-major 2^k x 2^k, real parts
+    double mi[64];    // imaginary parts
+    uint64_t off[8];  // amplitude offset of matrix index r
+};
+
+// Monomial matrix: row r takes val[r] * x[src[r]]; only rows in `touch`.
+struct MonoArgs {
+    double vr[32], vi[32];
+    uint64_t off[32];     // offset of row r
+    uint64_t srcoff[32];  // offset of the column feeding row r
+    uint32_t touch;
+};
+
+// One operation inside an LDS-tile pass.  Local positions index the tile
+// (bit i of the local index <-> i-th lowest tile position).
+enum TileOpKind : int32_t { TOP_DENSE = 0, TOP_MONO = 1, TOP_DIAG_GLOBAL = 2 };
+struct TileOp {
+    int32_t kind;
+    int32_t k;
+    uint32_t lctrl;       // local control bits (forced to 1)
+    uint32_t touch;       // MONO / DIAG: rows that change
+    uint64_t ectrl;       // control bits outside the tile: the op runs only if all are 1
+    uint64_t gctrl;       // DIAG_GLOBAL: control mask over the global index
+    int32_t npos;         // local positions where zero bits are inserted (targets + lctrl)
+    uint8_t pos[16];
+    uint8_t gt[8];        // DIAG_GLOBAL: global target positions
+    uint32_t loff[32];    // local offset of matrix index r
+    uint32_t srcoff[32];  // MONO: local offset of the column feeding row r
+    int64_t mat;          // offset (in complex entries of the tile dtype) into the pool
+    int32_t pad[2];
+};
+
+struct TileArgs {
+    int32_t m;            // tile bits
+    int32_t n_ops;
+    int32_t nq;           // state qubits
+    int32_t tile_pos_n;   // == m
+    uint8_t tpos[40];     // tile positions, ascending
+    uint64_t n_tiles;
+};
+
+// ------------------------------------------------------------------ gates
+// dtype: 0 = complex128, 1 = complex64.  Sizes in amplitudes.
+hipError_t launch_dense(int dtype, void *psi, int k, uint64_t ngroups, const IndexArgs &ia,
+                        const DenseArgs &a, hipStream_t s);
+hipError_t launch_mono(int dtype, void *psi, int k, uint64_t ngroups, const IndexArgs &ia,
+                       const MonoArgs &a, hipStream_t s);
+hipError_t launch_tile_pass(int dtype, void *psi, const TileArgs &ta, const TileOp *ops,
+                            const void *pool, hipStream_t s);
+int tile_pass_max_bits(int dtype);
+
+// ------------------------------------------------------------ state ops
+hipError_t fill_basis0(int dtype, void *psi, uint64_t dim, hipStream_t s);
+hipError_t zero_range(int dtype, void *psi, uint64_t from, uint64_t to, hipStream_t s);
+hipError_t compact(int dtype, const void *src, void *dst, int nq, int q, int value,
+                   hipStream_t s);
+hipError_t collapse(int dtype, void *psi, int nq, int q, int outcome, double scale,
+                    hipStream_t s);
+hipError_t gather(int dtype, const void *psi, const uint64_t *idx, uint64_t count,
+                  double *out, hipStream_t s);
+hipError_t convert_state(int dtype_src, const void *src, int dtype_dst, void *dst,
+                         uint64_t dim, hipStream_t s);
+
+// -------------------------------------------------------------- reductions
+// Workspace needs: see reduce_workspace_bytes().
+size_t reduce_workspace_bytes(int nq);
+// Sum of |psi_i|^2 over the indices matching (ia): out_dev[0].
+hipError_t prob_masked(int dtype, const void *psi, uint64_t ngroups, const IndexArgs &ia,
+                       double *ws, double *out_dev, hipStream_t s);
+// p0 (bit q = 0) and p1 (bit q = 1): out_dev[0..1].
+hipError_t prob_split(int dtype, const void *psi, int nq, int q, double *ws, double *out_dev,
+                      hipStream_t s);
+hipError_t probs(int dtype, const void *psi, uint64_t dim, double *out_dev, hipStream_t s);
+
+// Pauli sum.  Terms are grouped by x mask on the host; `grp_*` describe the
+// groups.  out_dev[0..1] = sum_t coeff_t <P_t> (re, im).
+struct PauliGroup {
+    uint64_t x;
+    int32_t first;        // first term index of the group
+    int32_t count;        // terms in the group
+};
+hipError_t pauli_expectation(int dtype, const void *psi, int nq, int ngroups,
+                             const PauliGroup *groups_host, const uint64_t *z_dev,
+                             const double *coef_dev, const int32_t *ny_dev, int nterms,
+                             double *ws, size_t ws_bytes, double *out_dev, hipStream_t s);
+size_t pauli_workspace_bytes(int nq, int ngroups, int nterms);
+
+// Sampling: out_dev[shots] indices.
+size_t sample_workspace_bytes(int nq);
+hipError_t sample(int dtype, const void *psi, int nq, int shots, const double *u_dev,
+                  double *ws, uint64_t *out_dev, hipStream_t s);
+
+}  // namespace dev
+}  // namespace qsv

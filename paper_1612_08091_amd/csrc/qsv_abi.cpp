@@ -1,0 +1,924 @@
+// C-ABI entry points of libqsv and the runtime behind them: handle, qubit-id
+// map, lazy gate queue, flush dispatch (per gate / fused / LDS-tile passes),
+// reductions, measurement, (de)allocation.
+//
+// Device memory for the state is materialised lazily: until a call needs the
+// amplitudes on the device, a handle only records that its state is |0...0>.
+// So creating handles, allocating qubits, queueing gates and planning work
+// without a GPU, which keeps argument validation testable on a CPU host.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/qsv.h"
+#include "device.hpp"
+#include "qsv_internal.hpp"
+
+using qsv::cd;
+using qsv::Gate;
+using qsv::Op;
+using qsv::Pass;
+using qsv::popc;
+
+struct qsv_sim {
+    qsv_options opt{};
+    int n = 0;
+    std::vector<int> id_at;            // bit position -> qubit id
+    int pos_of[64];                    // qubit id -> bit position, -1 if free
+    std::vector<Gate> queue;
+    bool materialized = false;         // device buffer holds the state
+    void *d_state = nullptr;
+    bool owns_state = false;
+    uint64_t cap_amps = 0;             // amplitudes the device buffer holds
+    hipStream_t stream = nullptr;
+    std::string err;
+    qsv_stats stats{};
+    // workspace for reductions
+    void *d_ws = nullptr;
+    size_t ws_bytes = 0;
+    double *d_small = nullptr;         // 16 doubles
+    // op pool for tile passes: pinned host staging + device copy, two slots
+    struct Slot {
+        void *h = nullptr;
+        void *d = nullptr;
+        size_t bytes = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    } slot[2];
+    int cur_slot = 0;
+    // adjoint / scratch vectors
+    void *d_vec[3] = {nullptr, nullptr, nullptr};
+    uint64_t vec_amps = 0;
+    int vec_dtype = -1;
+
+    int elem() const { return opt.dtype == QSV_C128 ? 16 : 8; }
+    uint64_t dim() const { return 1ull << n; }
+};
+
+namespace {
+
+std::mutex g_mu;
+std::unordered_set<const qsv_sim *> g_live;
+thread_local std::string g_err;
+
+bool live(const qsv_sim *s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return s && g_live.count(s);
+}
+
+qsv_status fail(qsv_sim *s, qsv_status st, const std::string &msg) {
+    if (s) s->err = msg;
+    else g_err = msg;
+    return st;
+}
+
+qsv_status hip_fail(qsv_sim *s, hipError_t e, const char *where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(s, QSV_EDEVICE, m);
+}
+
+#define QSV_HIP(s, call)                                   \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail((s), e_, #call); \
+    } while (0)
+
+#define QSV_TRY(expr)                      \
+    do {                                   \
+        qsv_status st_ = (expr);           \
+        if (st_ != QSV_OK) return st_;     \
+    } while (0)
+
+#define QSV_CHECK(s)                                                              \
+    do {                                                                          \
+        if (!live(s)) return fail(nullptr, QSV_ESTATE, "invalid or destroyed handle"); \
+        (s)->err.clear();                                                         \
+    } while (0)
+
+int default_tile_bits(int dtype) { return dtype == QSV_C128 ? 12 : 13; }
+
+// ------------------------------------------------------------- device memory
+qsv_status ensure_capacity(qsv_sim *s, int nq) {
+    const uint64_t need = 1ull << nq;
+    if (need <= s->cap_amps) return QSV_OK;
+    if (!s->owns_state && s->d_state)
+        return fail(s, QSV_ENOMEM, "borrowed state buffer too small");
+    // grow: at least 2^10 amplitudes, doubling
+    uint64_t amps = std::max<uint64_t>(need, 1024);
+    void *nb = nullptr;
+    hipError_t e = hipMalloc(&nb, amps * s->elem());
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+            return fail(s, QSV_ENOMEM, "hipMalloc of the state failed (out of device memory)");
+        return hip_fail(s, e, "hipMalloc of the state");
+    }
+    if (s->d_state && s->materialized)
+        QSV_HIP(s, hipMemcpyAsync(nb, s->d_state, s->dim() * s->elem(), hipMemcpyDeviceToDevice,
+                                  s->stream));
+    if (s->d_state) {
+        QSV_HIP(s, hipStreamSynchronize(s->stream));
+        QSV_HIP(s, hipFree(s->d_state));
+    }
+    s->d_state = nb;
+    s->cap_amps = amps;
+    s->owns_state = true;
+    return QSV_OK;
+}
+
+qsv_status materialize(qsv_sim *s) {
+    if (s->materialized) return QSV_OK;
+    QSV_TRY(ensure_capacity(s, s->n));
+    QSV_HIP(s, qsv::dev::fill_basis0(s->opt.dtype, s->d_state, s->dim(), s->stream));
+    if (!s->d_small) QSV_HIP(s, hipMalloc((void **)&s->d_small, 64 * sizeof(double)));
+    s->materialized = true;
+    return QSV_OK;
+}
+
+qsv_status ensure_ws(qsv_sim *s, size_t bytes) {
+    if (bytes <= s->ws_bytes) return QSV_OK;
+    if (s->d_ws) {
+        QSV_HIP(s, hipStreamSynchronize(s->stream));
+        QSV_HIP(s, hipFree(s->d_ws));
+        s->d_ws = nullptr;
+        s->ws_bytes = 0;
+    }
+    size_t b = std::max<size_t>(bytes, 1 << 20);
+    QSV_HIP(s, hipMalloc(&s->d_ws, b));
+    s->ws_bytes = b;
+    return QSV_OK;
+}
+
+// Stage `bytes` of host data into the current pool slot; returns the device
+// pointer.  The slot's previous upload must have completed before its host
+// buffer is overwritten.
+qsv_status stage(qsv_sim *s, const void *data, size_t bytes, void **dptr) {
+    qsv_sim::Slot &sl = s->slot[s->cur_slot];
+    s->cur_slot ^= 1;
+    if (sl.pending) {
+        QSV_HIP(s, hipEventSynchronize(sl.done));
+        sl.pending = false;
+    }
+    if (bytes > sl.bytes) {
+        QSV_HIP(s, hipStreamSynchronize(s->stream));
+        if (sl.h) QSV_HIP(s, hipHostFree(sl.h));
+        if (sl.d) QSV_HIP(s, hipFree(sl.d));
+        sl.h = sl.d = nullptr;
+        size_t b = std::max<size_t>(bytes, 1 << 20);
+        QSV_HIP(s, hipHostMalloc(&sl.h, b, hipHostMallocDefault));
+        QSV_HIP(s, hipMalloc(&sl.d, b));
+        sl.bytes = b;
+        if (!sl.done) QSV_HIP(s, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    }
+    std::memcpy(sl.h, data, bytes);
+    QSV_HIP(s, hipMemcpyAsync(sl.d, sl.h, bytes, hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(s, hipEventRecord(sl.done, s->stream));
+    sl.pending = true;
+    *dptr = sl.d;
+    return QSV_OK;
+}
+
+// --------------------------------------------------------------- launching
+void index_args(uint64_t insert_mask, uint64_t ones, qsv::dev::IndexArgs &ia) {
+    ia.npos = 0;
+    for (int p = 0; p < 64; ++p)
+        if ((insert_mask >> p) & 1) ia.pos[ia.npos++] = (uint8_t)p;
+    ia.ones = ones;
+}
+
+uint64_t offset_of(int r, const int *t, int k) {
+    uint64_t o = 0;
+    for (int j = 0; j < k; ++j)
+        if ((r >> j) & 1) o |= 1ull << t[j];
+    return o;
+}
+
+void account(qsv_sim *s, double touched_amps, double flops_per_amp) {
+    s->stats.kernels += 1;
+    s->stats.passes += 1;
+    s->stats.alg_bytes += 2.0 * touched_amps * s->elem();
+    s->stats.alg_flops += touched_amps * flops_per_amp;
+}
+
+qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes);
+
+qsv_status launch_op(qsv_sim *s, const Op &op) {
+    const int nq = s->n;
+    const int k = op.k;
+    const int c = popc(op.ctrl);
+    const uint64_t ngroups = 1ull << (nq - k - c);
+    qsv::dev::IndexArgs ia;
+    index_args(op.targets() | op.ctrl, op.ctrl, ia);
+    if (op.kind == Op::MONO) {
+        if (op.touch == 0) return QSV_OK;
+        qsv::dev::MonoArgs a{};
+        for (int r = 0; r < (1 << k); ++r) {
+            a.vr[r] = op.U[r].real();
+            a.vi[r] = op.U[r].imag();
+            a.off[r] = offset_of(r, op.t, k);
+            a.srcoff[r] = offset_of(op.perm[r], op.t, k);
+        }
+        a.touch = op.touch;
+        QSV_HIP(s, qsv::dev::launch_mono(s->opt.dtype, s->d_state, k, ngroups, ia, a, s->stream));
+        const double touched = (double)popc(op.touch) * (double)ngroups;
+        bool pure_perm = true;
+        for (int r = 0; r < (1 << k); ++r)
+            if (op.U[r] != cd(1, 0)) pure_perm = false;
+        account(s, touched, pure_perm ? 0.0 : 6.0);
+        return QSV_OK;
+    }
+    if (k <= 3) {
+        qsv::dev::DenseArgs a{};
+        const int D = 1 << k;
+        for (int i = 0; i < D * D; ++i) {
+            a.mr[i] = op.U[i].real();
+            a.mi[i] = op.U[i].imag();
+        }
+        for (int r = 0; r < D; ++r) a.off[r] = offset_of(r, op.t, k);
+        QSV_HIP(s, qsv::dev::launch_dense(s->opt.dtype, s->d_state, k, ngroups, ia, a, s->stream));
+        account(s, (double)(ngroups << k), 8.0 * D - 2.0);
+        return QSV_OK;
+    }
+    // k = 4, 5: one LDS-tile pass holding this op only
+    std::vector<Pass> one(1);
+    int m = s->opt.tile_bits > 0 ? s->opt.tile_bits : default_tile_bits(s->opt.dtype);
+    m = std::min(m, nq);
+    uint64_t tile = op.targets();
+    for (int p = 0; p < nq && popc(tile) < m; ++p) tile |= 1ull << p;
+    one[0].tile = tile;
+    one[0].ops.push_back(op);
+    return run_tile_passes(s, one);
+}
+
+// Build the device descriptors of all passes, upload them with the matrices
+// in one copy, then launch one tile kernel per pass.
+qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
+    using qsv::dev::TileOp;
+    const int nq = s->n;
+    std::vector<TileOp> tops;
+    std::vector<size_t> first(passes.size() + 1, 0);
+    std::vector<double> mats;     // complex entries as (re, im) doubles
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+        const Pass &ps = passes[pi];
+        first[pi] = tops.size();
+        int li[64];
+        int m = 0;
+        for (int p = 0; p < 64; ++p) {
+            li[p] = -1;
+            if ((ps.tile >> p) & 1) li[p] = m++;
+        }
+        for (const Op &op : ps.ops) {
+            if (op.kind == Op::MONO && op.touch == 0) continue;
+            TileOp t{};
+            t.k = op.k;
+            t.touch = op.touch;
+            t.mat = (int64_t)(mats.size() / 2);
+            const bool inside = (op.targets() & ~ps.tile) == 0;
+            if (op.kind == Op::MONO && op.diag && !inside) {
+                t.kind = qsv::dev::TOP_DIAG_GLOBAL;
+                for (int j = 0; j < op.k; ++j) t.gt[j] = (uint8_t)op.t[j];
+                t.gctrl = op.ctrl;
+                t.ectrl = 0;
+                for (int r = 0; r < (1 << op.k); ++r) {
+                    mats.push_back(op.U[r].real());
+                    mats.push_back(op.U[r].imag());
+                }
+            } else {
+                if (!inside) return fail(s, QSV_EDEVICE, "internal: mixing target outside tile");
+                t.kind = op.kind == Op::MONO ? qsv::dev::TOP_MONO : qsv::dev::TOP_DENSE;
+                uint32_t lctrl = 0;
+                uint64_t ectrl = 0;
+                for (int p = 0; p < 64; ++p)
+                    if ((op.ctrl >> p) & 1) {
+                        if (li[p] >= 0) lctrl |= 1u << li[p];
+                        else ectrl |= 1ull << p;
+                    }
+                t.lctrl = lctrl;
+                t.ectrl = ectrl;
+                uint32_t ins = lctrl;
+                int lt[qsv::kMaxK];
+                for (int j = 0; j < op.k; ++j) {
+                    lt[j] = li[op.t[j]];
+                    ins |= 1u << lt[j];
+                }
+                t.npos = 0;
+                for (int b = 0; b < 32; ++b)
+                    if ((ins >> b) & 1) t.pos[t.npos++] = (uint8_t)b;
+                for (int r = 0; r < (1 << op.k); ++r) {
+                    uint32_t o = 0;
+                    for (int j = 0; j < op.k; ++j)
+                        if ((r >> j) & 1) o |= 1u << lt[j];
+                    t.loff[r] = o;
+                }
+                if (op.kind == Op::MONO) {
+                    for (int r = 0; r < (1 << op.k); ++r) {
+                        t.srcoff[r] = t.loff[op.perm[r]];
+                        mats.push_back(op.U[r].real());
+                        mats.push_back(op.U[r].imag());
+                    }
+                } else {
+                    for (const cd &v : op.U) {
+                        mats.push_back(v.real());
+                        mats.push_back(v.imag());
+                    }
+                }
+            }
+            tops.push_back(t);
+        }
+    }
+    first[passes.size()] = tops.size();
+    // pool: [TileOp array][matrices in the state dtype]
+    const size_t ops_bytes = (tops.size() * sizeof(TileOp) + 255) & ~size_t(255);
+    const size_t nmat = mats.size();
+    const size_t mat_bytes = s->opt.dtype == QSV_C128 ? nmat * sizeof(double) : nmat * sizeof(float);
+    std::vector<unsigned char> host(ops_bytes + mat_bytes + 16);
+    if (!tops.empty()) std::memcpy(host.data(), tops.data(), tops.size() * sizeof(TileOp));
+    if (s->opt.dtype == QSV_C128) {
+        if (nmat) std::memcpy(host.data() + ops_bytes, mats.data(), mat_bytes);
+    } else {
+        float *f = reinterpret_cast<float *>(host.data() + ops_bytes);
+        for (size_t i = 0; i < nmat; ++i) f[i] = (float)mats[i];
+    }
+    void *dpool = nullptr;
+    QSV_TRY(stage(s, host.data(), host.size(), &dpool));
+    const TileOp *dops = reinterpret_cast<const TileOp *>(dpool);
+    const void *dmat = reinterpret_cast<const unsigned char *>(dpool) + ops_bytes;
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+        const Pass &ps = passes[pi];
+        const int nops = (int)(first[pi + 1] - first[pi]);
+        if (nops == 0) continue;
+        qsv::dev::TileArgs ta{};
+        ta.m = popc(ps.tile);
+        ta.nq = nq;
+        ta.n_ops = nops;
+        ta.tile_pos_n = ta.m;
+        int c = 0;
+        for (int p = 0; p < 64; ++p)
+            if ((ps.tile >> p) & 1) ta.tpos[c++] = (uint8_t)p;
+        ta.n_tiles = 1ull << (nq - ta.m);
+        QSV_HIP(s, qsv::dev::launch_tile_pass(s->opt.dtype, s->d_state, ta, dops + first[pi], dmat,
+                                              s->stream));
+        double fl = 0.0;
+        for (size_t oi = first[pi]; oi < first[pi + 1]; ++oi) {
+            const TileOp &t = tops[oi];
+            const double frac = 1.0 / (double)(1ull << popc(t.lctrl));
+            if (t.kind == qsv::dev::TOP_DENSE) fl += frac * (8.0 * (1 << t.k) - 2.0);
+            else fl += frac * 6.0 * popc(t.touch) / (double)(1 << t.k);
+        }
+        account(s, (double)s->dim(), fl);
+    }
+    return QSV_OK;
+}
+
+int tile_bits_for(const qsv_sim *s) {
+    int m = s->opt.tile_bits > 0 ? s->opt.tile_bits : default_tile_bits(s->opt.dtype);
+    return std::min(m, qsv::dev::tile_pass_max_bits(s->opt.dtype));
+}
+
+std::vector<Op> canonical_queue(const qsv_sim *s, uint64_t *dropped) {
+    std::vector<Op> ops;
+    ops.reserve(s->queue.size());
+    uint64_t drop = 0;
+    for (const Gate &g : s->queue) {
+        Op op;
+        if (qsv::canonicalize(g, op)) ops.push_back(std::move(op));
+        else ++drop;
+    }
+    if (dropped) *dropped = drop;
+    return ops;
+}
+
+qsv_status do_flush(qsv_sim *s) {
+    if (s->queue.empty()) return QSV_OK;
+    QSV_TRY(materialize(s));
+    std::vector<Op> ops = canonical_queue(s, nullptr);
+    s->stats.gates += s->queue.size();
+    s->stats.amp_gate_updates += (double)s->queue.size() * (double)s->dim();
+    const int mode = s->opt.mode;
+    if (mode == QSV_MODE_PERGATE) {
+        s->stats.fused_ops += ops.size();
+        for (const Op &op : ops) QSV_TRY(launch_op(s, op));
+    } else if (mode == QSV_MODE_FUSED) {
+        std::vector<Op> f = qsv::fuse(ops, s->opt.k_max);
+        s->stats.fused_ops += f.size();
+        for (const Op &op : f) QSV_TRY(launch_op(s, op));
+    } else {
+        const int m = std::min(tile_bits_for(s), s->n);
+        std::vector<Pass> passes = qsv::plan_passes(ops, s->n, m, 4, s->opt.k_max);
+        for (const Pass &p : passes) s->stats.fused_ops += p.ops.size();
+        QSV_TRY(run_tile_passes(s, passes));
+    }
+    s->queue.clear();
+    return QSV_OK;
+}
+
+qsv_status sync(qsv_sim *s) {
+    QSV_HIP(s, hipStreamSynchronize(s->stream));
+    return QSV_OK;
+}
+
+qsv_status check_ids(qsv_sim *s, int32_t m, const int32_t *ids, uint64_t *mask_out) {
+    uint64_t mask = 0;
+    for (int j = 0; j < m; ++j) {
+        const int id = ids[j];
+        if (id < 0 || id >= 64 || s->pos_of[id] < 0)
+            return fail(s, QSV_EINVAL, "unknown qubit id " + std::to_string(id));
+        const uint64_t b = 1ull << s->pos_of[id];
+        if (mask & b) return fail(s, QSV_EINVAL, "qubit id repeated: " + std::to_string(id));
+        mask |= b;
+    }
+    if (mask_out) *mask_out = mask;
+    return QSV_OK;
+}
+
+qsv_status prob_split_host(qsv_sim *s, int pos, double *p0, double *p1) {
+    QSV_TRY(ensure_ws(s, qsv::dev::reduce_workspace_bytes(s->n)));
+    QSV_HIP(s, qsv::dev::prob_split(s->opt.dtype, s->d_state, s->n, pos, (double *)s->d_ws,
+                                    s->d_small, s->stream));
+    double h[2];
+    QSV_HIP(s, hipMemcpyAsync(h, s->d_small, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    QSV_TRY(sync(s));
+    *p0 = h[0];
+    *p1 = h[1];
+    s->stats.kernels += 2;
+    s->stats.alg_bytes += (double)s->dim() * s->elem();
+    return QSV_OK;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+const char *qsv_version(void) { return "qsv 0.1 (gfx950)"; }
+
+const char *qsv_last_error(const qsv_sim *sim) {
+    if (sim && live(sim)) return sim->err.c_str();
+    return g_err.c_str();
+}
+
+qsv_status qsv_options_default(qsv_options *opt) {
+    if (!opt) return fail(nullptr, QSV_EINVAL, "NULL options");
+    std::memset(opt, 0, sizeof(*opt));
+    opt->n_max = 30;
+    opt->dtype = QSV_C128;
+    opt->mode = QSV_MODE_TILED;
+    opt->k_max = 3;
+    opt->tile_bits = 0;
+    opt->queue_limit = 0;
+    return QSV_OK;
+}
+
+qsv_status qsv_create(const qsv_options *opt, qsv_sim **out) {
+    if (!opt || !out) return fail(nullptr, QSV_EINVAL, "NULL argument");
+    if (opt->n_max < 1 || opt->n_max > qsv::kMaxQubits)
+        return fail(nullptr, QSV_EINVAL, "n_max must be in 1..36");
+    if (opt->dtype != QSV_C128 && opt->dtype != QSV_C64)
+        return fail(nullptr, QSV_EINVAL, "dtype must be QSV_C128 or QSV_C64");
+    if (opt->mode < QSV_MODE_PERGATE || opt->mode > QSV_MODE_TILED)
+        return fail(nullptr, QSV_EINVAL, "unknown mode");
+    if (opt->mode != QSV_MODE_PERGATE && (opt->k_max < 1 || opt->k_max > qsv::kMaxK))
+        return fail(nullptr, QSV_EINVAL, "k_max must be in 1..5");
+    const int maxm = qsv::dev::tile_pass_max_bits(opt->dtype);
+    if (opt->tile_bits < 0 || opt->tile_bits > maxm ||
+        (opt->tile_bits > 0 && opt->tile_bits < qsv::kMaxK + 1))
+        return fail(nullptr, QSV_EINVAL, "tile_bits must be 0 or in 6.." + std::to_string(maxm));
+    if (opt->queue_limit < 0) return fail(nullptr, QSV_EINVAL, "queue_limit must be >= 0");
+    const int elem = opt->dtype == QSV_C128 ? 16 : 8;
+    if (opt->state) {
+        if (opt->state_bytes < (uint64_t)elem << opt->n_max)
+            return fail(nullptr, QSV_ENOMEM, "borrowed state buffer smaller than 2^n_max amplitudes");
+    }
+    qsv_sim *s = new qsv_sim();
+    s->opt = *opt;
+    s->stream = (hipStream_t)opt->stream;
+    for (int i = 0; i < 64; ++i) s->pos_of[i] = -1;
+    if (opt->state) {
+        s->d_state = opt->state;
+        s->owns_state = false;
+        s->cap_amps = opt->state_bytes / elem;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.insert(s);
+    }
+    *out = s;
+    return QSV_OK;
+}
+
+qsv_status qsv_destroy(qsv_sim *s) {
+    if (!s) return QSV_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_live.count(s)) return fail(nullptr, QSV_ESTATE, "invalid or destroyed handle");
+        g_live.erase(s);
+    }
+    if (s->materialized || s->d_ws || s->slot[0].h || s->slot[1].h) (void)hipStreamSynchronize(s->stream);
+    if (s->owns_state && s->d_state) (void)hipFree(s->d_state);
+    if (s->d_ws) (void)hipFree(s->d_ws);
+    if (s->d_small) (void)hipFree(s->d_small);
+    for (auto &sl : s->slot) {
+        if (sl.h) (void)hipHostFree(sl.h);
+        if (sl.d) (void)hipFree(sl.d);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    for (void *v : s->d_vec)
+        if (v) (void)hipFree(v);
+    delete s;
+    return QSV_OK;
+}
+
+qsv_status qsv_allocate(qsv_sim *s, int32_t count, int32_t *ids_out) {
+    QSV_CHECK(s);
+    if (count < 0) return fail(s, QSV_EINVAL, "count must be >= 0");
+    if (s->n + count > s->opt.n_max)
+        return fail(s, QSV_ENOMEM, "allocation exceeds n_max = " + std::to_string(s->opt.n_max));
+    if (count == 0) return QSV_OK;
+    const int n_new = s->n + count;
+    if (s->materialized) {
+        QSV_TRY(ensure_capacity(s, n_new));
+        QSV_HIP(s, qsv::dev::zero_range(s->opt.dtype, s->d_state, 1ull << s->n, 1ull << n_new,
+                                        s->stream));
+    }
+    for (int c = 0; c < count; ++c) {
+        int id = 0;
+        while (s->pos_of[id] >= 0) ++id;
+        s->pos_of[id] = s->n;
+        s->id_at.push_back(id);
+        s->n += 1;
+        if (ids_out) ids_out[c] = id;
+    }
+    return QSV_OK;
+}
+
+qsv_status qsv_deallocate(qsv_sim *s, int32_t id) {
+    QSV_CHECK(s);
+    if (id < 0 || id >= 64 || s->pos_of[id] < 0)
+        return fail(s, QSV_EINVAL, "unknown qubit id " + std::to_string(id));
+    const int pos = s->pos_of[id];
+    if (s->materialized || !s->queue.empty()) {
+        QSV_TRY(do_flush(s));
+        double p0, p1;
+        QSV_TRY(prob_split_host(s, pos, &p0, &p1));
+        const double tau = s->opt.dtype == QSV_C128 ? 1e-12 : 1e-6;
+        int value;
+        if (p1 <= tau) value = 0;
+        else if (p0 <= tau) value = 1;
+        else
+            return fail(s, QSV_ENOTCLASSICAL,
+                        "qubit " + std::to_string(id) + " is in superposition (p1 = " +
+                            std::to_string(p1) + ")");
+        if (s->n == 1) {
+            // the state becomes the 0-qubit state |> = 1; keep the amplitude's phase
+            // by compacting into the first element
+        }
+        const uint64_t half = s->dim() >> 1;
+        // compact into the upper part of a scratch vector, then copy back
+        void *tmp = nullptr;
+        QSV_HIP(s, hipMalloc(&tmp, std::max<uint64_t>(half, 1) * s->elem()));
+        hipError_t e = qsv::dev::compact(s->opt.dtype, s->d_state, tmp, s->n, pos, value, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->d_state, tmp, half * s->elem(), hipMemcpyDeviceToDevice, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return hip_fail(s, e, "dealloc compaction");
+        s->stats.kernels += 1;
+        s->stats.alg_bytes += 2.0 * half * s->elem();
+    }
+    // bookkeeping: remove bit `pos`
+    s->id_at.erase(s->id_at.begin() + pos);
+    s->pos_of[id] = -1;
+    for (int p = pos; p < (int)s->id_at.size(); ++p) s->pos_of[s->id_at[p]] = p;
+    s->n -= 1;
+    return QSV_OK;
+}
+
+qsv_status qsv_qubits(const qsv_sim *s, int32_t *n, int32_t *ids) {
+    if (!live(s)) return fail(nullptr, QSV_ESTATE, "invalid or destroyed handle");
+    if (n) *n = s->n;
+    if (ids)
+        for (int p = 0; p < s->n; ++p) ids[p] = s->id_at[p];
+    return QSV_OK;
+}
+
+qsv_status qsv_apply(qsv_sim *s, const double *U, int32_t k, const int32_t *targets, int32_t c,
+                     const int32_t *controls) {
+    QSV_CHECK(s);
+    if (!U || !targets || (c > 0 && !controls)) return fail(s, QSV_EINVAL, "NULL argument");
+    if (k < 1 || k > qsv::kMaxK) return fail(s, QSV_EINVAL, "k must be in 1..5");
+    if (c < 0 || c + k > s->n) return fail(s, QSV_EINVAL, "too many qubits for the register");
+    Gate g;
+    g.k = k;
+    uint64_t seen = 0;
+    for (int j = 0; j < k; ++j) {
+        const int id = targets[j];
+        if (id < 0 || id >= 64 || s->pos_of[id] < 0)
+            return fail(s, QSV_EINVAL, "unknown target qubit id " + std::to_string(id));
+        const int p = s->pos_of[id];
+        if (seen & (1ull << p)) return fail(s, QSV_EINVAL, "qubit repeated in the gate");
+        seen |= 1ull << p;
+        g.t[j] = p;
+    }
+    for (int j = 0; j < c; ++j) {
+        const int id = controls[j];
+        if (id < 0 || id >= 64 || s->pos_of[id] < 0)
+            return fail(s, QSV_EINVAL, "unknown control qubit id " + std::to_string(id));
+        const int p = s->pos_of[id];
+        if (seen & (1ull << p)) return fail(s, QSV_EINVAL, "qubit repeated in the gate");
+        seen |= 1ull << p;
+        g.ctrl |= 1ull << p;
+    }
+    const int D = 1 << k;
+    g.U.resize((size_t)D * D);
+    for (int i = 0; i < D * D; ++i) {
+        const double re = U[2 * i], im = U[2 * i + 1];
+        if (!std::isfinite(re) || !std::isfinite(im))
+            return fail(s, QSV_EINVAL, "non-finite matrix entry");
+        g.U[i] = cd(re, im);
+    }
+    s->queue.push_back(std::move(g));
+    const int lim = s->opt.queue_limit > 0 ? s->opt.queue_limit : 4096;
+    if ((int)s->queue.size() >= lim) return do_flush(s);
+    return QSV_OK;
+}
+
+qsv_status qsv_flush(qsv_sim *s) {
+    QSV_CHECK(s);
+    return do_flush(s);
+}
+
+qsv_status qsv_synchronize(qsv_sim *s) {
+    QSV_CHECK(s);
+    if (!s->materialized) return QSV_OK;
+    return sync(s);
+}
+
+qsv_status qsv_get_probability(qsv_sim *s, int32_t m, const int32_t *qubits, const int8_t *bits,
+                               double *out) {
+    QSV_CHECK(s);
+    if (!out || m < 0 || (m > 0 && (!qubits || !bits))) return fail(s, QSV_EINVAL, "bad argument");
+    uint64_t mask;
+    QSV_TRY(check_ids(s, m, qubits, &mask));
+    uint64_t ones = 0;
+    for (int j = 0; j < m; ++j)
+        if (bits[j]) ones |= 1ull << s->pos_of[qubits[j]];
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    QSV_TRY(ensure_ws(s, qsv::dev::reduce_workspace_bytes(s->n)));
+    qsv::dev::IndexArgs ia;
+    index_args(mask, ones, ia);
+    QSV_HIP(s, qsv::dev::prob_masked(s->opt.dtype, s->d_state, 1ull << (s->n - m), ia,
+                                     (double *)s->d_ws, s->d_small, s->stream));
+    QSV_HIP(s, hipMemcpyAsync(out, s->d_small, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    s->stats.kernels += 2;
+    s->stats.alg_bytes += (double)(1ull << (s->n - m)) * s->elem();
+    return sync(s);
+}
+
+qsv_status qsv_get_probabilities(qsv_sim *s, double *out, int32_t out_is_device) {
+    QSV_CHECK(s);
+    if (!out) return fail(s, QSV_EINVAL, "NULL output");
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    s->stats.kernels += 1;
+    s->stats.alg_bytes += (double)s->dim() * (s->elem() + 8);
+    if (out_is_device) {
+        QSV_HIP(s, qsv::dev::probs(s->opt.dtype, s->d_state, s->dim(), out, s->stream));
+        return sync(s);
+    }
+    QSV_TRY(ensure_ws(s, s->dim() * sizeof(double)));
+    QSV_HIP(s, qsv::dev::probs(s->opt.dtype, s->d_state, s->dim(), (double *)s->d_ws, s->stream));
+    QSV_HIP(s, hipMemcpyAsync(out, s->d_ws, s->dim() * sizeof(double), hipMemcpyDeviceToHost,
+                              s->stream));
+    return sync(s);
+}
+
+// Pauli sum over bit positions (shared by the ABI call and the adjoint).
+static qsv_status expectation_positions(qsv_sim *s, const void *psi, int nq, int nterms,
+                                        const uint64_t *x, const uint64_t *z, const double *c,
+                                        double *re_out, double *im_out) {
+    std::vector<int> order(nterms);
+    for (int t = 0; t < nterms; ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return x[a] < x[b]; });
+    std::vector<uint64_t> zs(nterms + 1);
+    std::vector<double> cs(nterms + 1);
+    std::vector<int32_t> ny(nterms + 1);
+    std::vector<qsv::dev::PauliGroup> groups;
+    for (int i = 0; i < nterms; ++i) {
+        const int t = order[i];
+        zs[i] = z[t];
+        cs[i] = c[t];
+        ny[i] = popc(x[t] & z[t]);
+        if (groups.empty() || groups.back().x != x[t]) groups.push_back({x[t], i, 0});
+        groups.back().count += 1;
+    }
+    int nchunks = 0;
+    for (auto &g : groups) nchunks += (g.count + 7) / 8;
+    const size_t meta = ((nterms + 1) * (8 + 8 + 4) + 255) & ~size_t(255);
+    const size_t need = qsv::dev::pauli_workspace_bytes(nq, nchunks, nterms) + meta + 4096;
+    QSV_TRY(ensure_ws(s, need));
+    unsigned char *w = (unsigned char *)s->d_ws;
+    uint64_t *dz = (uint64_t *)w;
+    double *dc = (double *)(w + 8 * (nterms + 1));
+    int32_t *dny = (int32_t *)(w + 16 * (nterms + 1));
+    std::vector<unsigned char> hostmeta(meta, 0);
+    std::memcpy(hostmeta.data(), zs.data(), 8 * (nterms + 1));
+    std::memcpy(hostmeta.data() + 8 * (nterms + 1), cs.data(), 8 * (nterms + 1));
+    std::memcpy(hostmeta.data() + 16 * (nterms + 1), ny.data(), 4 * (nterms + 1));
+    QSV_HIP(s, hipMemcpyAsync(w, hostmeta.data(), meta, hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(s, hipStreamSynchronize(s->stream));
+    double *ws = (double *)(w + meta);
+    QSV_HIP(s, qsv::dev::pauli_expectation(s->opt.dtype, psi, nq, (int)groups.size(), groups.data(),
+                                           dz, dc, dny, nterms, ws, s->ws_bytes - meta,
+                                           s->d_small, s->stream));
+    double h[2];
+    QSV_HIP(s, hipMemcpyAsync(h, s->d_small, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    QSV_TRY(sync(s));
+    s->stats.kernels += 2;
+    s->stats.alg_bytes += (double)nchunks * (double)(1ull << nq) * s->elem();
+    *re_out = h[0];
+    if (im_out) *im_out = h[1];
+    return QSV_OK;
+}
+
+qsv_status qsv_get_expectation(qsv_sim *s, int32_t nterms, const uint64_t *xmask,
+                               const uint64_t *zmask, const double *coeff, double *out) {
+    QSV_CHECK(s);
+    if (!out || nterms < 0 || (nterms > 0 && (!xmask || !zmask || !coeff)))
+        return fail(s, QSV_EINVAL, "bad argument");
+    std::vector<uint64_t> x(nterms), z(nterms);
+    for (int t = 0; t < nterms; ++t) {
+        uint64_t xm = 0, zm = 0;
+        for (int id = 0; id < 64; ++id) {
+            const bool bx = (xmask[t] >> id) & 1, bz = (zmask[t] >> id) & 1;
+            if (!bx && !bz) continue;
+            if (s->pos_of[id] < 0)
+                return fail(s, QSV_EINVAL, "Pauli term on unknown qubit id " + std::to_string(id));
+            if (bx) xm |= 1ull << s->pos_of[id];
+            if (bz) zm |= 1ull << s->pos_of[id];
+        }
+        x[t] = xm;
+        z[t] = zm;
+    }
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    double im = 0.0;
+    return expectation_positions(s, s->d_state, s->n, nterms, x.data(), z.data(), coeff, out, &im);
+}
+
+qsv_status qsv_measure(qsv_sim *s, int32_t m, const int32_t *qubits, const double *u,
+                       int8_t *bits_out) {
+    QSV_CHECK(s);
+    if (m < 0 || (m > 0 && (!qubits || !u || !bits_out))) return fail(s, QSV_EINVAL, "bad argument");
+    QSV_TRY(check_ids(s, m, qubits, nullptr));
+    for (int j = 0; j < m; ++j)
+        if (!(u[j] >= 0.0 && u[j] < 1.0)) return fail(s, QSV_EINVAL, "uniform outside [0,1)");
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    for (int j = 0; j < m; ++j) {
+        const int pos = s->pos_of[qubits[j]];
+        double p0, p1;
+        QSV_TRY(prob_split_host(s, pos, &p0, &p1));
+        const int outcome = (u[j] * (p0 + p1) < p0) ? 0 : 1;
+        const double keep = outcome ? p1 : p0;
+        if (!(keep > 0.0)) return fail(s, QSV_EDEVICE, "measured branch has zero probability");
+        QSV_HIP(s, qsv::dev::collapse(s->opt.dtype, s->d_state, s->n, pos, outcome,
+                                      1.0 / std::sqrt(keep), s->stream));
+        s->stats.kernels += 1;
+        s->stats.alg_bytes += 2.0 * s->dim() * s->elem();
+        bits_out[j] = (int8_t)outcome;
+    }
+    return sync(s);
+}
+
+qsv_status qsv_sample(qsv_sim *s, int32_t shots, const double *u, uint64_t *out) {
+    QSV_CHECK(s);
+    if (shots < 0 || (shots > 0 && (!u || !out))) return fail(s, QSV_EINVAL, "bad argument");
+    for (int j = 0; j < shots; ++j)
+        if (!(u[j] >= 0.0 && u[j] < 1.0)) return fail(s, QSV_EINVAL, "uniform outside [0,1)");
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    if (shots == 0) return QSV_OK;
+    const size_t wsb = qsv::dev::sample_workspace_bytes(s->n);
+    const size_t ub = ((size_t)shots * 8 + 255) & ~size_t(255);
+    QSV_TRY(ensure_ws(s, wsb + 2 * ub + 256));
+    unsigned char *w = (unsigned char *)s->d_ws;
+    double *du = (double *)w;
+    uint64_t *dout = (uint64_t *)(w + ub);
+    double *dws = (double *)(w + 2 * ub);
+    QSV_HIP(s, hipMemcpyAsync(du, u, shots * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(s, qsv::dev::sample(s->opt.dtype, s->d_state, s->n, shots, du, dws, dout, s->stream));
+    QSV_HIP(s, hipMemcpyAsync(out, dout, shots * sizeof(uint64_t), hipMemcpyDeviceToHost, s->stream));
+    s->stats.kernels += 3;
+    s->stats.alg_bytes += (double)s->dim() * s->elem();
+    return sync(s);
+}
+
+qsv_status qsv_get_state(qsv_sim *s, void *dst, int32_t dst_is_device) {
+    QSV_CHECK(s);
+    if (!dst) return fail(s, QSV_EINVAL, "NULL destination");
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    QSV_HIP(s, hipMemcpyAsync(dst, s->d_state, s->dim() * s->elem(),
+                              dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                              s->stream));
+    return sync(s);
+}
+
+qsv_status qsv_set_state(qsv_sim *s, const void *src, int32_t src_is_device) {
+    QSV_CHECK(s);
+    if (!src) return fail(s, QSV_EINVAL, "NULL source");
+    s->queue.clear();
+    QSV_TRY(ensure_capacity(s, s->n));
+    if (!s->d_small) QSV_HIP(s, hipMalloc((void **)&s->d_small, 64 * sizeof(double)));
+    QSV_HIP(s, hipMemcpyAsync(s->d_state, src, s->dim() * s->elem(),
+                              src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              s->stream));
+    s->materialized = true;
+    return sync(s);
+}
+
+qsv_status qsv_get_amplitudes(qsv_sim *s, int64_t count, const uint64_t *indices, double *out) {
+    QSV_CHECK(s);
+    if (count < 0 || (count > 0 && (!indices || !out))) return fail(s, QSV_EINVAL, "bad argument");
+    for (int64_t i = 0; i < count; ++i)
+        if (indices[i] >= (1ull << s->n)) return fail(s, QSV_EINVAL, "amplitude index out of range");
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    if (count == 0) return QSV_OK;
+    const size_t ib = ((size_t)count * 8 + 255) & ~size_t(255);
+    QSV_TRY(ensure_ws(s, ib + (size_t)count * 16));
+    uint64_t *di = (uint64_t *)s->d_ws;
+    double *dout = (double *)((unsigned char *)s->d_ws + ib);
+    QSV_HIP(s, hipMemcpyAsync(di, indices, count * 8, hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(s, qsv::dev::gather(s->opt.dtype, s->d_state, di, (uint64_t)count, dout, s->stream));
+    QSV_HIP(s, hipMemcpyAsync(out, dout, count * 16, hipMemcpyDeviceToHost, s->stream));
+    return sync(s);
+}
+
+qsv_status qsv_state_pointer(qsv_sim *s, void **ptr, void **stream) {
+    QSV_CHECK(s);
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    if (ptr) *ptr = s->d_state;
+    if (stream) *stream = (void *)s->stream;
+    return QSV_OK;
+}
+
+qsv_status qsv_get_stats(const qsv_sim *s, qsv_stats *out) {
+    if (!live(s)) return fail(nullptr, QSV_ESTATE, "invalid or destroyed handle");
+    if (!out) return QSV_EINVAL;
+    *out = s->stats;
+    return QSV_OK;
+}
+
+qsv_status qsv_reset_stats(qsv_sim *s) {
+    QSV_CHECK(s);
+    s->stats = qsv_stats{};
+    return QSV_OK;
+}
+
+qsv_status qsv_plan(qsv_sim *s, int32_t *n_ops, int32_t *n_passes, int32_t max_ops, int32_t *ks,
+                    int32_t *targets, uint64_t *ctrls, double *mats) {
+    QSV_CHECK(s);
+    if (max_ops > 0 && (!ks || !targets || !ctrls || !mats)) return fail(s, QSV_EINVAL, "NULL output");
+    std::vector<Op> ops = canonical_queue(s, nullptr);
+    std::vector<Op> flat;
+    int np = 0;
+    if (s->opt.mode == QSV_MODE_PERGATE) {
+        flat = ops;
+        np = (int)ops.size();
+    } else if (s->opt.mode == QSV_MODE_FUSED) {
+        flat = qsv::fuse(ops, s->opt.k_max);
+        np = (int)flat.size();
+    } else {
+        const int m = std::min(tile_bits_for(s), s->n);
+        std::vector<Pass> passes = qsv::plan_passes(ops, s->n, m, 4, s->opt.k_max);
+        np = (int)passes.size();
+        for (auto &p : passes)
+            for (auto &o : p.ops) flat.push_back(o);
+    }
+    if (n_ops) *n_ops = (int32_t)flat.size();
+    if (n_passes) *n_passes = np;
+    for (int i = 0; i < (int)flat.size() && i < max_ops; ++i) {
+        const Op &o = flat[i];
+        ks[i] = o.k;
+        for (int j = 0; j < 5; ++j) targets[5 * i + j] = j < o.k ? o.t[j] : -1;
+        ctrls[i] = o.ctrl;
+        std::vector<cd> U = qsv::dense_matrix(o);
+        for (size_t e = 0; e < U.size(); ++e) {
+            mats[(size_t)i * 2048 + 2 * e] = U[e].real();
+            mats[(size_t)i * 2048 + 2 * e + 1] = U[e].imag();
+        }
+    }
+    return QSV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal types shared by the planner, the C-ABI layer and the kernel
+// launchers of libqsv.  Not part of the public interface.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace qsv {
+
+using cd = std::complex<double>;
+
+constexpr int kMaxK = 5;          // widest dense operation (32 x 32)
+constexpr int kMaxQubits = 36;    // 2^36 c64 amplitudes = 512 GiB: beyond one GPU
+
+inline int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+// One gate as queued: U (2^k x 2^k, row-major, bit j of the index <-> t[j])
+// on bit positions t[0..k-1], applied where every bit of `ctrl` is 1.
+struct Gate {
+    int k = 0;
+    int t[kMaxK] = {0, 0, 0, 0, 0};
+    uint64_t ctrl = 0;
+    std::vector<cd> U;
+};
+
+// A canonical operation.  DENSE: U is the full matrix.  MONO: one nonzero per
+// row -- row r of the result takes val[r] * x[perm[r]]; rows outside `touch`
+// are unchanged (perm[r] == r and val[r] == 1).  A MONO op with perm == id is
+// diagonal.
+struct Op {
+    enum Kind { DENSE = 0, MONO = 1 };
+    int kind = DENSE;
+    int k = 0;
+    int t[kMaxK] = {0, 0, 0, 0, 0};
+    uint64_t ctrl = 0;
+    bool diag = false;
+    std::vector<cd> U;            // DENSE: 4^k entries; MONO: 2^k values
+    uint8_t perm[32] = {};
+    uint32_t touch = 0;
+    int n_orig = 1;               // original gates merged into this op
+
+    uint64_t targets() const {
+        uint64_t m = 0;
+        for (int j = 0; j < k; ++j) m |= 1ull << t[j];
+        return m;
+    }
+    uint64_t qubits() const { return targets() | ctrl; }
+    // Bit positions whose value the op may change.  Diagonal ops change none;
+    // on every other qubit the op acts diagonally (controls, phases).
+    uint64_t mixing() const { return diag ? 0 : targets(); }
+};
+
+// Diag-aware commutation test: two ops commute if on every shared qubit both
+// act diagonally (sufficient, not necessary).
+inline bool commute_masks(uint64_t mix_a, uint64_t all_a, uint64_t mix_b, uint64_t all_b) {
+    uint64_t shared = all_a & all_b;
+    return (shared & (mix_a | mix_b)) == 0;
+}
+inline bool commute(const Op &a, const Op &b) {
+    return commute_masks(a.mixing(), a.qubits(), b.mixing(), b.qubits());
+}
+
+// Reduce a gate to canonical form: controls hidden inside the matrix are
+// moved to `ctrl`, identity gates vanish (returns false), monomial matrices
+// become MONO ops.
+bool canonicalize(const Gate &g, Op &out);
+
+// Greedy commutation-aware fusion into ops of at most k_max qubits (targets
+// and controls together).  The fused matrices are products in complex128.
+std::vector<Op> fuse(const std::vector<Op> &ops, int k_max);
+
+// A pass over the state in LDS tiles: the 2^m amplitudes that share the
+// values of the bits outside `tile` are processed together by one workgroup.
+struct Pass {
+    uint64_t tile = 0;            // bit positions inside a tile
+    std::vector<Op> ops;
+};
+
+// Group ops into passes whose mixing qubits fit in m tile bits, the lowest
+// `low_bits` positions always included (contiguous HBM runs).  Ops are moved
+// across each other only when they commute.  Then each pass is fused to
+// k_max (only ops with all their qubits inside the tile are fused).
+std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_bits,
+                              int k_max);
+
+// Dense 2^k x 2^k matrix of an op on its own target list (controls excluded).
+std::vector<cd> dense_matrix(const Op &op);
+
+}  // namespace qsv

@@ -1,0 +1,366 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: complex128 amplitudes within 1e-12 of the oracle (max abs); complex64
+states within 1e-5 normwise relative error; reductions accumulated in double;
+samples identical except at a CDF boundary closer than 1e-10 * total, where
+both answers are correct.  At the 30-qubit sizes of the benchmark, where the
+oracle cannot run the whole circuit, the checks are sampled amplitudes
+against a closed form (QFT of a basis state) and the U^dag U = 1 property.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+Q = None
+
+
+def setup_module(module):
+    global Q
+    from paper_1612_08091_amd import qsv
+    Q = qsv
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make(n, **kw):
+    kw.setdefault("use_torch_stream", False)
+    s = Q.Simulator(n_max=kw.pop("n_max", max(n, 1)), **kw)
+    s.allocate(n)
+    return s
+
+
+def check_c128(got, want, tol=1e-12):
+    err = float(np.max(np.abs(got - want)))
+    assert err <= tol, "max |diff| = %g" % err
+
+
+def check_c64(got, want, tol=1e-5):
+    rel = float(np.linalg.norm(got.astype(np.complex128) - want) / np.linalg.norm(want))
+    assert rel <= tol, "normwise relative error %g" % rel
+
+
+def check_samples(got, want, psi, u):
+    p = np.abs(psi.astype(np.complex128)) ** 2
+    cdf = np.cumsum(p)
+    total = cdf[-1]
+    bad = np.nonzero(got != want)[0]
+    for s in bad:
+        i = int(min(got[s], want[s]))
+        r = u[s] * total
+        assert abs(r - cdf[i]) <= 1e-10 * total, "shot %d: %d vs %d" % (s, got[s], want[s])
+    assert len(bad) <= max(2, len(u) // 1000)
+
+
+def random_circuit(rng, n, count, kmax=3):
+    c = W.Circuit(n)
+    for _ in range(count):
+        kind = rng.integers(0, 7)
+        if kind == 0:
+            k = int(rng.integers(1, min(kmax, n) + 1))
+            qs = rng.permutation(n)[:k].tolist()
+            c.add(W.haar_unitary(1 << k, rng), qs)
+        elif kind == 1:
+            a, b = rng.permutation(n)[:2].tolist()
+            c.add(W.X, (b,), (a,))
+        elif kind == 2:
+            a, b = rng.permutation(n)[:2].tolist()
+            c.add(W.phase(float(rng.uniform(0, 6))), (b,), (a,))
+        elif kind == 3:
+            a, b = rng.permutation(n)[:2].tolist()
+            c.add(W.SWAP, (a, b))
+        elif kind == 4 and n >= 3:
+            qs = rng.permutation(n)[:3].tolist()
+            c.add(W.haar_2x2(rng), qs[:1], qs[1:])
+        elif kind == 5:
+            c.add(W.haar_2x2(rng), (int(rng.integers(0, min(n, 3))),))   # low targets
+        else:
+            q = int(rng.integers(0, n))
+            c.add(W.rz(float(rng.uniform(0, 6))), (q,))
+    return c
+
+
+MODES = [("pergate", 1, 0), ("fused", 2, 0), ("fused", 3, 0), ("fused", 4, 0), ("fused", 5, 0),
+         ("tiled", 1, 0), ("tiled", 2, 0), ("tiled", 3, 0), ("tiled", 4, 0), ("tiled", 5, 0),
+         ("tiled", 3, 6), ("tiled", 5, 10)]
+
+
+@pytest.mark.parametrize("mode,k_max,tile_bits", MODES)
+@pytest.mark.parametrize("n", [3, 9, 14, 18])
+def test_random_circuits_c128(mode, k_max, tile_bits, n):
+    rng = np.random.default_rng(1000 * n + 10 * k_max + tile_bits)
+    circ = random_circuit(rng, n, 80 if n < 18 else 40)
+    log("case", mode, k_max, tile_bits, n)
+    s = make(n, mode=mode, k_max=k_max, tile_bits=tile_bits)
+    s.run(circ)
+    got = s.get_state()
+    want = oracle.run(circ)
+    check_c128(got, want)
+    s.close()
+
+
+@pytest.mark.parametrize("mode,k_max", [("pergate", 1), ("fused", 3), ("fused", 5), ("tiled", 3),
+                                        ("tiled", 5)])
+def test_random_circuits_c64(mode, k_max):
+    n = 16
+    rng = np.random.default_rng(77 + k_max)
+    circ = random_circuit(rng, n, 80)
+    log("case c64", mode, k_max)
+    s = make(n, mode=mode, k_max=k_max, dtype="c64")
+    s.run(circ)
+    got = s.get_state()
+    check_c64(got, oracle.run(circ))
+    s.close()
+
+
+def test_config0_state_probs_samples():
+    circ, u = W.config0()
+    log("case config0")
+    s = make(16, mode="pergate")
+    s.run(circ)
+    got = s.get_state()
+    want = oracle.run(circ)
+    check_c128(got, want)
+    pg = s.get_probabilities()
+    assert np.max(np.abs(pg - oracle.probs(want))) <= 1e-13
+    smp = s.sample(u)
+    check_samples(smp, oracle.sample(want, u), want, u)
+    s.close()
+
+
+@pytest.mark.parametrize("mode", ["tiled", "fused"])
+def test_config0_other_modes(mode):
+    circ, u = W.config0()
+    s = make(16, mode=mode, k_max=4)
+    s.run(circ)
+    got = s.get_state()
+    want = oracle.run(circ)
+    check_c128(got, want)
+    check_samples(s.sample(u), oracle.sample(want, u), want, u)
+    s.close()
+
+
+def test_sampling_large_and_edges():
+    rng = np.random.default_rng(5)
+    n = 20
+    circ = random_circuit(rng, n, 30)
+    s = make(n)
+    s.run(circ)
+    want = oracle.run(circ)
+    u = rng.random(3000)
+    u[:3] = [0.0, 0.5, np.nextafter(1.0, 0)]
+    check_samples(s.sample(u), oracle.sample(want, u), want, u)
+    s.close()
+    # sparse state: u close to 1 lands on the last nonzero amplitude
+    s = make(12)
+    st = np.zeros(1 << 12, dtype=np.complex128)
+    st[[3, 700, 2049]] = [0.6, 0.0 + 0.64j, 0.48]
+    st /= np.linalg.norm(st)
+    s.set_state(st)
+    uu = np.array([0.0, 0.3, 0.5, 0.99, np.nextafter(1.0, 0)])
+    check_samples(s.sample(uu), oracle.sample(st, uu), st, uu)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_expectation(dtype):
+    rng = np.random.default_rng(11)
+    for n, ham in [(10, W.random_pauli_dense(10, 64, rng)), (16, W.random_pauli_local(16, 200, 4, rng)),
+                   (1, W.random_pauli_dense(1, 4, rng))]:
+        circ = random_circuit(rng, n, 40)
+        s = make(n, dtype=dtype)
+        s.run(circ)
+        got = s.expectation(ham)
+        want, wim = oracle.expectation(oracle.run(circ), ham)
+        tol = 1e-12 * max(1.0, np.sum(np.abs(ham.coeff))) if dtype == "c128" else \
+            1e-5 * np.sum(np.abs(ham.coeff))
+        assert abs(got - want) <= tol, (n, got, want)
+        s.close()
+
+
+def test_probability_masks():
+    rng = np.random.default_rng(12)
+    n = 14
+    circ = random_circuit(rng, n, 50)
+    s = make(n)
+    s.run(circ)
+    psi = oracle.run(circ)
+    for qs, bs in [([], []), ([0], [1]), ([13], [0]), ([2, 9], [1, 0]), ([0, 1, 2, 3, 4], [1, 0, 1, 1, 0])]:
+        got = s.get_probability(qs, bs)
+        assert abs(got - oracle.prob_bits(psi, qs, bs)) <= 1e-13
+    s.close()
+
+
+def test_measure_collapse_matches_oracle():
+    rng = np.random.default_rng(13)
+    n = 12
+    circ = random_circuit(rng, n, 50)
+    s = make(n)
+    s.run(circ)
+    psi = oracle.run(circ)
+    qs = [3, 0, 11, 7]
+    u = rng.random(len(qs)).tolist()
+    got_bits = s.measure(qs, u)
+    want_bits = [oracle.measure(psi, q, x)[0] for q, x in zip(qs, u)]
+    assert got_bits == want_bits
+    check_c128(s.get_state(), psi)
+    # measuring again repeats the outcome
+    assert s.measure(qs, [0.999, 0.0, 0.5, 0.25]) == want_bits
+    s.close()
+
+
+@pytest.mark.parametrize("branch", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_teleportation(branch):
+    # App. A.1 on the GPU path: Bob's qubit ends in the created state.
+    u_create = W.haar_2x2(np.random.default_rng(99))
+    s = make(3, mode="pergate")
+    b1, b2, psi = 0, 1, 2
+    s.apply(W.H, [b1])
+    s.apply(W.X, [b2], [b1])
+    s.apply(u_create, [psi])
+    s.apply(W.X, [b1], [psi])
+    s.apply(W.H, [psi])
+    upsi = 0.0 if branch[0] == 0 else np.nextafter(1.0, 0)
+    ub1 = 0.0 if branch[1] == 0 else np.nextafter(1.0, 0)
+    m = s.measure([psi, b1], [upsi, ub1])
+    assert m == list(branch)
+    if m[1]:
+        s.apply(W.X, [b2], [b1])
+    if m[0]:
+        s.apply(W.Z, [b2], [psi])
+    st = s.get_state()
+    base = m[1] * 1 + m[0] * 4
+    bob = np.array([st[base], st[base + 2]])
+    check_c128(bob, u_create @ np.array([1, 0]), 1e-14)
+    s.close()
+
+
+def test_allocate_deallocate_sequence():
+    rng = np.random.default_rng(14)
+    s = Q.Simulator(n_max=12, use_torch_stream=False)
+    ids = s.allocate(6)
+    ref = oracle.zero_state(6)
+    circ = random_circuit(rng, 6, 30)
+    s.run(circ)
+    oracle.run(circ, ref)
+    # put qubit 2 into |1> with an X after uncomputing nothing: a classical qubit
+    s.apply(W.X, [ids[2]])
+    oracle.apply(ref, W.X, [2])
+    with pytest.raises(Q.NotClassicalError):
+        s.deallocate(ids[4])          # entangled: must raise, state unchanged
+    check_c128(s.get_state(), ref)
+    # prepare a classical qubit: allocate, flip, deallocate
+    new = s.allocate(2)
+    ref = oracle.allocate(ref, 2)
+    s.apply(W.X, [new[0]])
+    oracle.apply(ref, W.X, [6])
+    s.deallocate(new[0])
+    v, ref = oracle.dealloc(ref, 6, 1e-12)
+    assert v == 1
+    check_c128(s.get_state(), ref)
+    s.deallocate(new[1])
+    v, ref = oracle.dealloc(ref, 6, 1e-12)
+    assert v == 0
+    check_c128(s.get_state(), ref)
+    s.close()
+
+
+@pytest.mark.parametrize("n", [5, 20])
+def test_ghz_w_grover_closed_forms(n):
+    s = make(n, mode="tiled")
+    s.run(W.ghz(n))
+    st = s.get_state()
+    want = np.zeros(1 << n, dtype=np.complex128)
+    want[0] = want[-1] = 1 / math.sqrt(2)
+    check_c128(st, want, 1e-14)
+    s.close()
+    s = make(n, mode="fused", k_max=3)
+    s.run(W.w_state(n))
+    st = s.get_state()
+    want = np.zeros(1 << n, dtype=np.complex128)
+    for q in range(n):
+        want[1 << q] = 1 / math.sqrt(n)
+    check_c128(st, want, 1e-13)
+    s.close()
+    g = min(n, 9)
+    marked = sum(1 << q for q in range(0, g, 2))
+    s = make(g + 1, mode="tiled", k_max=2)
+    j = int(math.floor(math.pi * math.sqrt(2 ** g) / 4))
+    s.run(W.grover(g, marked, j))
+    p = s.get_probability(list(range(g)), [(marked >> q) & 1 for q in range(g)])
+    assert abs(p - math.sin((2 * j + 1) * math.asin(2 ** (-g / 2))) ** 2) <= 1e-12
+    s.close()
+
+
+def test_borrowed_torch_state():
+    import torch
+    n = 12
+    buf = torch.empty(2 << n, dtype=torch.float64, device="cuda")
+    s = Q.Simulator(n_max=n, state=buf)
+    s.allocate(n)
+    circ = random_circuit(np.random.default_rng(15), n, 40)
+    s.run(circ)
+    s.flush()
+    s.synchronize()
+    torch.cuda.synchronize()
+    got = buf.cpu().numpy().view(np.complex128)
+    check_c128(got, oracle.run(circ))
+    s.close()
+
+
+def test_config2_twin_c64_vs_oracle():
+    n = 20
+    circ = W.config2(n=n)
+    want = oracle.run(circ)
+    for mode, k in [("fused", 5), ("tiled", 5), ("tiled", 3)]:
+        log("case config2 twin", mode, k)
+        s = make(n, mode=mode, k_max=k, dtype="c64")
+        s.run(circ)
+        check_c64(s.get_state(), want)
+        s.close()
+
+
+# ------------------------------------------------------------- full size, 30 q
+def test_qft_30q_sampled_closed_form():
+    n = 30
+    x, circ = W.config1_qft(n)
+    log("case qft30 x=%d" % x)
+    s = make(n, mode="tiled", k_max=4)
+    s.run(W.basis_prep(n, x))
+    s.run(circ)
+    rng = np.random.default_rng(21)
+    idx = rng.integers(0, 1 << n, size=4096, dtype=np.uint64)
+    idx[:4] = [0, 1, (1 << n) - 1, 1 << (n - 1)]
+    got = s.get_amplitudes(idx)
+    y = idx.astype(object)
+    ph = np.array([float((x * int(v)) % (1 << n)) for v in y]) / (1 << n)
+    want = np.exp(2j * math.pi * ph) / (2 ** (n / 2))
+    check_c128(got, want, 1e-12)
+    assert abs(s.norm2() - 1.0) <= 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("mode,k_max", [("tiled", 3), ("pergate", 1)])
+def test_brick_30q_then_inverse(mode, k_max):
+    n = 30
+    circ = W.config1_random(n)
+    if mode == "pergate":
+        circ.gates = circ.gates[:200]
+    log("case brick30 inverse", mode, len(circ.gates))
+    s = make(n, mode=mode, k_max=k_max)
+    s.run(circ)
+    assert abs(s.norm2() - 1.0) <= 1e-11
+    for g in reversed(circ.gates):
+        s.apply(g.matrix.conj().T, g.targets, g.controls)
+    amp = s.get_amplitudes([0, 1, 12345])
+    assert abs(amp[0] - 1.0) <= 1e-10 and np.max(np.abs(amp[1:])) <= 1e-10
+    s.close()
