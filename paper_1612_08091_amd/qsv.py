@@ -113,6 +113,14 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libqsv.so is not built (run __graft_entry__.build() or "
                           "python paper_1612_08091_amd/build.py); there is no fallback path")
+    # libqsv needs libamdhip64.so.7, the soname torch's bundled HIP runtime
+    # also carries.  Loading torch first makes the dynamic loader bind libqsv
+    # to that same runtime, so the process holds one HIP runtime and torch's
+    # streams and buffers can be handed to the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

@@ -64,7 +64,7 @@ def check_samples(got, want, psi, u):
 def random_circuit(rng, n, count, kmax=3):
     c = W.Circuit(n)
     for _ in range(count):
-        kind = rng.integers(0, 7)
+        kind = rng.integers(0, 7) if n >= 2 else rng.choice([0, 5, 6])
         if kind == 0:
             k = int(rng.integers(1, min(kmax, n) + 1))
             qs = rng.permutation(n)[:k].tolist()
