@@ -1,0 +1,239 @@
+"""Benchmark of the state-vector hot path on one MI355X.
+
+Workload: the 30-qubit random circuit -- 40 layers of a Haar-random 2x2 gate
+on every qubit then CNOTs on alternating neighbour pairs (1200 + 580 gates),
+complex128, from |0...0>.  One step = reset the state, queue the 1780 gates,
+flush (fusion + LDS-tile passes), then the reductions: the squared norm, an
+8-term Pauli-sum expectation value and 1000 samples.  Inputs are seeded and
+synthetic; the state is resident in HBM for the whole run.
+
+value = original gates x 2^30 amplitudes x steps / wall time of the timed
+steps (amplitude-gate updates per second).  Also reported: the algorithmic
+HBM bytes per step over its time (fraction of the 8 TB/s peak), the roofline
+of the dominant kernel (the LDS-tile pass) from HIP events recorded by the
+library around every launch, a complex64 (FP32) leg of the same circuit, a
+per-gate FP64 leg, and the CPU oracle timed on a bounded sample.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+FP64_PEAK = 78.6e12        # MI355X FP64 (vector and matrix), flop/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def step_hamiltonian(n: int):
+    """4 Z-strings (one shared pass) + 4 terms with X/Y letters."""
+    import workloads as W
+    s = []
+    for t in range(4):
+        z = ["I"] * n
+        for q in (t, 7 + t, 15 + t, 29 - t):
+            z[q] = "Z"
+        s.append("".join(z))
+    for t in range(4):
+        p = ["I"] * n
+        p[2 * t] = "X"
+        p[2 * t + 11] = "Y"
+        p[27 - t] = "Z"
+        s.append("".join(p))
+    rng = np.random.default_rng(W.SEED_BASE + 1)
+    return W.PauliSum.from_strings(s, rng.standard_normal(len(s)))
+
+
+def run_leg(circ, ham, u, steps, warmup, dtype, mode, k_max, tile_bits, timing=True, reduce=True,
+            reg_bits=0):
+    import torch
+    from paper_1612_08091_amd import qsv as Q
+    n = circ.n
+    sim = Q.Simulator(n_max=n, dtype=dtype, mode=mode, k_max=k_max, tile_bits=tile_bits,
+                      timing=timing, reg_bits=reg_bits)
+    sim.allocate(n)
+    gates = [(np.ascontiguousarray(g.matrix), list(g.targets), list(g.controls))
+             for g in circ.gates]
+    out = {}
+
+    def one_step():
+        sim.reset()
+        for m, t, c in gates:
+            sim.apply(m, t, c)
+        sim.flush()
+        if reduce:
+            out["norm2"] = sim.norm2()
+            out["energy"] = sim.expectation(ham)
+            out["samples"] = sim.sample(u)
+
+    for w in range(warmup):
+        one_step()
+        sim.synchronize()
+        log("  warmup step %d done" % w)
+    torch.cuda.synchronize()
+    sim.synchronize()
+    sim.reset_stats()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        one_step()
+        log("  step %d queued/done" % k)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = sim.stats()
+    kt = sim.kernel_times() if timing else {}
+    sim.close()
+    wall = t1 - t0
+    return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "stats": st, "ktimes": kt,
+            "norm2": out.get("norm2"), "energy": out.get("energy"),
+            "updates_per_step": len(circ.gates) * float(1 << n)}
+
+
+def cpu_baseline(circ, budget_s=15.0):
+    """The oracle applying the first gates of the same 30-qubit circuit, one
+    at a time, until about budget_s seconds of work (single thread)."""
+    import oracle
+    n = circ.n
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1.0
+    done = 0
+    t0 = time.perf_counter()
+    for g in circ.gates:
+        oracle.apply(psi, g.matrix, g.targets, g.controls)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    t = time.perf_counter() - t0
+    del psi
+    return {"value": done * float(1 << n) / t, "unit": "amp*gate/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d gates of the %d-qubit circuit, complex128, one thread "
+                      "(%.1f s)" % (done, len(circ.gates), n, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--qubits", type=int, default=30)
+    ap.add_argument("--mode", default="tiled")
+    ap.add_argument("--k-max", type=int, default=2)
+    ap.add_argument("--reg-bits", type=int, default=0)
+    ap.add_argument("--tile-bits", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-legs", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the state-vector path here runs on a single MI355X; "
+              "a sharded multi-GPU state is not built (run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    n = args.qubits
+    circ = W.config1_random(n=n)
+    ham = step_hamiltonian(n)
+    u = W.streams(1)[3].random(1000)
+    log("bench: %d qubits, %d gates, mode=%s k_max=%d" % (n, len(circ.gates), args.mode, args.k_max))
+
+    main_leg = run_leg(circ, ham, u, args.steps, args.warmup, "c128", args.mode, args.k_max,
+                       args.tile_bits, reg_bits=args.reg_bits)
+    log("main leg: %.2f ms/step" % main_leg["ms_per_step"])
+    steps = args.steps
+    value = main_leg["updates_per_step"] * steps / main_leg["wall_s"]
+    st = main_leg["stats"]
+    alg_bytes_step = st["alg_bytes"] / steps
+    pct_hbm = alg_bytes_step / (main_leg["ms_per_step"] * 1e-3) / HBM_PEAK
+
+    kt = main_leg["ktimes"]
+    dom = "tile" if kt.get("tile", (0, 0, 0))[1] > 0 else "dense"
+    ms, launches, kbytes = kt[dom]
+    per_launch_bytes = kbytes / max(launches, 1)
+    avg_ms = ms / max(launches, 1)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "traffic": None,
+                "kernel": "k_tile<double>" if dom == "tile" else "k_dense<double,1>",
+                "launches": launches, "avg_ms": avg_ms, "alg_bytes_per_launch": per_launch_bytes}
+
+    extra = {}
+    if not args.no_extra_legs:
+        leg32 = run_leg(circ, ham, u, steps, 1, "c64", args.mode, args.k_max, 0)
+        ms32, l32, b32 = leg32["ktimes"]["tile"]
+        extra["fp32_fused"] = {
+            "value": leg32["updates_per_step"] * steps / leg32["wall_s"],
+            "ms_per_step": leg32["ms_per_step"],
+            "pct_hbm_peak": leg32["stats"]["alg_bytes"] / steps / (leg32["ms_per_step"] * 1e-3)
+            / HBM_PEAK,
+            "tile_kernel_GBps": (b32 / max(l32, 1)) / (ms32 / max(l32, 1) * 1e-3) / 1e9 if ms32 else None,
+            "energy_abs_diff_vs_fp64": abs(leg32["energy"] - main_leg["energy"]),
+        }
+        log("fp32 leg: %.2f ms/step" % leg32["ms_per_step"])
+        pg = run_leg(circ, ham, u, 1, 0, "c128", "pergate", 1, 0, reduce=False)
+        d_ms, d_l, d_b = pg["ktimes"]["dense"]
+        m_ms, m_l, m_b = pg["ktimes"]["mono"]
+        extra["fp64_pergate"] = {
+            "value": pg["updates_per_step"] / pg["wall_s"],
+            "ms_per_step": pg["ms_per_step"],
+            "dense_1q_GBps": d_b / (d_ms * 1e-3) / 1e9 if d_ms else None,
+            "cnot_GBps": m_b / (m_ms * 1e-3) / 1e9 if m_ms else None,
+            "pct_hbm_peak": pg["stats"]["alg_bytes"] / (pg["ms_per_step"] * 1e-3) / HBM_PEAK,
+        }
+        log("per-gate leg: %.2f ms/step" % pg["ms_per_step"])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        cpu = cpu_baseline(circ, args.cpu_budget)
+
+    line = {
+        "metric": "amplitude*gate updates/s + % HBM peak, 30q random circuit; fp64 vs fused fp32",
+        "value": value,
+        "unit": "amp*gate/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_leg["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%d-qubit random circuit, 40 layers of Haar 1q + CNOT brick "
+                               "(%d gates), complex128 from |0..0>, then norm, 8-term <H>, "
+                               "1000 samples" % (n, len(circ.gates)),
+                   "n_qubits": n, "gates": len(circ.gates), "mode": args.mode,
+                   "k_max": args.k_max, "tile_bits": args.tile_bits or 12,
+                   "reg_bits": args.reg_bits or 4},
+        "pct_hbm_peak": pct_hbm,
+        "alg_bytes_per_step": alg_bytes_step,
+        "hbm_passes_per_step": st["passes"] / steps,
+        "fused_ops_per_step": st["fused_ops"] / steps,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": extra,
+        "check": {"norm2": main_leg["norm2"], "energy": main_leg["energy"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

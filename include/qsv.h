@@ -76,7 +76,20 @@ typedef struct qsv_options {
     void *stream;           /* hipStream_t used for all device work; NULL = null stream */
     void *state;            /* optional borrowed device buffer for the state */
     uint64_t state_bytes;   /* its size in bytes (>= 2^n_max amplitudes) */
+    int32_t timing;         /* 1: bracket every kernel with HIP events (qsv_get_kernel_times) */
+    int32_t reg_bits;       /* amplitudes per thread = 2^reg_bits in the register-resident
+                               tile kernel (3..5; tile_bits - reg_bits thread bits must be
+                               8 or 9), 0 = default */
 } qsv_options;
+
+/* Kernel classes reported by qsv_get_kernel_times. */
+typedef enum qsv_kernel_class {
+    QSV_K_TILE = 0,         /* LDS-tile pass (one HBM read + write of the state) */
+    QSV_K_DENSE = 1,        /* per-gate dense update */
+    QSV_K_MONO = 2,         /* per-gate monomial (permutation / diagonal) update */
+    QSV_K_REDUCE = 3,       /* reductions, collapse, sampling */
+    QSV_K_COUNT = 4
+} qsv_kernel_class;
 
 typedef struct qsv_sim qsv_sim;
 
@@ -91,7 +104,7 @@ typedef struct qsv_stats {
     double amp_gate_updates;/* sum over original gates of 2^n */
 } qsv_stats;
 
-/* Fill *opt with defaults: n_max 30, C128, mode TILED, k_max 3, tile_bits 0. */
+/* Fill *opt with defaults: n_max 30, C128, mode TILED, k_max 2, tile_bits 0. */
 qsv_status qsv_options_default(qsv_options *opt);
 
 /* Create a simulator holding 0 qubits (state |>).  No device memory is
@@ -176,6 +189,16 @@ qsv_status qsv_get_amplitudes(qsv_sim *sim, int64_t count, const uint64_t *indic
  * wrap the buffer, e.g. as a torch tensor).  Flushes. */
 qsv_status qsv_state_pointer(qsv_sim *sim, void **ptr, void **stream);
 
+/* Reset the state to |0...0> on the live qubits and drop queued gates. */
+qsv_status qsv_reset(qsv_sim *sim);
+
+/* With qsv_options.timing = 1: total device time (ms, from HIP events
+ * recorded on the handle's stream around each launch), number of launches
+ * and algorithmic HBM bytes of the kernels of class `kclass` since the last
+ * qsv_reset_stats.  Synchronises. */
+qsv_status qsv_get_kernel_times(qsv_sim *sim, int32_t kclass, double *ms, uint64_t *launches,
+                                double *alg_bytes);
+
 qsv_status qsv_get_stats(const qsv_sim *sim, qsv_stats *out);
 qsv_status qsv_reset_stats(qsv_sim *sim);
 
@@ -253,7 +276,9 @@ qsv_status qsv_batch_create(int32_t count, const qsv_circuit *circuits,
                             const qsv_pauli_sum *hams, const qsv_batch_options *opt,
                             qsv_batch **out);
 qsv_status qsv_batch_run(qsv_batch *b, double *out_host);
-qsv_status qsv_batch_info(const qsv_batch *b, int32_t *tile_bits, int32_t *wg_size,
+/* Tile bits and fusion width in use (from the autotuner or the options) and
+ * the device time of the last run in ms. */
+qsv_status qsv_batch_info(const qsv_batch *b, int32_t *tile_bits, int32_t *k_fuse,
                           double *last_ms);
 qsv_status qsv_batch_destroy(qsv_batch *b);
 

@@ -22,8 +22,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]
+# -simplifycfg-sink-common=false: without it LLVM merges the per-register-bit
+# cases of the tile kernel into one dynamically indexed access, which moves
+# the register-resident amplitudes to scratch memory.
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-munsafe-fp-atomics", "-mllvm", "--simplifycfg-sink-common=false"]
 
 
 def sources():

@@ -58,6 +58,25 @@ struct TileArgs {
     int32_t tile_pos_n;   // == m
     uint8_t tpos[40];     // tile positions, ascending
     uint64_t n_tiles;
+    uint8_t reg_lbit[8];  // register kernel: initial layout, tile bit of register bit j
+    uint8_t thr_lbit[16]; //                  tile bit of thread-id bit i
+    int32_t rb;           // register bits per thread (threads = 2^(m - rb))
+    int32_t pad;
+};
+
+// One operation of the register-resident tile kernel.
+enum RegOpKind : int32_t { ROP_G1 = 0, ROP_G2 = 1, ROP_DIAG = 2, ROP_REMAP = 3, ROP_LDS = 4 };
+struct RegOp {
+    int32_t kind;
+    int32_t a;            // G1: register bit; G2: lower register bit (matrix bit 0);
+                          // DIAG: number of targets; LDS: index into the TileOp list
+    int32_t b;            // G2: higher register bit (matrix bit 1)
+    uint32_t pad0;
+    uint64_t ctrl;        // G1/G2/DIAG: control bits over the global index
+    int64_t mat;          // offset (complex entries of the tile dtype) into the pool
+    uint8_t gt[8];        // DIAG: global target positions
+    uint8_t reg_lbit[8];  // REMAP: new layout
+    uint8_t thr_lbit[16];
 };
 
 // ------------------------------------------------------------------ gates
@@ -68,7 +87,12 @@ hipError_t launch_mono(int dtype, void *psi, int k, uint64_t ngroups, const Inde
                        const MonoArgs &a, hipStream_t s);
 hipError_t launch_tile_pass(int dtype, void *psi, const TileArgs &ta, const TileOp *ops,
                             const void *pool, hipStream_t s);
+// Register-resident tile pass: ta.rb register bits in {3, 4, 5} and
+// ta.m - ta.rb thread bits in {8, 9}.
+hipError_t launch_tile_reg(int dtype, void *psi, const TileArgs &ta, const RegOp *rops,
+                           const void *pool, hipStream_t s);
 int tile_pass_max_bits(int dtype);
+int tile_reg_bits(int dtype);     // default register bits per thread
 
 // ------------------------------------------------------------ state ops
 hipError_t fill_basis0(int dtype, void *psi, uint64_t dim, hipStream_t s);
@@ -105,6 +129,65 @@ hipError_t pauli_expectation(int dtype, const void *psi, int nq, int ngroups,
                              const double *coef_dev, const int32_t *ny_dev, int nterms,
                              double *ws, size_t ws_bytes, double *out_dev, hipStream_t s);
 size_t pauli_workspace_bytes(int nq, int ngroups, int nterms);
+
+// ---------------------------------------------------------------- adjoint
+// phi = H psi for a Pauli sum over bit positions (device arrays).
+hipError_t ham_apply(int dtype, const void *psi, void *phi, uint64_t dim, int nterms,
+                     const uint64_t *x, const uint64_t *z, const double *c, const int32_t *ny,
+                     hipStream_t s);
+// out_dev[0] = Re<a|b>; ws holds adjoint_blocks(dim) doubles.
+hipError_t dot_re(int dtype, const void *a, const void *b, uint64_t dim, double *ws,
+                  double *out_dev, hipStream_t s);
+int adjoint_blocks(uint64_t npairs);
+// Reverse step for exp(-i theta P/2), P = X/Y/Z (axis 1/2/3), on the pairs
+// given by ia (target bit cleared, controls set) and partner offset toff;
+// c = cos(theta/2), sn = sin(theta/2).  partial[adjoint_blocks(npairs)].
+hipError_t adjoint_rotation(int dtype, void *psi, void *phi, uint64_t npairs,
+                            const IndexArgs &ia, uint64_t toff, int axis, double c, double sn,
+                            double *partial, hipStream_t s);
+hipError_t grad_finish(const double *partial, int ng, int nb, const int32_t *param, double *grad,
+                       int nparams, hipStream_t s);
+
+// ---------------------------------------------------------------- batched
+struct BatchCircuit {
+    int32_t n;            // qubits
+    int32_t pass_begin;   // first BatchPass
+    int32_t pass_count;
+    int32_t term_begin;   // first BatchTerm
+    int32_t term_count;
+    int32_t out_index;
+    int32_t pad[2];
+};
+struct BatchPass {
+    int32_t m;            // tile bits
+    int32_t op_begin;     // first TileOp
+    int32_t op_count;
+    int32_t pad;
+    uint8_t tpos[16];     // tile positions, ascending
+};
+struct BatchTerm {
+    uint64_t x, z;
+    double c;
+    int32_t ny;
+    int32_t pad;
+};
+struct BatchLaunch {
+    const BatchCircuit *circuits;
+    const int32_t *order;     // processing order (longest first)
+    int32_t count;
+    const BatchPass *passes;
+    const TileOp *ops;
+    const void *pool;         // matrices in the batch dtype
+    const BatchTerm *terms;
+    void *scratch;            // grid slots of slot_amps amplitudes
+    uint64_t slot_amps;
+    int32_t mb;               // LDS-resident limit and tile bits
+    unsigned int *counter;
+    double *out;
+    unsigned int grid;
+};
+hipError_t batch_launch(int dtype, const BatchLaunch &L, hipStream_t s);
+int batch_occupancy(int dtype, int mb);   // resident workgroups per CU
 
 // Sampling: out_dev[shots] indices.
 size_t sample_workspace_bytes(int nq);

@@ -1,0 +1,220 @@
+// Batched expectation values: many small circuits, each with its own Pauli
+// sum, evaluated by one persistent launch.  Every workgroup repeatedly takes
+// the next circuit from an atomic counter (circuits are ordered longest
+// first), simulates it alone and writes <H>.  A state of at most MB qubits
+// lives in LDS for its whole life; a larger one lives in a per-workgroup
+// slot of global memory and is updated by LDS-tile passes planned on the
+// host.  No workgroup ever waits for another, so the grid drains as soon as
+// the counter passes the number of circuits.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "lds_ops.hpp"
+
+namespace qsv {
+namespace dev {
+
+template <typename R>
+__device__ __forceinline__ double block_sum_b(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+    return r;
+}
+
+// sum_t c_t Re(i^{ny_t} sum_j conj(psi_{j^x}) psi_j (-1)^{popcount(j & z)}),
+// this thread's share, state `st` of 2^n amplitudes (LDS or global).
+template <typename R, bool SWZ>
+__device__ __forceinline__ double pauli_partial(const typename VT<R>::T *st, int n,
+                                                const BatchTerm *__restrict__ terms, int nt) {
+    double acc = 0.0;
+    const uint64_t dim = 1ull << n;
+    for (int t = 0; t < nt; ++t) {
+        const BatchTerm tm = terms[t];
+        double sr = 0.0, si = 0.0;
+        if (tm.x == 0) {
+            for (uint64_t j = threadIdx.x; j < dim; j += blockDim.x) {
+                const auto a = st[SWZ ? swz<R>((uint32_t)j) : j];
+                const double p = (double)a.x * a.x + (double)a.y * a.y;
+                sr += (__popcll(j & tm.z) & 1) ? -p : p;
+            }
+        } else {
+            const int h = 63 - __builtin_clzll(tm.x);
+            const uint64_t lowm = (1ull << h) - 1;
+            for (uint64_t g = threadIdx.x; g < (dim >> 1); g += blockDim.x) {
+                const uint64_t j = ((g & ~lowm) << 1) | (g & lowm);
+                const uint64_t j2 = j ^ tm.x;
+                const auto a = st[SWZ ? swz<R>((uint32_t)j) : j];
+                const auto b = st[SWZ ? swz<R>((uint32_t)j2) : j2];
+                const double u = (double)b.x * a.x + (double)b.y * a.y;
+                const double v = (double)b.x * a.y - (double)b.y * a.x;
+                const double s1 = (__popcll(j & tm.z) & 1) ? -1.0 : 1.0;
+                const double s2 = (__popcll(j2 & tm.z) & 1) ? -1.0 : 1.0;
+                sr += (s1 + s2) * u;
+                si += (s1 - s2) * v;
+            }
+        }
+        // Re(i^{ny} (sr + i si))
+        double re;
+        switch (tm.ny & 3) {
+        case 0: re = sr; break;
+        case 1: re = -si; break;
+        case 2: re = -sr; break;
+        default: re = si; break;
+        }
+        acc += tm.c * re;
+    }
+    return acc;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ circuits,
+                                               const int32_t *__restrict__ order, int count,
+                                               const BatchPass *__restrict__ passes,
+                                               const TileOp *__restrict__ ops,
+                                               const typename VT<R>::T *__restrict__ pool,
+                                               const BatchTerm *__restrict__ terms,
+                                               typename VT<R>::T *__restrict__ scratch,
+                                               uint64_t slot_amps, int mb,
+                                               unsigned int *counter, double *out) {
+    using T = typename VT<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    T *tile = reinterpret_cast<T *>(smem_raw);
+    __shared__ int s_next;
+    __shared__ double sh[16];
+    T *slot = scratch + (uint64_t)blockIdx.x * slot_amps;
+    const uint32_t tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_next = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int ci = s_next;
+        __syncthreads();
+        if (ci >= count) break;
+        const BatchCircuit bc = circuits[order[ci]];
+        const int n = bc.n;
+        double part;
+        if (n <= mb) {
+            // whole state in LDS: |0...0>, every op of the single pass, <H>
+            const uint32_t dim = 1u << n;
+            for (uint32_t l = tid; l < dim; l += kNT) {
+                T v;
+                v.x = (l == 0) ? R(1) : R(0);
+                v.y = R(0);
+                tile[swz<R>(l)] = v;
+            }
+            __syncthreads();
+            TileArgs ta;
+            ta.m = n;
+            for (int i = 0; i < n; ++i) ta.tpos[i] = (uint8_t)i;
+            for (int p = 0; p < bc.pass_count; ++p) {
+                const BatchPass bp = passes[bc.pass_begin + p];
+                for (int o = 0; o < bp.op_count; ++o) {
+                    lds_op<R>(tile, n, 0, ta, ops[bp.op_begin + o], pool);
+                    __syncthreads();
+                }
+            }
+            part = pauli_partial<R, true>(tile, n, terms + bc.term_begin, bc.term_count);
+        } else {
+            // state in this workgroup's global slot, updated by tile passes
+            for (int p = 0; p < bc.pass_count; ++p) {
+                const BatchPass bp = passes[bc.pass_begin + p];
+                const int m = bp.m;
+                TileArgs ta;
+                ta.m = m;
+                for (int i = 0; i < m; ++i) ta.tpos[i] = bp.tpos[i];
+                const uint32_t tsize = 1u << m;
+                const uint64_t ntiles = 1ull << (n - m);
+                for (uint64_t t = 0; t < ntiles; ++t) {
+                    uint64_t base = t;
+                    for (int i = 0; i < m; ++i) {
+                        const uint64_t lowm = (1ull << ta.tpos[i]) - 1;
+                        base = ((base & ~lowm) << 1) | (base & lowm);
+                    }
+                    for (uint32_t l = tid; l < tsize; l += kNT) {
+                        const uint64_t gi = base | deposit_bits(l, ta.tpos, m);
+                        T v;
+                        if (p == 0) {       // the first pass starts from |0...0>
+                            v.x = (gi == 0) ? R(1) : R(0);
+                            v.y = R(0);
+                        } else {
+                            v = slot[gi];
+                        }
+                        tile[swz<R>(l)] = v;
+                    }
+                    __syncthreads();
+                    for (int o = 0; o < bp.op_count; ++o) {
+                        lds_op<R>(tile, m, base, ta, ops[bp.op_begin + o], pool);
+                        __syncthreads();
+                    }
+                    for (uint32_t l = tid; l < tsize; l += kNT)
+                        slot[base | deposit_bits(l, ta.tpos, m)] = tile[swz<R>(l)];
+                    __syncthreads();
+                }
+            }
+            if (bc.pass_count == 0) {
+                const uint64_t dim = 1ull << n;
+                for (uint64_t j = tid; j < dim; j += kNT) {
+                    T v;
+                    v.x = (j == 0) ? R(1) : R(0);
+                    v.y = R(0);
+                    slot[j] = v;
+                }
+                __syncthreads();
+            }
+            part = pauli_partial<R, false>(slot, n, terms + bc.term_begin, bc.term_count);
+        }
+        const double tot = block_sum_b<R>(part, sh);
+        if (tid == 0) out[bc.out_index] = tot;
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset_counter(unsigned int *counter) { *counter = 0u; }
+
+template <typename R>
+static hipError_t batch_t(const BatchLaunch &L, hipStream_t s) {
+    using T = typename VT<R>::T;
+    const size_t lds = sizeof(T) << L.mb;
+    static size_t attr = 0;
+    if (attr < lds) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_batch<R>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = lds;
+    }
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, L.counter);
+    hipLaunchKernelGGL((k_batch<R>), dim3(L.grid), dim3(kNT), lds, s, L.circuits, L.order, L.count,
+                       L.passes, L.ops, (const T *)L.pool, L.terms, (T *)L.scratch, L.slot_amps,
+                       L.mb, L.counter, L.out);
+    return hipGetLastError();
+}
+
+hipError_t batch_launch(int dtype, const BatchLaunch &L, hipStream_t s) {
+    return dtype == 0 ? batch_t<double>(L, s) : batch_t<float>(L, s);
+}
+
+int batch_occupancy(int dtype, int mb) {
+    int blocks = 0;
+    hipError_t e;
+    if (dtype == 0) {
+        (void)hipFuncSetAttribute((const void *)k_batch<double>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(16u << mb));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<double>, kNT,
+                                                         (size_t)16 << mb);
+    } else {
+        (void)hipFuncSetAttribute((const void *)k_batch<float>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(8u << mb));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<float>, kNT,
+                                                         (size_t)8 << mb);
+    }
+    if (e != hipSuccess) return 0;
+    return blocks;
+}
+
+}  // namespace dev
+}  // namespace qsv

@@ -1,0 +1,354 @@
+// LDS-tile passes for gfx950.  One workgroup owns a tile: the 2^m amplitudes
+// whose indices agree outside the m tile bits.  The tile is read from HBM
+// once, every operation of the pass is applied to it on chip, and it is
+// written back once, so a pass costs one read and one write of the state
+// whatever the number of gates it holds (the lazily cached gates of Sec.
+// 4.3.2 executed in bulk).
+//
+// Two kernels:
+//  * k_tile_reg<R, RB>: m = RB + 8.  Each of the 256 threads keeps 2^RB
+//    amplitudes in registers.  Register bit j and thread bit i each stand for
+//    one tile bit (the layout).  1- and 2-qubit dense operations on register
+//    bits run in registers; diagonal operations on any bits use the global
+//    index of each amplitude; a REMAP op moves the tile through LDS (XOR
+//    swizzled against bank conflicts) into a new layout.  Passes holding
+//    wider operations use k_tile_lds.
+//  * k_tile_lds<R>: any m <= 14; the tile lives in LDS and every operation
+//    sweeps it (used for small states).
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "lds_ops.hpp"
+
+namespace qsv {
+namespace dev {
+
+// ------------------------------------------------------- k_tile_lds
+template <typename R>
+__global__ __launch_bounds__(kNT) void k_tile_lds(typename VT<R>::T *__restrict__ psi,
+                                                  TileArgs ta, const TileOp *__restrict__ ops,
+                                                  const typename VT<R>::T *__restrict__ pool) {
+    using T = typename VT<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    T *tile = reinterpret_cast<T *>(smem_raw);
+    const int m = ta.m;
+    const uint32_t tsize = 1u << m;
+    uint64_t base = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+    for (int i = 0; i < m; ++i) {
+        const uint64_t lowm = (1ull << ta.tpos[i]) - 1;
+        base = ((base & ~lowm) << 1) | (base & lowm);
+    }
+    const uint32_t tid = threadIdx.x;
+    const uint64_t dep_tid = deposit_bits(tid & (tsize - 1), ta.tpos, m);
+    for (uint32_t j = 0; j < tsize; j += kNT) {
+        const uint32_t l = j + tid;
+        if (l < tsize) tile[swz<R>(l)] = psi[base | dep_tid | deposit_bits(j, ta.tpos, m)];
+    }
+    __syncthreads();
+    for (int oi = 0; oi < ta.n_ops; ++oi) {
+        lds_op<R>(tile, m, base, ta, ops[oi], pool);
+        __syncthreads();
+    }
+    for (uint32_t j = 0; j < tsize; j += kNT) {
+        const uint32_t l = j + tid;
+        if (l < tsize) psi[base | dep_tid | deposit_bits(j, ta.tpos, m)] = tile[swz<R>(l)];
+    }
+}
+
+// ------------------------------------------------------- k_tile_reg
+template <typename T, int NR, int RB>
+__device__ __forceinline__ uint64_t greg(int i, const uint64_t *gbit) {
+    uint64_t g = 0;
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+        if ((i >> j) & 1) g |= gbit[j];
+    return g;
+}
+
+template <typename T, int NR, int RB, int J, bool CTRL>
+__device__ __forceinline__ void reg_g1(T *amp, const T *__restrict__ U, uint64_t gb,
+                                       const uint64_t *gbit, uint64_t ctrl) {
+    const T u00 = U[0], u01 = U[1], u10 = U[2], u11 = U[3];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i & (1 << J)) continue;
+        const int i1 = i | (1 << J);
+        const T a = amp[i], b = amp[i1];
+        T na = cmul(u00, a);
+        na = cmadd(na, u01, b);
+        T nb = cmul(u10, a);
+        nb = cmadd(nb, u11, b);
+        if (CTRL) {
+            const bool c = ((gb | greg<T, NR, RB>(i, gbit)) & ctrl) == ctrl;
+            amp[i] = csel(c, na, a);
+            amp[i1] = csel(c, nb, b);
+        } else {
+            amp[i] = na;
+            amp[i1] = nb;
+        }
+    }
+}
+
+template <typename T, int NR, int RB, int J1, int J2, bool CTRL>
+__device__ __forceinline__ void reg_g2(T *amp, const T *__restrict__ U, uint64_t gb,
+                                       const uint64_t *gbit, uint64_t ctrl) {
+    T u[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) u[e] = U[e];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i & ((1 << J1) | (1 << J2))) continue;
+        const int idx[4] = {i, i | (1 << J1), i | (1 << J2), i | (1 << J1) | (1 << J2)};
+        T x[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[c] = amp[idx[c]];
+        bool c = true;
+        if (CTRL) c = ((gb | greg<T, NR, RB>(i, gbit)) & ctrl) == ctrl;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            T y = cmul(u[r * 4], x[0]);
+#pragma unroll
+            for (int cc = 1; cc < 4; ++cc) y = cmadd(y, u[r * 4 + cc], x[cc]);
+            amp[idx[r]] = CTRL ? csel(c, y, x[r]) : y;
+        }
+    }
+}
+
+template <typename T, int NR, int RB>
+__device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const T *__restrict__ pool,
+                                         uint64_t gb, const uint64_t *gbit) {
+    const int k = op.a;
+    const uint64_t ctrl = op.ctrl;
+    const T *val = pool + op.mat;
+    if (k <= 2) {
+        const T v0 = val[0], v1 = val[1];
+        const T v2 = k == 2 ? val[2] : v0, v3 = k == 2 ? val[3] : v1;
+        const int t0 = op.gt[0], t1 = k == 2 ? op.gt[1] : op.gt[0];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const uint64_t g = gb | greg<T, NR, RB>(i, gbit);
+            const bool on = (g & ctrl) == ctrl;
+            const bool b0 = (g >> t0) & 1, b1 = (k == 2) && ((g >> t1) & 1);
+            const T v = b1 ? (b0 ? v3 : v2) : (b0 ? v1 : v0);
+            amp[i] = csel(on, cmul(v, amp[i]), amp[i]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const uint64_t g = gb | greg<T, NR, RB>(i, gbit);
+            if ((g & ctrl) != ctrl) continue;
+            uint32_t r = 0;
+            for (int q = 0; q < k; ++q) r |= (uint32_t)((g >> op.gt[q]) & 1u) << q;
+            amp[i] = cmul(val[r], amp[i]);
+        }
+    }
+}
+
+template <typename T, int NR, int RB, bool CTRL>
+__device__ __forceinline__ void dispatch_g1(T *amp, int j, const T *U, uint64_t gb,
+                                            const uint64_t *gbit, uint64_t ctrl) {
+    switch (j) {
+    case 0: reg_g1<T, NR, RB, 0, CTRL>(amp, U, gb, gbit, ctrl); break;
+    case 1: reg_g1<T, NR, RB, 1, CTRL>(amp, U, gb, gbit, ctrl); break;
+    case 2: reg_g1<T, NR, RB, 2, CTRL>(amp, U, gb, gbit, ctrl); break;
+    case 3:
+        if constexpr (RB > 3) reg_g1<T, NR, RB, 3, CTRL>(amp, U, gb, gbit, ctrl);
+        break;
+    case 4:
+        if constexpr (RB > 4) reg_g1<T, NR, RB, 4, CTRL>(amp, U, gb, gbit, ctrl);
+        break;
+    }
+}
+
+template <typename T, int NR, int RB, bool CTRL>
+__device__ __forceinline__ void dispatch_g2(T *amp, int a, int b, const T *U, uint64_t gb,
+                                            const uint64_t *gbit, uint64_t ctrl) {
+#define QSV_G2(A, B) \
+    case (A) * 8 + (B): reg_g2<T, NR, RB, A, B, CTRL>(amp, U, gb, gbit, ctrl); break;
+    switch (a * 8 + b) {
+        QSV_G2(0, 1) QSV_G2(0, 2) QSV_G2(1, 2)
+    default:
+        if constexpr (RB > 3) {
+            switch (a * 8 + b) { QSV_G2(0, 3) QSV_G2(1, 3) QSV_G2(2, 3) }
+        }
+        if constexpr (RB > 4) {
+            switch (a * 8 + b) { QSV_G2(0, 4) QSV_G2(1, 4) QSV_G2(2, 4) QSV_G2(3, 4) }
+        }
+        break;
+    }
+#undef QSV_G2
+}
+
+template <typename R, int RB, int TB>
+__global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restrict__ psi,
+                                                  TileArgs ta, const RegOp *__restrict__ ops,
+                                                  const typename VT<R>::T *__restrict__ pool) {
+    using T = typename VT<R>::T;
+    constexpr int NR = 1 << RB;
+    constexpr int m = RB + TB;
+    extern __shared__ unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    uint64_t base = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+#pragma unroll
+    for (int i = 0; i < m; ++i) {
+        const uint64_t lowm = (1ull << ta.tpos[i]) - 1;
+        base = ((base & ~lowm) << 1) | (base & lowm);
+    }
+    const uint32_t tid = threadIdx.x;
+    // current layout
+    uint32_t lbit[RB];
+    uint64_t gbit[RB];
+    uint32_t lthr = 0;
+    uint64_t gthr = 0;
+    {
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            lbit[j] = 1u << ta.reg_lbit[j];
+            gbit[j] = 1ull << ta.tpos[ta.reg_lbit[j]];
+        }
+#pragma unroll
+        for (int i = 0; i < TB; ++i)
+            if ((tid >> i) & 1) {
+                lthr |= 1u << ta.thr_lbit[i];
+                gthr |= 1ull << ta.tpos[ta.thr_lbit[i]];
+            }
+    }
+    T amp[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) amp[i] = psi[base | gthr | greg<T, NR, RB>(i, gbit)];
+
+    for (int oi = 0; oi < ta.n_ops; ++oi) {
+        // fields are read through a reference into the uniform op array so
+        // they stay scalar (a local copy would go to per-lane memory)
+        const RegOp &op = ops[oi];
+        const int kind = op.kind;
+        const uint64_t gb = base | gthr;
+        if (kind == ROP_G1) {
+            const T *U = pool + op.mat;
+            if (op.ctrl) dispatch_g1<T, NR, RB, true>(amp, op.a, U, gb, gbit, op.ctrl);
+            else dispatch_g1<T, NR, RB, false>(amp, op.a, U, gb, gbit, 0);
+        } else if (kind == ROP_G2) {
+            const T *U = pool + op.mat;
+            if (op.ctrl) dispatch_g2<T, NR, RB, true>(amp, op.a, op.b, U, gb, gbit, op.ctrl);
+            else dispatch_g2<T, NR, RB, false>(amp, op.a, op.b, U, gb, gbit, 0);
+        } else if (kind == ROP_DIAG) {
+            reg_diag<T, NR, RB>(amp, op, pool, gb, gbit);
+        } else {
+            // REMAP: the tile goes through LDS into the new layout
+            uint32_t lreg[NR];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                uint32_t l = 0;
+#pragma unroll
+                for (int j = 0; j < RB; ++j)
+                    if ((i >> j) & 1) l |= lbit[j];
+                lreg[i] = l;
+            }
+#pragma unroll
+            for (int i = 0; i < NR; ++i) lds[swz<R>(lthr | lreg[i])] = amp[i];
+            __syncthreads();
+            lthr = 0;
+            gthr = 0;
+#pragma unroll
+            for (int j = 0; j < RB; ++j) {
+                lbit[j] = 1u << op.reg_lbit[j];
+                gbit[j] = 1ull << ta.tpos[op.reg_lbit[j]];
+            }
+#pragma unroll
+            for (int i = 0; i < TB; ++i)
+                if ((tid >> i) & 1) {
+                    lthr |= 1u << op.thr_lbit[i];
+                    gthr |= 1ull << ta.tpos[op.thr_lbit[i]];
+                }
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                uint32_t l = 0;
+#pragma unroll
+                for (int j = 0; j < RB; ++j)
+                    if ((i >> j) & 1) l |= lbit[j];
+                amp[i] = lds[swz<R>(lthr | l)];
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) psi[base | gthr | greg<T, NR, RB>(i, gbit)] = amp[i];
+}
+
+int tile_pass_max_bits(int dtype) { return dtype == 0 ? 13 : 14; }
+int tile_reg_bits(int dtype) { return dtype == 0 ? 4 : 5; }
+
+template <typename K>
+static hipError_t set_lds_attr(K kern, size_t bytes) {
+    return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+static dim3 tile_grid(uint64_t nt) {
+    if (nt <= 0x7fffffffull) return dim3((unsigned)nt, 1, 1);
+    return dim3(1u << 30, (unsigned)(nt >> 30), 1);
+}
+
+template <typename R>
+static hipError_t launch_lds_t(void *psi, const TileArgs &ta, const TileOp *ops, const void *pool,
+                               hipStream_t s) {
+    using T = typename VT<R>::T;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = set_lds_attr(k_tile_lds<R>, sizeof(T) << tile_pass_max_bits(sizeof(R) == 8 ? 0 : 1));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (ta.n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_tile_lds<R>), tile_grid(ta.n_tiles), dim3(kNT), sizeof(T) << ta.m, s,
+                       (T *)psi, ta, ops, (const T *)pool);
+    return hipGetLastError();
+}
+
+template <typename R, int RB, int TB>
+static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
+                               const void *pool, hipStream_t s) {
+    using T = typename VT<R>::T;
+    static bool attr = false;
+    const size_t lds = sizeof(T) << (RB + TB);
+    if (!attr) {
+        hipError_t e = set_lds_attr(k_tile_reg<R, RB, TB>, lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (ta.n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_tile_reg<R, RB, TB>), tile_grid(ta.n_tiles), dim3(1 << TB), lds, s,
+                       (T *)psi, ta, rops, (const T *)pool);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_pass(int dtype, void *psi, const TileArgs &ta, const TileOp *ops,
+                            const void *pool, hipStream_t s) {
+    if (ta.m < 1 || ta.m > tile_pass_max_bits(dtype)) return hipErrorInvalidValue;
+    return dtype == 0 ? launch_lds_t<double>(psi, ta, ops, pool, s)
+                      : launch_lds_t<float>(psi, ta, ops, pool, s);
+}
+
+hipError_t launch_tile_reg(int dtype, void *psi, const TileArgs &ta, const RegOp *rops,
+                           const void *pool, hipStream_t s) {
+    const int rb = ta.rb, tb = ta.m - ta.rb;
+#define QSV_REG(R)                                                                   \
+    if (tb == 8) {                                                                   \
+        if (rb == 3) return launch_reg_t<R, 3, 8>(psi, ta, rops, pool, s);           \
+        if (rb == 4) return launch_reg_t<R, 4, 8>(psi, ta, rops, pool, s);           \
+        if (rb == 5) return launch_reg_t<R, 5, 8>(psi, ta, rops, pool, s);           \
+    } else if (tb == 9) {                                                            \
+        if (rb == 3) return launch_reg_t<R, 3, 9>(psi, ta, rops, pool, s);           \
+        if (rb == 4) return launch_reg_t<R, 4, 9>(psi, ta, rops, pool, s);           \
+    }
+    if (dtype == 0) {
+        QSV_REG(double)
+    } else {
+        QSV_REG(float)
+    }
+#undef QSV_REG
+    return hipErrorInvalidValue;
+}
+
+}  // namespace dev
+}  // namespace qsv

@@ -20,6 +20,7 @@
 #include "../../include/qsv.h"
 #include "device.hpp"
 #include "qsv_internal.hpp"
+#include "tileprog.hpp"
 
 using qsv::cd;
 using qsv::Gate;
@@ -40,6 +41,7 @@ struct qsv_sim {
     hipStream_t stream = nullptr;
     std::string err;
     qsv_stats stats{};
+    uint64_t stats_remaps = 0;
     // workspace for reductions
     void *d_ws = nullptr;
     size_t ws_bytes = 0;
@@ -53,6 +55,17 @@ struct qsv_sim {
         bool pending = false;
     } slot[2];
     int cur_slot = 0;
+    // kernel timing (opt.timing): events bracketing launches
+    struct EvRec {
+        hipEvent_t a, b;
+        int cls;
+        double bytes;
+    };
+    std::vector<EvRec> ev_pending;
+    std::vector<hipEvent_t> ev_pool;
+    double k_ms[QSV_K_COUNT] = {0, 0, 0, 0};
+    uint64_t k_launch[QSV_K_COUNT] = {0, 0, 0, 0};
+    double k_bytes[QSV_K_COUNT] = {0, 0, 0, 0};
     // adjoint / scratch vectors
     void *d_vec[3] = {nullptr, nullptr, nullptr};
     uint64_t vec_amps = 0;
@@ -185,6 +198,51 @@ qsv_status stage(qsv_sim *s, const void *data, size_t bytes, void **dptr) {
     return QSV_OK;
 }
 
+// ------------------------------------------------------------------ timing
+hipEvent_t pool_event(qsv_sim *s) {
+    if (!s->ev_pool.empty()) {
+        hipEvent_t e = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Record the start of a launch; returns an opaque token (or -1).
+int tbegin(qsv_sim *s) {
+    if (!s->opt.timing) return -1;
+    hipEvent_t a = pool_event(s), b = pool_event(s);
+    if (!a || !b) return -1;
+    if (hipEventRecord(a, s->stream) != hipSuccess) return -1;
+    s->ev_pending.push_back({a, b, 0, 0.0});
+    return (int)s->ev_pending.size() - 1;
+}
+
+void tend(qsv_sim *s, int tok, int cls, double bytes) {
+    if (tok < 0) return;
+    auto &r = s->ev_pending[tok];
+    r.cls = cls;
+    r.bytes = bytes;
+    (void)hipEventRecord(r.b, s->stream);
+}
+
+qsv_status collect_times(qsv_sim *s) {
+    for (auto &r : s->ev_pending) {
+        QSV_HIP(s, hipEventSynchronize(r.b));
+        float ms = 0.f;
+        QSV_HIP(s, hipEventElapsedTime(&ms, r.a, r.b));
+        s->k_ms[r.cls] += ms;
+        s->k_launch[r.cls] += 1;
+        s->k_bytes[r.cls] += r.bytes;
+        s->ev_pool.push_back(r.a);
+        s->ev_pool.push_back(r.b);
+    }
+    s->ev_pending.clear();
+    return QSV_OK;
+}
+
 // --------------------------------------------------------------- launching
 void index_args(uint64_t insert_mask, uint64_t ones, qsv::dev::IndexArgs &ia) {
     ia.npos = 0;
@@ -226,8 +284,10 @@ qsv_status launch_op(qsv_sim *s, const Op &op) {
             a.srcoff[r] = offset_of(op.perm[r], op.t, k);
         }
         a.touch = op.touch;
-        QSV_HIP(s, qsv::dev::launch_mono(s->opt.dtype, s->d_state, k, ngroups, ia, a, s->stream));
         const double touched = (double)popc(op.touch) * (double)ngroups;
+        const int tok = tbegin(s);
+        QSV_HIP(s, qsv::dev::launch_mono(s->opt.dtype, s->d_state, k, ngroups, ia, a, s->stream));
+        tend(s, tok, QSV_K_MONO, 2.0 * touched * s->elem());
         bool pure_perm = true;
         for (int r = 0; r < (1 << k); ++r)
             if (op.U[r] != cd(1, 0)) pure_perm = false;
@@ -242,7 +302,9 @@ qsv_status launch_op(qsv_sim *s, const Op &op) {
             a.mi[i] = op.U[i].imag();
         }
         for (int r = 0; r < D; ++r) a.off[r] = offset_of(r, op.t, k);
+        const int tok = tbegin(s);
         QSV_HIP(s, qsv::dev::launch_dense(s->opt.dtype, s->d_state, k, ngroups, ia, a, s->stream));
+        tend(s, tok, QSV_K_DENSE, 2.0 * (double)(ngroups << k) * s->elem());
         account(s, (double)(ngroups << k), 8.0 * D - 2.0);
         return QSV_OK;
     }
@@ -257,122 +319,89 @@ qsv_status launch_op(qsv_sim *s, const Op &op) {
     return run_tile_passes(s, one);
 }
 
-// Build the device descriptors of all passes, upload them with the matrices
-// in one copy, then launch one tile kernel per pass.
+// Lower every pass (register-resident kernel when the tile has RB + 8 bits,
+// LDS kernel otherwise), upload all descriptors and matrices in one copy,
+// then launch one tile kernel per pass.
 qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
+    using qsv::dev::RegOp;
     using qsv::dev::TileOp;
     const int nq = s->n;
-    std::vector<TileOp> tops;
-    std::vector<size_t> first(passes.size() + 1, 0);
-    std::vector<double> mats;     // complex entries as (re, im) doubles
+    const int rb = s->opt.reg_bits > 0 ? s->opt.reg_bits
+                                       : (s->opt.tile_bits >= 11 && s->opt.tile_bits <= 13)
+                                             ? s->opt.tile_bits - 8
+                                             : qsv::dev::tile_reg_bits(s->opt.dtype);
+    std::vector<double> mats;
+    std::vector<qsv::TileProgram> progs(passes.size());
+    size_t n_rops = 0, n_lops = 0;
     for (size_t pi = 0; pi < passes.size(); ++pi) {
-        const Pass &ps = passes[pi];
-        first[pi] = tops.size();
-        int li[64];
-        int m = 0;
-        for (int p = 0; p < 64; ++p) {
-            li[p] = -1;
-            if ((ps.tile >> p) & 1) li[p] = m++;
-        }
-        for (const Op &op : ps.ops) {
-            if (op.kind == Op::MONO && op.touch == 0) continue;
-            TileOp t{};
-            t.k = op.k;
-            t.touch = op.touch;
-            t.mat = (int64_t)(mats.size() / 2);
-            const bool inside = (op.targets() & ~ps.tile) == 0;
-            if (op.kind == Op::MONO && op.diag && !inside) {
-                t.kind = qsv::dev::TOP_DIAG_GLOBAL;
-                for (int j = 0; j < op.k; ++j) t.gt[j] = (uint8_t)op.t[j];
-                t.gctrl = op.ctrl;
-                t.ectrl = 0;
-                for (int r = 0; r < (1 << op.k); ++r) {
-                    mats.push_back(op.U[r].real());
-                    mats.push_back(op.U[r].imag());
-                }
-            } else {
-                if (!inside) return fail(s, QSV_EDEVICE, "internal: mixing target outside tile");
-                t.kind = op.kind == Op::MONO ? qsv::dev::TOP_MONO : qsv::dev::TOP_DENSE;
-                uint32_t lctrl = 0;
-                uint64_t ectrl = 0;
-                for (int p = 0; p < 64; ++p)
-                    if ((op.ctrl >> p) & 1) {
-                        if (li[p] >= 0) lctrl |= 1u << li[p];
-                        else ectrl |= 1ull << p;
-                    }
-                t.lctrl = lctrl;
-                t.ectrl = ectrl;
-                uint32_t ins = lctrl;
-                int lt[qsv::kMaxK];
-                for (int j = 0; j < op.k; ++j) {
-                    lt[j] = li[op.t[j]];
-                    ins |= 1u << lt[j];
-                }
-                t.npos = 0;
-                for (int b = 0; b < 32; ++b)
-                    if ((ins >> b) & 1) t.pos[t.npos++] = (uint8_t)b;
-                for (int r = 0; r < (1 << op.k); ++r) {
-                    uint32_t o = 0;
-                    for (int j = 0; j < op.k; ++j)
-                        if ((r >> j) & 1) o |= 1u << lt[j];
-                    t.loff[r] = o;
-                }
-                if (op.kind == Op::MONO) {
-                    for (int r = 0; r < (1 << op.k); ++r) {
-                        t.srcoff[r] = t.loff[op.perm[r]];
-                        mats.push_back(op.U[r].real());
-                        mats.push_back(op.U[r].imag());
-                    }
-                } else {
-                    for (const cd &v : op.U) {
-                        mats.push_back(v.real());
-                        mats.push_back(v.imag());
-                    }
-                }
-            }
-            tops.push_back(t);
-        }
+        qsv::compile_pass(passes[pi], rb, mats, progs[pi]);
+        n_rops += progs[pi].rops.size();
+        n_lops += progs[pi].lops.size();
     }
-    first[passes.size()] = tops.size();
-    // pool: [TileOp array][matrices in the state dtype]
-    const size_t ops_bytes = (tops.size() * sizeof(TileOp) + 255) & ~size_t(255);
+    // pool: [RegOp array][TileOp array][matrices in the state dtype]
+    const size_t r_bytes = (n_rops * sizeof(RegOp) + 255) & ~size_t(255);
+    const size_t l_bytes = (n_lops * sizeof(TileOp) + 255) & ~size_t(255);
     const size_t nmat = mats.size();
     const size_t mat_bytes = s->opt.dtype == QSV_C128 ? nmat * sizeof(double) : nmat * sizeof(float);
-    std::vector<unsigned char> host(ops_bytes + mat_bytes + 16);
-    if (!tops.empty()) std::memcpy(host.data(), tops.data(), tops.size() * sizeof(TileOp));
+    std::vector<unsigned char> host(r_bytes + l_bytes + mat_bytes + 16, 0);
+    {
+        size_t ro = 0, lo = 0;
+        for (const auto &pg : progs) {
+            if (!pg.rops.empty())
+                std::memcpy(host.data() + ro * sizeof(RegOp), pg.rops.data(), pg.rops.size() * sizeof(RegOp));
+            if (!pg.lops.empty())
+                std::memcpy(host.data() + r_bytes + lo * sizeof(TileOp), pg.lops.data(),
+                            pg.lops.size() * sizeof(TileOp));
+            ro += pg.rops.size();
+            lo += pg.lops.size();
+        }
+    }
     if (s->opt.dtype == QSV_C128) {
-        if (nmat) std::memcpy(host.data() + ops_bytes, mats.data(), mat_bytes);
+        if (nmat) std::memcpy(host.data() + r_bytes + l_bytes, mats.data(), mat_bytes);
     } else {
-        float *f = reinterpret_cast<float *>(host.data() + ops_bytes);
+        float *f = reinterpret_cast<float *>(host.data() + r_bytes + l_bytes);
         for (size_t i = 0; i < nmat; ++i) f[i] = (float)mats[i];
     }
     void *dpool = nullptr;
     QSV_TRY(stage(s, host.data(), host.size(), &dpool));
-    const TileOp *dops = reinterpret_cast<const TileOp *>(dpool);
-    const void *dmat = reinterpret_cast<const unsigned char *>(dpool) + ops_bytes;
+    const RegOp *drops = reinterpret_cast<const RegOp *>(dpool);
+    const TileOp *dlops = reinterpret_cast<const TileOp *>((const unsigned char *)dpool + r_bytes);
+    const void *dmat = (const unsigned char *)dpool + r_bytes + l_bytes;
+    size_t ro = 0, lo = 0;
     for (size_t pi = 0; pi < passes.size(); ++pi) {
-        const Pass &ps = passes[pi];
-        const int nops = (int)(first[pi + 1] - first[pi]);
-        if (nops == 0) continue;
+        const qsv::TileProgram &pg = progs[pi];
+        const size_t nr = pg.rops.size(), nl = pg.lops.size();
+        if ((pg.reg && nr == 0) || (!pg.reg && nl == 0)) {
+            ro += nr;
+            lo += nl;
+            continue;
+        }
         qsv::dev::TileArgs ta{};
-        ta.m = popc(ps.tile);
+        ta.m = pg.m;
         ta.nq = nq;
-        ta.n_ops = nops;
-        ta.tile_pos_n = ta.m;
+        ta.tile_pos_n = pg.m;
         int c = 0;
         for (int p = 0; p < 64; ++p)
-            if ((ps.tile >> p) & 1) ta.tpos[c++] = (uint8_t)p;
-        ta.n_tiles = 1ull << (nq - ta.m);
-        QSV_HIP(s, qsv::dev::launch_tile_pass(s->opt.dtype, s->d_state, ta, dops + first[pi], dmat,
-                                              s->stream));
-        double fl = 0.0;
-        for (size_t oi = first[pi]; oi < first[pi + 1]; ++oi) {
-            const TileOp &t = tops[oi];
-            const double frac = 1.0 / (double)(1ull << popc(t.lctrl));
-            if (t.kind == qsv::dev::TOP_DENSE) fl += frac * (8.0 * (1 << t.k) - 2.0);
-            else fl += frac * 6.0 * popc(t.touch) / (double)(1 << t.k);
+            if ((pg.tile >> p) & 1) ta.tpos[c++] = (uint8_t)p;
+        ta.n_tiles = 1ull << (nq - pg.m);
+        std::memcpy(ta.reg_lbit, pg.reg_lbit, 8);
+        std::memcpy(ta.thr_lbit, pg.thr_lbit, 16);
+        ta.rb = rb;
+        const int tok = tbegin(s);
+        if (pg.reg) {
+            ta.n_ops = (int)nr;
+            QSV_HIP(s, qsv::dev::launch_tile_reg(s->opt.dtype, s->d_state, ta, drops + ro, dmat,
+                                                 s->stream));
+        } else {
+            ta.n_ops = (int)nl;
+            QSV_HIP(s, qsv::dev::launch_tile_pass(s->opt.dtype, s->d_state, ta, dlops + lo, dmat,
+                                                  s->stream));
         }
-        account(s, (double)s->dim(), fl);
+        tend(s, tok, QSV_K_TILE, 2.0 * (double)s->dim() * s->elem());
+        account(s, (double)s->dim(), pg.flops_per_amp);
+        s->stats_remaps += pg.remaps;
+        ro += nr;
+        lo += nl;
     }
     return QSV_OK;
 }
@@ -411,7 +440,7 @@ qsv_status do_flush(qsv_sim *s) {
         for (const Op &op : f) QSV_TRY(launch_op(s, op));
     } else {
         const int m = std::min(tile_bits_for(s), s->n);
-        std::vector<Pass> passes = qsv::plan_passes(ops, s->n, m, 4, s->opt.k_max);
+        std::vector<Pass> passes = qsv::plan_passes(ops, s->n, m, 3, s->opt.k_max);
         for (const Pass &p : passes) s->stats.fused_ops += p.ops.size();
         QSV_TRY(run_tile_passes(s, passes));
     }
@@ -440,8 +469,10 @@ qsv_status check_ids(qsv_sim *s, int32_t m, const int32_t *ids, uint64_t *mask_o
 
 qsv_status prob_split_host(qsv_sim *s, int pos, double *p0, double *p1) {
     QSV_TRY(ensure_ws(s, qsv::dev::reduce_workspace_bytes(s->n)));
+    const int tok = tbegin(s);
     QSV_HIP(s, qsv::dev::prob_split(s->opt.dtype, s->d_state, s->n, pos, (double *)s->d_ws,
                                     s->d_small, s->stream));
+    tend(s, tok, QSV_K_REDUCE, (double)s->dim() * s->elem());
     double h[2];
     QSV_HIP(s, hipMemcpyAsync(h, s->d_small, sizeof(h), hipMemcpyDeviceToHost, s->stream));
     QSV_TRY(sync(s));
@@ -453,6 +484,8 @@ qsv_status prob_split_host(qsv_sim *s, int pos, double *p0, double *p1) {
 }
 
 }  // namespace
+
+void qsv::set_last_error(const std::string &msg) { g_err = msg; }
 
 // =================================================================== ABI
 extern "C" {
@@ -470,7 +503,7 @@ qsv_status qsv_options_default(qsv_options *opt) {
     opt->n_max = 30;
     opt->dtype = QSV_C128;
     opt->mode = QSV_MODE_TILED;
-    opt->k_max = 3;
+    opt->k_max = 2;
     opt->tile_bits = 0;
     opt->queue_limit = 0;
     return QSV_OK;
@@ -491,6 +524,9 @@ qsv_status qsv_create(const qsv_options *opt, qsv_sim **out) {
         (opt->tile_bits > 0 && opt->tile_bits < qsv::kMaxK + 1))
         return fail(nullptr, QSV_EINVAL, "tile_bits must be 0 or in 6.." + std::to_string(maxm));
     if (opt->queue_limit < 0) return fail(nullptr, QSV_EINVAL, "queue_limit must be >= 0");
+    if (opt->timing != 0 && opt->timing != 1) return fail(nullptr, QSV_EINVAL, "timing must be 0 or 1");
+    if (opt->reg_bits != 0 && (opt->reg_bits < 3 || opt->reg_bits > 5))
+        return fail(nullptr, QSV_EINVAL, "reg_bits must be 0 or 3..5");
     const int elem = opt->dtype == QSV_C128 ? 16 : 8;
     if (opt->state) {
         if (opt->state_bytes < (uint64_t)elem << opt->n_max)
@@ -531,6 +567,11 @@ qsv_status qsv_destroy(qsv_sim *s) {
     }
     for (void *v : s->d_vec)
         if (v) (void)hipFree(v);
+    for (auto &r : s->ev_pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     delete s;
     return QSV_OK;
 }
@@ -674,8 +715,10 @@ qsv_status qsv_get_probability(qsv_sim *s, int32_t m, const int32_t *qubits, con
     QSV_TRY(ensure_ws(s, qsv::dev::reduce_workspace_bytes(s->n)));
     qsv::dev::IndexArgs ia;
     index_args(mask, ones, ia);
+    const int tok = tbegin(s);
     QSV_HIP(s, qsv::dev::prob_masked(s->opt.dtype, s->d_state, 1ull << (s->n - m), ia,
                                      (double *)s->d_ws, s->d_small, s->stream));
+    tend(s, tok, QSV_K_REDUCE, (double)(1ull << (s->n - m)) * s->elem());
     QSV_HIP(s, hipMemcpyAsync(out, s->d_small, sizeof(double), hipMemcpyDeviceToHost, s->stream));
     s->stats.kernels += 2;
     s->stats.alg_bytes += (double)(1ull << (s->n - m)) * s->elem();
@@ -735,9 +778,11 @@ static qsv_status expectation_positions(qsv_sim *s, const void *psi, int nq, int
     QSV_HIP(s, hipMemcpyAsync(w, hostmeta.data(), meta, hipMemcpyHostToDevice, s->stream));
     QSV_HIP(s, hipStreamSynchronize(s->stream));
     double *ws = (double *)(w + meta);
+    const int tok = tbegin(s);
     QSV_HIP(s, qsv::dev::pauli_expectation(s->opt.dtype, psi, nq, (int)groups.size(), groups.data(),
                                            dz, dc, dny, nterms, ws, s->ws_bytes - meta,
                                            s->d_small, s->stream));
+    tend(s, tok, QSV_K_REDUCE, (double)nchunks * (double)(1ull << nq) * s->elem());
     double h[2];
     QSV_HIP(s, hipMemcpyAsync(h, s->d_small, sizeof(h), hipMemcpyDeviceToHost, s->stream));
     QSV_TRY(sync(s));
@@ -814,7 +859,9 @@ qsv_status qsv_sample(qsv_sim *s, int32_t shots, const double *u, uint64_t *out)
     uint64_t *dout = (uint64_t *)(w + ub);
     double *dws = (double *)(w + 2 * ub);
     QSV_HIP(s, hipMemcpyAsync(du, u, shots * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    const int tok = tbegin(s);
     QSV_HIP(s, qsv::dev::sample(s->opt.dtype, s->d_state, s->n, shots, du, dws, dout, s->stream));
+    tend(s, tok, QSV_K_REDUCE, (double)s->dim() * s->elem());
     QSV_HIP(s, hipMemcpyAsync(out, dout, shots * sizeof(uint64_t), hipMemcpyDeviceToHost, s->stream));
     s->stats.kernels += 3;
     s->stats.alg_bytes += (double)s->dim() * s->elem();
@@ -882,6 +929,31 @@ qsv_status qsv_get_stats(const qsv_sim *s, qsv_stats *out) {
 qsv_status qsv_reset_stats(qsv_sim *s) {
     QSV_CHECK(s);
     s->stats = qsv_stats{};
+    QSV_TRY(collect_times(s));
+    for (int c = 0; c < QSV_K_COUNT; ++c) {
+        s->k_ms[c] = 0.0;
+        s->k_launch[c] = 0;
+        s->k_bytes[c] = 0.0;
+    }
+    return QSV_OK;
+}
+
+qsv_status qsv_get_kernel_times(qsv_sim *s, int32_t kclass, double *ms, uint64_t *launches,
+                                double *alg_bytes) {
+    QSV_CHECK(s);
+    if (kclass < 0 || kclass >= QSV_K_COUNT) return fail(s, QSV_EINVAL, "unknown kernel class");
+    QSV_TRY(collect_times(s));
+    if (ms) *ms = s->k_ms[kclass];
+    if (launches) *launches = s->k_launch[kclass];
+    if (alg_bytes) *alg_bytes = s->k_bytes[kclass];
+    return QSV_OK;
+}
+
+qsv_status qsv_reset(qsv_sim *s) {
+    QSV_CHECK(s);
+    s->queue.clear();
+    if (!s->materialized) return QSV_OK;
+    QSV_HIP(s, qsv::dev::fill_basis0(s->opt.dtype, s->d_state, s->dim(), s->stream));
     return QSV_OK;
 }
 
@@ -900,7 +972,7 @@ qsv_status qsv_plan(qsv_sim *s, int32_t *n_ops, int32_t *n_passes, int32_t max_o
         np = (int)flat.size();
     } else {
         const int m = std::min(tile_bits_for(s), s->n);
-        std::vector<Pass> passes = qsv::plan_passes(ops, s->n, m, 4, s->opt.k_max);
+        std::vector<Pass> passes = qsv::plan_passes(ops, s->n, m, 3, s->opt.k_max);
         np = (int)passes.size();
         for (auto &p : passes)
             for (auto &o : p.ops) flat.push_back(o);
@@ -922,3 +994,221 @@ qsv_status qsv_plan(qsv_sim *s, int32_t *n_ops, int32_t *n_passes, int32_t max_o
 }
 
 }  // extern "C"
+
+// ======================================================== adjoint gradient
+namespace {
+
+// Points the handle's launch machinery at another vector for a while.
+struct StateSwap {
+    qsv_sim *s;
+    void *ptr;
+    int n;
+    StateSwap(qsv_sim *sim, void *buf, int nq) : s(sim), ptr(sim->d_state), n(sim->n) {
+        s->d_state = buf;
+        s->n = nq;
+    }
+    void to(void *buf) { s->d_state = buf; }
+    ~StateSwap() {
+        s->d_state = ptr;
+        s->n = n;
+    }
+};
+
+void rotation_matrix(int op, double theta, std::vector<cd> &U) {
+    const double c = std::cos(theta / 2), sn = std::sin(theta / 2);
+    if (op == QSV_OP_RX) U = {cd(c, 0), cd(0, -sn), cd(0, -sn), cd(c, 0)};
+    else if (op == QSV_OP_RY) U = {cd(c, 0), cd(-sn, 0), cd(sn, 0), cd(c, 0)};
+    else U = {std::polar(1.0, -theta / 2), cd(0, 0), cd(0, 0), std::polar(1.0, theta / 2)};
+}
+
+// Read gate g of a flat circuit (positions = circuit qubits).
+qsv_status circuit_gate(qsv_sim *s, const qsv_circuit *c, int g, Gate &out, int *axis,
+                        int *param) {
+    const int k = c->k[g], nc = c->c[g], op = c->op[g];
+    if (k < 1 || k > qsv::kMaxK || nc < 0 || k + nc > 8 || k + nc > c->n_qubits)
+        return fail(s, QSV_EINVAL, "gate " + std::to_string(g) + ": bad qubit counts");
+    out = Gate();
+    out.k = k;
+    uint64_t seen = 0;
+    for (int j = 0; j < k + nc; ++j) {
+        const int q = c->qubits[8 * g + j];
+        if (q < 0 || q >= c->n_qubits || ((seen >> q) & 1))
+            return fail(s, QSV_EINVAL, "gate " + std::to_string(g) + ": bad or repeated qubit");
+        seen |= 1ull << q;
+        if (j < k) out.t[j] = q;
+        else out.ctrl |= 1ull << q;
+    }
+    *axis = 0;
+    *param = -1;
+    if (op == QSV_OP_MATRIX) {
+        if (!c->matrices || !c->mat_off) return fail(s, QSV_EINVAL, "matrix gate without matrices");
+        const int D = 1 << k;
+        const double *m = c->matrices + 2 * c->mat_off[g];
+        out.U.resize((size_t)D * D);
+        for (int e = 0; e < D * D; ++e) {
+            if (!std::isfinite(m[2 * e]) || !std::isfinite(m[2 * e + 1]))
+                return fail(s, QSV_EINVAL, "non-finite matrix entry");
+            out.U[e] = cd(m[2 * e], m[2 * e + 1]);
+        }
+    } else if (op >= QSV_OP_RX && op <= QSV_OP_RZ) {
+        if (k != 1) return fail(s, QSV_EINVAL, "rotation gates act on one target");
+        const int p = c->param ? c->param[g] : -1;
+        if (p < 0 || p >= c->n_params || !c->params)
+            return fail(s, QSV_EINVAL, "rotation gate " + std::to_string(g) + ": bad parameter index");
+        const double th = c->params[p];
+        if (!std::isfinite(th)) return fail(s, QSV_EINVAL, "non-finite angle");
+        rotation_matrix(op, th, out.U);
+        *axis = op;   // 1 = X, 2 = Y, 3 = Z
+        *param = p;
+    } else {
+        return fail(s, QSV_EINVAL, "unknown gate op");
+    }
+    return QSV_OK;
+}
+
+qsv_status ensure_vectors(qsv_sim *s, uint64_t amps) {
+    if (s->vec_amps >= amps && s->vec_dtype == s->opt.dtype) return QSV_OK;
+    QSV_HIP(s, hipStreamSynchronize(s->stream));
+    for (void *&v : s->d_vec)
+        if (v) {
+            QSV_HIP(s, hipFree(v));
+            v = nullptr;
+        }
+    for (int i = 0; i < 2; ++i) {
+        hipError_t e = hipMalloc(&s->d_vec[i], amps * s->elem());
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(s, QSV_ENOMEM, "hipMalloc of the adjoint vectors failed");
+        }
+    }
+    s->vec_amps = amps;
+    s->vec_dtype = s->opt.dtype;
+    return QSV_OK;
+}
+
+qsv_status run_ops(qsv_sim *s, const std::vector<Op> &ops) {
+    if (s->opt.mode == QSV_MODE_PERGATE) {
+        for (const Op &op : ops) QSV_TRY(launch_op(s, op));
+        return QSV_OK;
+    }
+    if (s->opt.mode == QSV_MODE_FUSED) {
+        for (const Op &op : qsv::fuse(ops, s->opt.k_max)) QSV_TRY(launch_op(s, op));
+        return QSV_OK;
+    }
+    const int m = std::min(tile_bits_for(s), s->n);
+    return run_tile_passes(s, qsv::plan_passes(ops, s->n, m, 3, s->opt.k_max));
+}
+
+}  // namespace
+
+extern "C" qsv_status qsv_adjoint_gradient(qsv_sim *s, const qsv_circuit *circ,
+                                           const qsv_pauli_sum *ham, double *value_out,
+                                           double *grad_out) {
+    QSV_CHECK(s);
+    if (!circ || !ham || !value_out) return fail(s, QSV_EINVAL, "NULL argument");
+    if (circ->n_qubits < 1 || circ->n_qubits > qsv::kMaxQubits || circ->n_gates < 0 ||
+        (circ->n_gates > 0 && (!circ->op || !circ->k || !circ->c || !circ->qubits)) ||
+        circ->n_params < 0 || (circ->n_params > 0 && !grad_out))
+        return fail(s, QSV_EINVAL, "bad circuit description");
+    if (ham->n_terms < 0 || (ham->n_terms > 0 && (!ham->xmask || !ham->zmask || !ham->coeff)))
+        return fail(s, QSV_EINVAL, "bad Pauli sum");
+    const int n = circ->n_qubits;
+    const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    for (int t = 0; t < ham->n_terms; ++t)
+        if (((ham->xmask[t] | ham->zmask[t]) & ~full) != 0 || !std::isfinite(ham->coeff[t]))
+            return fail(s, QSV_EINVAL, "Pauli term outside the circuit's qubits");
+    const int G = circ->n_gates;
+    std::vector<Gate> gates(G);
+    std::vector<int> axis(G), param(G);
+    int nrot = 0;
+    for (int g = 0; g < G; ++g) {
+        QSV_TRY(circuit_gate(s, circ, g, gates[g], &axis[g], &param[g]));
+        if (axis[g]) ++nrot;
+    }
+    const uint64_t dim = 1ull << n;
+    QSV_TRY(ensure_vectors(s, dim));
+    if (!s->d_small) QSV_HIP(s, hipMalloc((void **)&s->d_small, 64 * sizeof(double)));
+    void *psi = s->d_vec[0], *phi = s->d_vec[1];
+    const uint64_t npairs_max = dim >> 1;
+    const int nb = qsv::dev::adjoint_blocks(npairs_max);
+    // workspace: [x z c ny | param order | grad | partials]
+    const int T = ham->n_terms;
+    const size_t off_z = 8 * (size_t)(T + 1), off_c = 16 * (size_t)(T + 1), off_ny = 24 * (size_t)(T + 1);
+    const size_t off_po = (off_ny + 4 * (size_t)(T + 1) + 255) & ~size_t(255);
+    const size_t off_gr = (off_po + 4 * (size_t)(nrot + 1) + 255) & ~size_t(255);
+    const size_t off_pa = (off_gr + 8 * (size_t)(circ->n_params + 1) + 255) & ~size_t(255);
+    const size_t need = off_pa + 8 * (size_t)nb * (nrot + 1) + 4096;
+    QSV_TRY(ensure_ws(s, need));
+    unsigned char *w = (unsigned char *)s->d_ws;
+    std::vector<unsigned char> meta(off_gr, 0);
+    std::vector<int32_t> ny(T + 1, 0), porder;
+    for (int t = 0; t < T; ++t) ny[t] = popc(ham->xmask[t] & ham->zmask[t]);
+    if (T) {
+        std::memcpy(meta.data(), ham->xmask, 8 * T);
+        std::memcpy(meta.data() + off_z, ham->zmask, 8 * T);
+        std::memcpy(meta.data() + off_c, ham->coeff, 8 * T);
+        std::memcpy(meta.data() + off_ny, ny.data(), 4 * T);
+    }
+    for (int g = G - 1; g >= 0; --g)
+        if (axis[g]) porder.push_back(param[g]);
+    if (!porder.empty()) std::memcpy(meta.data() + off_po, porder.data(), 4 * porder.size());
+    QSV_HIP(s, hipMemcpyAsync(w, meta.data(), off_gr, hipMemcpyHostToDevice, s->stream));
+
+    StateSwap sw(s, psi, n);
+    // forward: psi = U|0>
+    QSV_HIP(s, qsv::dev::fill_basis0(s->opt.dtype, psi, dim, s->stream));
+    {
+        std::vector<Op> ops;
+        for (const Gate &g : gates) {
+            Op op;
+            if (qsv::canonicalize(g, op)) ops.push_back(std::move(op));
+        }
+        QSV_TRY(run_ops(s, ops));
+    }
+    // phi = H psi, value = Re<psi|phi>
+    QSV_HIP(s, qsv::dev::ham_apply(s->opt.dtype, psi, phi, dim, T, (const uint64_t *)w,
+                                   (const uint64_t *)(w + off_z), (const double *)(w + off_c),
+                                   (const int32_t *)(w + off_ny), s->stream));
+    double *partial = (double *)(w + off_pa);
+    QSV_HIP(s, qsv::dev::dot_re(s->opt.dtype, psi, phi, dim, partial + (size_t)nb * nrot,
+                                s->d_small, s->stream));
+    // reverse sweep
+    int slot = 0;
+    for (int g = G - 1; g >= 0; --g) {
+        const Gate &gt = gates[g];
+        if (axis[g]) {
+            const int c = popc(gt.ctrl);
+            qsv::dev::IndexArgs ia;
+            index_args((1ull << gt.t[0]) | gt.ctrl, gt.ctrl, ia);
+            const double th = circ->params[param[g]];
+            const int tok = tbegin(s);
+            QSV_HIP(s, qsv::dev::adjoint_rotation(s->opt.dtype, psi, phi, dim >> (1 + c), ia,
+                                                  1ull << gt.t[0], axis[g], std::cos(th / 2),
+                                                  std::sin(th / 2), partial + (size_t)nb * slot,
+                                                  s->stream));
+            tend(s, tok, QSV_K_DENSE, 4.0 * (double)(dim >> c) * s->elem());
+            ++slot;
+        } else {
+            Gate d = gt;
+            const int D = 1 << gt.k;
+            for (int r = 0; r < D; ++r)
+                for (int cc = 0; cc < D; ++cc) d.U[(size_t)r * D + cc] = std::conj(gt.U[(size_t)cc * D + r]);
+            Op op;
+            if (!qsv::canonicalize(d, op)) continue;
+            sw.to(psi);
+            QSV_TRY(launch_op(s, op));
+            sw.to(phi);
+            QSV_TRY(launch_op(s, op));
+        }
+    }
+    double *dgrad = (double *)(w + off_gr);
+    if (circ->n_params > 0) {
+        QSV_HIP(s, qsv::dev::grad_finish(partial, nrot, nb, (const int32_t *)(w + off_po), dgrad,
+                                         circ->n_params, s->stream));
+        QSV_HIP(s, hipMemcpyAsync(grad_out, dgrad, 8 * (size_t)circ->n_params,
+                                  hipMemcpyDeviceToHost, s->stream));
+    }
+    QSV_HIP(s, hipMemcpyAsync(value_out, s->d_small, sizeof(double), hipMemcpyDeviceToHost,
+                              s->stream));
+    return sync(s);
+}

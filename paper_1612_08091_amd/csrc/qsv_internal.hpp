@@ -88,4 +88,7 @@ std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_
 // Dense 2^k x 2^k matrix of an op on its own target list (controls excluded).
 std::vector<cd> dense_matrix(const Op &op);
 
+// Message returned by qsv_last_error(NULL) (calls without a handle).
+void set_last_error(const std::string &msg);
+
 }  // namespace qsv

@@ -1,0 +1,243 @@
+// Lowering of a planned pass into the instruction list of a tile kernel.
+//
+// For the register-resident kernel (m = RB + 8 tile bits, 2^RB amplitudes per
+// thread) this decides, op by op, which tile bits live in registers: a 1- or
+// 2-qubit dense operation needs its targets there; when it finds them absent
+// a REMAP moves the tile through LDS into a layout holding the targets plus
+// the bits used soonest afterwards (Belady's furthest-next-use rule applied
+// to the RB register slots).  Diagonal operations run in any layout; wider
+// operations run on the LDS copy of the tile.
+#include <algorithm>
+#include <cstring>
+
+#include "device.hpp"
+#include "qsv_internal.hpp"
+#include "tileprog.hpp"
+
+namespace qsv {
+
+namespace {
+
+void push(std::vector<double> &mats, const cd &v) {
+    mats.push_back(v.real());
+    mats.push_back(v.imag());
+}
+
+// TileOp (LDS kernel form) of an op whose mixing targets lie in the tile.
+dev::TileOp lds_form(const Op &op, const int *li, std::vector<double> &mats) {
+    dev::TileOp t{};
+    t.k = op.k;
+    t.touch = op.touch;
+    t.mat = (int64_t)(mats.size() / 2);
+    bool inside = true;
+    for (int j = 0; j < op.k; ++j)
+        if (li[op.t[j]] < 0) inside = false;
+    if (op.kind == Op::MONO && op.diag && !inside) {
+        t.kind = dev::TOP_DIAG_GLOBAL;
+        for (int j = 0; j < op.k; ++j) t.gt[j] = (uint8_t)op.t[j];
+        t.gctrl = op.ctrl;
+        for (int r = 0; r < (1 << op.k); ++r) push(mats, op.U[r]);
+        return t;
+    }
+    t.kind = op.kind == Op::MONO ? dev::TOP_MONO : dev::TOP_DENSE;
+    uint32_t lctrl = 0;
+    uint64_t ectrl = 0;
+    for (int p = 0; p < 64; ++p)
+        if ((op.ctrl >> p) & 1) {
+            if (li[p] >= 0) lctrl |= 1u << li[p];
+            else ectrl |= 1ull << p;
+        }
+    t.lctrl = lctrl;
+    t.ectrl = ectrl;
+    uint32_t ins = lctrl;
+    int lt[kMaxK];
+    for (int j = 0; j < op.k; ++j) {
+        lt[j] = li[op.t[j]];
+        ins |= 1u << lt[j];
+    }
+    t.npos = 0;
+    for (int b = 0; b < 32; ++b)
+        if ((ins >> b) & 1) t.pos[t.npos++] = (uint8_t)b;
+    for (int r = 0; r < (1 << op.k); ++r) {
+        uint32_t o = 0;
+        for (int j = 0; j < op.k; ++j)
+            if ((r >> j) & 1) o |= 1u << lt[j];
+        t.loff[r] = o;
+    }
+    if (op.kind == Op::MONO) {
+        for (int r = 0; r < (1 << op.k); ++r) {
+            t.srcoff[r] = t.loff[op.perm[r]];
+            push(mats, op.U[r]);
+        }
+    } else {
+        for (const cd &v : op.U) push(mats, v);
+    }
+    return t;
+}
+
+double lds_flops(const dev::TileOp &t) {
+    const double frac = 1.0 / (double)(1ull << __builtin_popcount(t.lctrl));
+    if (t.kind == dev::TOP_DENSE) return frac * (8.0 * (1 << t.k) - 2.0);
+    return frac * 6.0 * __builtin_popcount(t.touch) / (double)(1 << t.k);
+}
+
+void set_layout(uint32_t regmask, int m, int rb, uint8_t *reg_lbit, uint8_t *thr_lbit) {
+    int j = 0, i = 0;
+    for (int b = 0; b < m; ++b) {
+        if ((regmask >> b) & 1) reg_lbit[j++] = (uint8_t)b;
+        else thr_lbit[i++] = (uint8_t)b;
+    }
+    (void)rb;
+}
+
+}  // namespace
+
+void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram &prog) {
+    prog = TileProgram();
+    prog.tile = ps.tile;
+    int li[64];
+    int m = 0;
+    for (int p = 0; p < 64; ++p) {
+        li[p] = -1;
+        if ((ps.tile >> p) & 1) li[p] = m++;
+    }
+    prog.m = m;
+    const int tb = m - rb;
+    prog.reg = rb >= 3 && rb <= 5 && (tb == 8 || (tb == 9 && rb <= 4));
+    // the register kernel runs 1- and 2-qubit dense ops and diagonal ops only
+    for (const Op &op : ps.ops) {
+        if (op.kind == Op::MONO && (op.diag || op.touch == 0)) continue;
+        bool inside = true;
+        for (int j = 0; j < op.k; ++j)
+            if (li[op.t[j]] < 0) inside = false;
+        if (!inside || op.k > 2) prog.reg = false;
+    }
+    if (!prog.reg) {
+        for (const Op &op : ps.ops) {
+            if (op.kind == Op::MONO && op.touch == 0) continue;
+            dev::TileOp t = lds_form(op, li, mats);
+            prog.flops_per_amp += lds_flops(t);
+            prog.lops.push_back(t);
+        }
+        return;
+    }
+    // classify
+    struct Item {
+        int kind;          // ROP_G1/G2/DIAG/LDS
+        uint32_t need;     // local bits that must be register bits
+        const Op *op;
+    };
+    std::vector<Item> items;
+    for (const Op &op : ps.ops) {
+        if (op.kind == Op::MONO && op.touch == 0) continue;
+        if (op.kind == Op::MONO && op.diag) {
+            items.push_back({dev::ROP_DIAG, 0u, &op});
+            continue;
+        }
+        bool inside = true;
+        uint32_t need = 0;
+        for (int j = 0; j < op.k; ++j) {
+            if (li[op.t[j]] < 0) inside = false;
+            else need |= 1u << li[op.t[j]];
+        }
+        if (inside && op.k <= 2) items.push_back({op.k == 1 ? dev::ROP_G1 : dev::ROP_G2, need, &op});
+        else items.push_back({dev::ROP_LDS, 0u, &op});
+    }
+    const int n_items = (int)items.size();
+    // initial register set: the first needed bits, then the highest free bits
+    uint32_t S = 0;
+    for (const Item &it : items) {
+        if (__builtin_popcount(S | it.need) > rb) break;
+        S |= it.need;
+        if (__builtin_popcount(S) == rb) break;
+    }
+    for (int b = m - 1; b >= 0 && __builtin_popcount(S) < rb; --b) S |= 1u << b;
+    set_layout(S, m, rb, prog.reg_lbit, prog.thr_lbit);
+    uint8_t cur_reg[8];
+    std::memcpy(cur_reg, prog.reg_lbit, 8);
+
+    for (int i = 0; i < n_items; ++i) {
+        const Item &it = items[i];
+        const Op &op = *it.op;
+        if ((it.need & ~S) != 0) {
+            // Belady: keep the bits needed soonest
+            int next_use[32];
+            for (int b = 0; b < m; ++b) next_use[b] = 1 << 30;
+            for (int j = n_items - 1; j >= i; --j)
+                for (int b = 0; b < m; ++b)
+                    if ((items[j].need >> b) & 1) next_use[b] = j;
+            uint32_t Sn = it.need;
+            std::vector<int> cand;
+            for (int b = 0; b < m; ++b)
+                if (!((Sn >> b) & 1)) cand.push_back(b);
+            std::sort(cand.begin(), cand.end(), [&](int x, int y) {
+                if (next_use[x] != next_use[y]) return next_use[x] < next_use[y];
+                const bool sx = (S >> x) & 1, sy = (S >> y) & 1;
+                if (sx != sy) return sx;
+                return x > y;
+            });
+            for (int c = 0; c < (int)cand.size() && __builtin_popcount(Sn) < rb; ++c)
+                Sn |= 1u << cand[c];
+            dev::RegOp r{};
+            r.kind = dev::ROP_REMAP;
+            set_layout(Sn, m, rb, r.reg_lbit, r.thr_lbit);
+            std::memcpy(cur_reg, r.reg_lbit, 8);
+            prog.rops.push_back(r);
+            prog.remaps += 1;
+            S = Sn;
+        }
+        dev::RegOp r{};
+        r.kind = it.kind;
+        if (it.kind == dev::ROP_DIAG) {
+            r.a = op.k;
+            r.ctrl = op.ctrl;
+            for (int j = 0; j < op.k; ++j) r.gt[j] = (uint8_t)op.t[j];
+            r.mat = (int64_t)(mats.size() / 2);
+            for (int e = 0; e < (1 << op.k); ++e) push(mats, op.U[e]);
+            prog.flops_per_amp += 6.0 * __builtin_popcount(op.touch) / (double)(1 << op.k) /
+                                  (double)(1ull << popc(op.ctrl));
+        } else if (it.kind == dev::ROP_LDS) {
+            dev::TileOp t = lds_form(op, li, mats);
+            prog.flops_per_amp += lds_flops(t);
+            r.a = (int32_t)prog.lops.size();
+            prog.lops.push_back(t);
+        } else {
+            auto reg_index = [&](int local_bit) {
+                for (int j = 0; j < rb; ++j)
+                    if (cur_reg[j] == local_bit) return j;
+                return -1;
+            };
+            std::vector<cd> U = dense_matrix(op);
+            r.ctrl = op.ctrl;
+            r.mat = (int64_t)(mats.size() / 2);
+            if (it.kind == dev::ROP_G1) {
+                r.a = reg_index(li[op.t[0]]);
+                for (const cd &v : U) push(mats, v);
+                prog.flops_per_amp += 14.0 / (double)(1ull << popc(op.ctrl));
+            } else {
+                const int j0 = reg_index(li[op.t[0]]), j1 = reg_index(li[op.t[1]]);
+                if (j0 < j1) {
+                    r.a = j0;
+                    r.b = j1;
+                    for (const cd &v : U) push(mats, v);
+                } else {
+                    r.a = j1;
+                    r.b = j0;
+                    auto sw = [](int x) { return ((x & 1) << 1) | ((x >> 1) & 1); };
+                    for (int row = 0; row < 4; ++row)
+                        for (int col = 0; col < 4; ++col) push(mats, U[sw(row) * 4 + sw(col)]);
+                }
+                prog.flops_per_amp += 30.0 / (double)(1ull << popc(op.ctrl));
+            }
+        }
+        prog.rops.push_back(r);
+    }
+}
+
+}  // namespace qsv
+
+namespace qsv {
+dev::TileOp lower_to_lds(const Op &op, const int *li, std::vector<double> &mats) {
+    return lds_form(op, li, mats);
+}
+}  // namespace qsv

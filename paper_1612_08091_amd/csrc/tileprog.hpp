@@ -1,0 +1,35 @@
+// Lowering of planned passes to tile-kernel instruction lists.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "device.hpp"
+#include "qsv_internal.hpp"
+
+namespace qsv {
+
+struct TileProgram {
+    uint64_t tile = 0;
+    int m = 0;
+    bool reg = false;                   // register-resident kernel (else LDS kernel)
+    std::vector<dev::RegOp> rops;       // register kernel instructions
+    std::vector<dev::TileOp> lops;      // LDS ops (all ops of an LDS-kernel pass)
+    uint8_t reg_lbit[8] = {};           // initial layout (register kernel)
+    uint8_t thr_lbit[16] = {};
+    int remaps = 0;
+    double flops_per_amp = 0.0;
+};
+
+// Lower pass `ps` for a register kernel with rb register bits (rb = 0: LDS
+// kernel).  The register kernel is used when the tile has rb + 8 bits
+// (256 threads) or rb + 9 bits (512 threads, rb <= 4).
+// Matrices are appended to `mats` as complex128 (re, im) pairs; ops refer to
+// them by complex-entry offset.
+void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram &prog);
+
+// LDS-kernel form of one op; li maps a global bit position to its tile bit
+// (-1 outside the tile).
+dev::TileOp lower_to_lds(const Op &op, const int *li, std::vector<double> &mats);
+
+}  // namespace qsv

@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
     _fields_ = [("n_max", ctypes.c_int32), ("dtype", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("k_max", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
                 ("queue_limit", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("state", ctypes.c_void_p), ("state_bytes", ctypes.c_uint64)]
+                ("state", ctypes.c_void_p), ("state_bytes", ctypes.c_uint64),
+                ("timing", ctypes.c_int32), ("reg_bits", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -99,6 +100,8 @@ _SIGS = {
     "qsv_get_amplitudes": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
     "qsv_state_pointer": (ctypes.c_int, [_P, _P, _P]),
     "qsv_get_stats": (ctypes.c_int, [_P, _P]),
+    "qsv_reset": (ctypes.c_int, [_P]),
+    "qsv_get_kernel_times": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "qsv_reset_stats": (ctypes.c_int, [_P]),
     "qsv_plan": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     "qsv_adjoint_gradient": (ctypes.c_int, [_P, _P, _P, _P, _P]),
@@ -164,7 +167,7 @@ class Simulator:
 
     def __init__(self, n_max: int = 30, dtype="c128", mode="tiled", k_max: int = 3,
                  tile_bits: int = 0, queue_limit: int = 0, stream=None, state=None,
-                 use_torch_stream: bool = True):
+                 use_torch_stream: bool = True, timing: bool = False, reg_bits: int = 0):
         opt = Options()
         _check(lib.qsv_options_default(ctypes.byref(opt)))
         opt.n_max = n_max
@@ -173,6 +176,8 @@ class Simulator:
         opt.k_max = k_max
         opt.tile_bits = tile_bits
         opt.queue_limit = queue_limit
+        opt.timing = int(bool(timing))
+        opt.reg_bits = reg_bits
         if stream is None and use_torch_stream:
             stream = _torch_stream()
         opt.stream = stream
@@ -337,6 +342,23 @@ class Simulator:
     def reset_stats(self):
         _check(lib.qsv_reset_stats(self._h), self._h)
 
+    def reset(self):
+        """State back to |0...0> on the live qubits; queued gates dropped."""
+        _check(lib.qsv_reset(self._h), self._h)
+
+    KERNEL_CLASSES = {"tile": 0, "dense": 1, "mono": 2, "reduce": 3}
+
+    def kernel_times(self) -> dict:
+        """Per kernel class: (device ms, launches, algorithmic bytes), from HIP
+        events (needs timing=True)."""
+        out = {}
+        for name, cls in self.KERNEL_CLASSES.items():
+            ms, n, b = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_double()
+            _check(lib.qsv_get_kernel_times(self._h, cls, ctypes.byref(ms), ctypes.byref(n),
+                                            ctypes.byref(b)), self._h)
+            out[name] = (ms.value, n.value, b.value)
+        return out
+
     def plan(self, max_ops: int = 100000):
         """(operations, passes): operations as (matrix, targets, control mask)
         in execution order, planned from the queued gates (nothing runs)."""
@@ -384,7 +406,7 @@ class FlatCircuit:
             self.k[i] = len(gt.targets)
             self.c[i] = len(gt.controls)
             self.qubits[8 * i: 8 * i + len(qs)] = qs
-            if gt.param >= 0 and not gt.controls:
+            if gt.param >= 0:
                 self.op[i] = _AXIS_OP[gt.axis]
                 self.param[i] = gt.param
             else:
@@ -453,9 +475,9 @@ class Batch:
         return out[: self.count]
 
     def info(self):
-        tb, wg, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-        _check(lib.qsv_batch_info(self._h, ctypes.byref(tb), ctypes.byref(wg), ctypes.byref(ms)))
-        return {"tile_bits": tb.value, "wg_size": wg.value, "last_ms": ms.value}
+        tb, kf, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib.qsv_batch_info(self._h, ctypes.byref(tb), ctypes.byref(kf), ctypes.byref(ms)))
+        return {"tile_bits": tb.value, "k_fuse": kf.value, "last_ms": ms.value}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -1,0 +1,137 @@
+"""Adjoint gradient (differentiation form) on the GPU against the CPU oracle.
+
+Bars: <H> within 1e-12 * sum|c| of the oracle (complex128); the gradient
+within 1e-9 * max|g| of the oracle's parameter-shift gradient (exact for
+exp(-i theta P/2)); controlled rotations, whose generator has three
+eigenvalues so that the two-term shift rule does not hold, against central
+finite differences of the oracle (1e-6).  At the full 24-qubit size of
+config 4 the sampled parameters of tests/golden/config4_adjoint.json (oracle
+values) are compared.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def sim(n, **kw):
+    from paper_1612_08091_amd import qsv as Q
+    return Q.Simulator(n_max=n, **kw)
+
+
+@pytest.mark.parametrize("mode", ["tiled", "pergate"])
+def test_adjoint_matches_parameter_shift(mode):
+    from paper_1612_08091_amd import qsv as Q
+    rng = np.random.default_rng(31)
+    n, layers = 7, 3
+    circ = W.hea(n, layers, rng.uniform(0, 2 * math.pi, 2 * n * layers))
+    ham = W.random_pauli_local(n, 25, 4, rng)
+    s = sim(n, mode=mode)
+    val, grad = Q.adjoint_gradient(s, circ, ham)
+    want_val = oracle.energy(circ, ham)
+    want = oracle.grad_param_shift(circ, ham)
+    assert abs(val - want_val) <= 1e-12 * max(1.0, np.sum(np.abs(ham.coeff)))
+    assert np.max(np.abs(grad - want)) <= 1e-9 * max(1.0, np.max(np.abs(want)))
+    s.close()
+
+
+def test_adjoint_mixed_gates_and_controls():
+    from paper_1612_08091_amd import qsv as Q
+    rng = np.random.default_rng(32)
+    n = 6
+    th = rng.uniform(0, 2 * math.pi, 8)
+    c = W.Circuit(n, theta=th)
+    c.add(W.haar_unitary(4, rng), (0, 3))
+    c.add(W.rx(th[0]), (1,), name="rx", param=0, axis="X")
+    c.add(W.ry(th[1]), (2,), (0,), name="cry", param=1, axis="Y")       # controlled rotation
+    c.add(W.X, (5,), (1, 2), name="ccx")
+    c.add(W.rz(th[2]), (4,), name="rz", param=2, axis="Z")
+    c.add(W.haar_2x2(rng), (5,))
+    c.add(W.ry(th[3]), (3,), name="ry", param=3, axis="Y")
+    c.add(W.rz(th[4]), (0,), (4, 5), name="ccrz", param=4, axis="Z")
+    c.add(W.rx(th[5]), (2,), name="rx", param=5, axis="X")
+    c.add(W.ry(th[6]), (1,), name="ry", param=6, axis="Y")
+    c.add(W.rz(th[7]), (5,), name="rz", param=7, axis="Z")
+    c.add(W.SWAP, (1, 4))
+    ham = W.random_pauli_dense(n, 30, rng)
+    s = sim(n)
+    val, grad = Q.adjoint_gradient(s, c, ham)
+    assert abs(val - oracle.energy(c, ham)) <= 1e-12 * np.sum(np.abs(ham.coeff))
+    fd = oracle.grad_fd(c, ham, h=1e-5)
+    assert np.max(np.abs(grad - fd)) <= 1e-6
+    s.close()
+
+
+def test_adjoint_shared_parameter_accumulates():
+    from paper_1612_08091_amd import qsv as Q
+    n = 3
+    th = np.array([0.7])
+    c = W.Circuit(n, theta=th)
+    for q in range(n):
+        c.add(W.ry(th[0]), (q,), name="ry", param=0, axis="Y")
+    ham = W.PauliSum.from_strings(["ZII", "IZI", "IIZ"], [1.0, 1.0, 1.0])
+    s = sim(n)
+    val, grad = Q.adjoint_gradient(s, c, ham)
+    # <Z> = cos(theta) on each qubit: value 3 cos, derivative -3 sin
+    assert abs(val - 3 * math.cos(0.7)) <= 1e-14
+    assert abs(grad[0] + 3 * math.sin(0.7)) <= 1e-14
+    s.close()
+
+
+def test_adjoint_c64_tolerance():
+    from paper_1612_08091_amd import qsv as Q
+    rng = np.random.default_rng(33)
+    n, layers = 12, 3
+    circ = W.hea(n, layers, rng.uniform(0, 2 * math.pi, 2 * n * layers))
+    ham = W.random_pauli_local(n, 40, 4, rng)
+    s = sim(n, dtype="c64")
+    val, grad = Q.adjoint_gradient(s, circ, ham)
+    scale = np.sum(np.abs(ham.coeff))
+    assert abs(val - oracle.energy(circ, ham)) <= 1e-5 * scale
+    ps = oracle.grad_param_shift(circ, ham, params=range(0, len(circ.theta), 7))
+    assert np.max(np.abs(grad[::7] - ps)) <= 1e-5 * scale
+    s.close()
+
+
+def test_config4_full_size_against_oracle_golden():
+    from paper_1612_08091_amd import qsv as Q
+    with open(os.path.join(GOLDEN, "config4_adjoint.json")) as f:
+        gold = json.load(f)
+    circ, ham = W.config4()
+    s = sim(24)
+    val, grad = Q.adjoint_gradient(s, circ, ham)
+    scale = np.sum(np.abs(ham.coeff))
+    assert abs(val - gold["energy"]) <= 1e-12 * scale
+    g = np.array(gold["grad"])
+    got = grad[gold["params"]]
+    assert np.max(np.abs(got - g)) <= 1e-9 * max(1.0, np.max(np.abs(g)))
+    s.close()
+
+
+def test_torch_autograd_function():
+    import torch
+    from paper_1612_08091_amd.autograd import expectation
+    rng = np.random.default_rng(34)
+    n, layers = 3, 2
+    theta0 = rng.uniform(0, 2 * math.pi, 2 * n * layers)
+    circ = W.hea(n, layers, theta0)
+    ham = W.random_pauli_dense(n, 8, rng)
+    s = sim(n)
+    theta = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    e = expectation(theta, s, circ, ham)
+    e.backward()
+    want = oracle.grad_param_shift(circ, ham)
+    assert abs(e.item() - oracle.energy(circ, ham)) <= 1e-12
+    assert np.max(np.abs(theta.grad.numpy() - want)) <= 1e-10
+    assert torch.autograd.gradcheck(lambda t: expectation(t, s, circ, ham), (theta,),
+                                    eps=1e-6, atol=1e-7)
+    s.close()

@@ -1,0 +1,89 @@
+"""Batched form on the GPU: many HEA circuits of uneven size, each with its
+own Pauli sum, in one persistent launch replayed from a HIP graph.
+
+Bars: complex128 batches within 1e-12 * sum|c| of the oracle; complex64
+batches within 1e-5 * sum|c| (the FP32 tolerance on reductions).  Graph
+replays are checked against an eager (non-graph) run, with other device work
+between the replays.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch(count, n_lo, n_hi, layers, terms, seed):
+    rng = np.random.default_rng(seed)
+    circuits, hams = [], []
+    for _ in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        circuits.append(W.hea(n, layers, rng.uniform(0, 2 * math.pi, 2 * n * layers)))
+        hams.append(W.random_pauli_dense(n, terms, rng))
+    return circuits, hams
+
+
+@pytest.mark.parametrize("dtype,tile_bits", [("c128", 10), ("c128", 8), ("c64", 12), ("c64", 9)])
+def test_batch_matches_oracle(dtype, tile_bits):
+    from paper_1612_08091_amd import qsv as Q
+    # sizes on both sides of the LDS-resident limit
+    circuits, hams = small_batch(40, 3, 14, 3, 16, seed=41 + tile_bits)
+    b = Q.Batch(circuits, hams, dtype=dtype, autotune=False, tile_bits=tile_bits)
+    got = b.run()
+    want = np.array([oracle.energy(c, h) for c, h in zip(circuits, hams)])
+    scale = np.array([np.sum(np.abs(h.coeff)) for h in hams])
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    assert np.all(np.abs(got - want) <= tol * scale), np.max(np.abs(got - want) / scale)
+    b.close()
+
+
+def test_batch_graph_replays_equal_eager():
+    import torch
+    from paper_1612_08091_amd import qsv as Q
+    circuits, hams = small_batch(64, 4, 15, 4, 12, seed=43)
+    eager = Q.Batch(circuits, hams, dtype="c64", autotune=False, tile_bits=11, use_graph=False)
+    ref = eager.run()
+    g = Q.Batch(circuits, hams, dtype="c64", autotune=False, tile_bits=11, use_graph=True)
+    x = torch.randn(1 << 20, device="cuda")
+    for rep in range(4):
+        out = g.run()
+        assert np.array_equal(out, ref), rep
+        y = (x * 2.0 + 1.0).sum()     # unrelated device work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(y)
+    eager.close()
+    g.close()
+
+
+def test_batch_autotune_and_cache(tmp_path):
+    from paper_1612_08091_amd import qsv as Q
+    circuits, hams = small_batch(24, 6, 16, 2, 8, seed=44)
+    cache = str(tmp_path / "tune.json")
+    b = Q.Batch(circuits, hams, dtype="c64", autotune=True, tune_cache=cache)
+    info = b.info()
+    out1 = b.run()
+    b.close()
+    b2 = Q.Batch(circuits, hams, dtype="c64", autotune=True, tune_cache=cache)
+    assert b2.info()["tile_bits"] == info["tile_bits"] and b2.info()["k_fuse"] == info["k_fuse"]
+    want = np.array([oracle.energy(c, h) for c, h in zip(circuits, hams)])
+    scale = np.array([np.sum(np.abs(h.coeff)) for h in hams])
+    assert np.all(np.abs(b2.run() - want) <= 1e-5 * scale)
+    assert np.all(np.abs(out1 - want) <= 1e-5 * scale)
+    b2.close()
+
+
+def test_config3_subset_against_oracle_and_single_path():
+    from paper_1612_08091_amd import qsv as Q
+    circuits, hams = W.config3(count=256)
+    b = Q.Batch(circuits, hams, dtype="c64", autotune=False, tile_bits=12)
+    got = b.run()
+    b.close()
+    rng = np.random.default_rng(45)
+    pick = rng.choice(256, size=12, replace=False)
+    for i in pick:
+        want = oracle.energy(circuits[i], hams[i])
+        assert abs(got[i] - want) <= 1e-5 * np.sum(np.abs(hams[i].coeff)), i
