@@ -276,7 +276,8 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
 }
 
 int tile_pass_max_bits(int dtype) { return dtype == 0 ? 13 : 14; }
-int tile_reg_bits(int dtype) { return dtype == 0 ? 4 : 5; }
+// 16 amplitudes per thread: 64 VGPRs of state for complex128, 32 for complex64
+int tile_reg_bits(int) { return 4; }
 
 template <typename K>
 static hipError_t set_lds_attr(K kern, size_t bytes) {

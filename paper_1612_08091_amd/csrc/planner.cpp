@@ -205,7 +205,7 @@ std::vector<Op> fuse_impl(const std::vector<Op> &ops, int k_max, uint64_t allowe
     for (int i = 0; i < (int)ops.size(); ++i) {
         const Op &op = ops[i];
         const uint64_t all = op.qubits(), mix = op.mixing();
-        const bool fusable = k_max > 1 && (all & ~allowed) == 0 && popc(all) <= k_max;
+        const bool fusable = k_max >= 1 && (all & ~allowed) == 0 && popc(all) <= k_max;
         // latest block that does not commute with op
         int j = -1;
         for (int b = (int)blocks.size() - 1; b >= 0; --b)
@@ -287,4 +287,10 @@ std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_
     return passes;
 }
 
+}  // namespace qsv
+
+namespace qsv {
+std::vector<Pass> plan_tiled(const std::vector<Op> &ops, int n, int m, int k_max) {
+    return plan_passes(fuse(ops, k_max), n, m, 3, k_max);
+}
 }  // namespace qsv

@@ -440,7 +440,7 @@ qsv_status do_flush(qsv_sim *s) {
         for (const Op &op : f) QSV_TRY(launch_op(s, op));
     } else {
         const int m = std::min(tile_bits_for(s), s->n);
-        std::vector<Pass> passes = qsv::plan_passes(ops, s->n, m, 3, s->opt.k_max);
+        std::vector<Pass> passes = qsv::plan_tiled(ops, s->n, m, s->opt.k_max);
         for (const Pass &p : passes) s->stats.fused_ops += p.ops.size();
         QSV_TRY(run_tile_passes(s, passes));
     }
@@ -972,7 +972,7 @@ qsv_status qsv_plan(qsv_sim *s, int32_t *n_ops, int32_t *n_passes, int32_t max_o
         np = (int)flat.size();
     } else {
         const int m = std::min(tile_bits_for(s), s->n);
-        std::vector<Pass> passes = qsv::plan_passes(ops, s->n, m, 3, s->opt.k_max);
+        std::vector<Pass> passes = qsv::plan_tiled(ops, s->n, m, s->opt.k_max);
         np = (int)passes.size();
         for (auto &p : passes)
             for (auto &o : p.ops) flat.push_back(o);
@@ -1096,7 +1096,7 @@ qsv_status run_ops(qsv_sim *s, const std::vector<Op> &ops) {
         return QSV_OK;
     }
     const int m = std::min(tile_bits_for(s), s->n);
-    return run_tile_passes(s, qsv::plan_passes(ops, s->n, m, 3, s->opt.k_max));
+    return run_tile_passes(s, qsv::plan_tiled(ops, s->n, m, s->opt.k_max));
 }
 
 }  // namespace

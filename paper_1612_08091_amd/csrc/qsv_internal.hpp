@@ -85,6 +85,11 @@ struct Pass {
 std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_bits,
                               int k_max);
 
+// Whole-queue fusion to k_max first, then pass planning of the fused ops
+// (blocks are not cut at pass boundaries); three low bits stay in every
+// tile for contiguous HBM runs.
+std::vector<Pass> plan_tiled(const std::vector<Op> &ops, int n, int m, int k_max);
+
 // Dense 2^k x 2^k matrix of an op on its own target list (controls excluded).
 std::vector<cd> dense_matrix(const Op &op);
 
