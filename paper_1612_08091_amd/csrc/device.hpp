@@ -34,7 +34,10 @@ struct MonoArgs {
 
 // One operation inside an LDS-tile pass.  Local positions index the tile
 // (bit i of the local index <-> i-th lowest tile position).
-enum TileOpKind : int32_t { TOP_DENSE = 0, TOP_MONO = 1, TOP_DIAG_GLOBAL = 2 };
+// TOP_DENSE_MFMA: dense k = 3..5 op on matrix cores; `mat` then points at
+// the real embedding W = [[Re U, -Im U], [Im U, Re U]] (2^(k+1) x 2^(k+1),
+// row-major, in the tile's real type).
+enum TileOpKind : int32_t { TOP_DENSE = 0, TOP_MONO = 1, TOP_DIAG_GLOBAL = 2, TOP_DENSE_MFMA = 3 };
 struct TileOp {
     int32_t kind;
     int32_t k;

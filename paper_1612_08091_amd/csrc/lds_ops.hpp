@@ -119,6 +119,88 @@ __device__ __forceinline__ uint64_t deposit_bits(uint32_t l, const uint8_t *tpos
     return out;
 }
 
+// ------------------------------------------------------ matrix-core ops
+// A dense k-qubit op (k = 3..5) on the tile as a real GEMM Y = W X on the
+// 16x16x4 MFMA: X holds one group of 2^k amplitudes per column as
+// [Re x; Im x] (2^(k+1) rows), W is the real embedding of U.  A wave takes 16
+// groups at a time (one B column per lane % 16); the W fragments a lane
+// feeds to the A operand stay in registers for the whole op.
+typedef float qsv_v4f __attribute__((ext_vector_type(4)));
+typedef double qsv_v4d __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Mfma;
+template <> struct Mfma<float> {
+    using V = qsv_v4f;
+    static __device__ __forceinline__ V op(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // row of the 16x16 result held in accumulator element r of lane l
+    static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct Mfma<double> {
+    using V = qsv_v4d;
+    static __device__ __forceinline__ V op(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+template <typename R, int K>
+__device__ __forceinline__ void lds_dense_mfma(typename VT<R>::T *tile, int m, const TileOp &op,
+                                               const R *__restrict__ W) {
+    using V = typename Mfma<R>::V;
+    constexpr int D = 1 << K, D2 = 2 * D;
+    constexpr int MB = D2 / 16, KC = D2 / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int npos = op.npos;
+    const uint32_t ngroups = 1u << (m - npos);
+    const uint32_t ncb = (ngroups + 15) >> 4;
+    R a[MB][KC];
+    uint32_t in_off[KC];
+    int in_part[KC];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+        const int rho = 4 * kc + (lane >> 4);
+        in_off[kc] = op.loff[rho & (D - 1)];
+        in_part[kc] = rho >= D;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) a[mb][kc] = W[(16 * mb + (lane & 15)) * D2 + rho];
+    }
+    uint32_t out_off[MB][4];
+    int out_part[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * mb + Mfma<R>::row(lane, r);
+            out_off[mb][r] = op.loff[row & (D - 1)];
+            out_part[mb][r] = row >= D;
+        }
+    R *tr = reinterpret_cast<R *>(tile);
+    for (uint32_t cb = wave; cb < ncb; cb += nwaves) {
+        const uint32_t g = cb * 16 + (lane & 15);
+        const bool valid = g < ngroups;
+        const uint32_t l0 = valid ? (insert_local(g, op.pos, npos) | op.lctrl) : 0u;
+        V acc[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            const R b = valid ? tr[2 * swz<R>(l0 + in_off[kc]) + in_part[kc]] : R(0);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = Mfma<R>::op(a[mb][kc], b, acc[mb]);
+        }
+        if (valid) {
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    tr[2 * swz<R>(l0 + out_off[mb][r]) + out_part[mb][r]] = acc[mb][r];
+        }
+    }
+}
+
 // Apply LDS op `op` to the whole tile (all threads take part).
 template <typename R>
 __device__ void lds_op(typename VT<R>::T *tile, int m, uint64_t base, const TileArgs &ta,
@@ -126,7 +208,14 @@ __device__ void lds_op(typename VT<R>::T *tile, int m, uint64_t base, const Tile
     using T = typename VT<R>::T;
     if ((base & op.ectrl) != op.ectrl) return;
     const T *mat = pool + op.mat;
-    if (op.kind == TOP_DENSE) {
+    if (op.kind == TOP_DENSE_MFMA) {
+        const R *W = reinterpret_cast<const R *>(mat);
+        switch (op.k) {
+        case 3: lds_dense_mfma<R, 3>(tile, m, op, W); break;
+        case 4: lds_dense_mfma<R, 4>(tile, m, op, W); break;
+        case 5: lds_dense_mfma<R, 5>(tile, m, op, W); break;
+        }
+    } else if (op.kind == TOP_DENSE) {
         switch (op.k) {
         case 1: lds_dense<R, 1>(tile, m, op, mat); break;
         case 2: lds_dense<R, 2>(tile, m, op, mat); break;

@@ -69,6 +69,18 @@ dev::TileOp lds_form(const Op &op, const int *li, std::vector<double> &mats) {
             t.srcoff[r] = t.loff[op.perm[r]];
             push(mats, op.U[r]);
         }
+    } else if (op.k >= 3) {
+        // matrix cores: real embedding W = [[Re U, -Im U], [Im U, Re U]]
+        t.kind = dev::TOP_DENSE_MFMA;
+        const int D = 1 << op.k;
+        for (int i = 0; i < 2 * D; ++i)
+            for (int j = 0; j < 2 * D; ++j) {
+                const cd u = op.U[(size_t)(i % D) * D + (j % D)];
+                double w;
+                if (i < D) w = (j < D) ? u.real() : -u.imag();
+                else w = (j < D) ? u.imag() : u.real();
+                mats.push_back(w);
+            }
     } else {
         for (const cd &v : op.U) push(mats, v);
     }
@@ -77,7 +89,8 @@ dev::TileOp lds_form(const Op &op, const int *li, std::vector<double> &mats) {
 
 double lds_flops(const dev::TileOp &t) {
     const double frac = 1.0 / (double)(1ull << __builtin_popcount(t.lctrl));
-    if (t.kind == dev::TOP_DENSE) return frac * (8.0 * (1 << t.k) - 2.0);
+    if (t.kind == dev::TOP_DENSE || t.kind == dev::TOP_DENSE_MFMA)
+        return frac * (8.0 * (1 << t.k) - 2.0);
     return frac * 6.0 * __builtin_popcount(t.touch) / (double)(1 << t.k);
 }
 
