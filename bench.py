@@ -136,6 +136,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-legs", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 4 GiB device copy (read 4 GiB, write 4 GiB), the "
+                         "reference for scaling profiler byte counters")
+    ap.add_argument("--fp32-k-max", type=int, default=2)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -147,6 +151,13 @@ def main():
     import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.empty(1 << 29, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     n = args.qubits
     circ = W.config1_random(n=n)
@@ -176,7 +187,7 @@ def main():
 
     extra = {}
     if not args.no_extra_legs:
-        leg32 = run_leg(circ, ham, u, steps, 1, "c64", args.mode, args.k_max, 0)
+        leg32 = run_leg(circ, ham, u, steps, 1, "c64", args.mode, args.fp32_k_max, 0)
         ms32, l32, b32 = leg32["ktimes"]["tile"]
         extra["fp32_fused"] = {
             "value": leg32["updates_per_step"] * steps / leg32["wall_s"],

@@ -144,6 +144,41 @@ __device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const T *__res
     }
 }
 
+// Layout change through an LDS buffer of half a tile.  Slot J holds the same
+// tile bit (local mask lbit_o[J] == lbit_n[J]) before and after; the buffer is
+// indexed by the local index with that bit removed.  In phase p every thread
+// writes its registers whose slot-J bit is p, then reads the same register
+// indices in the new layout, so no register is overwritten before it was
+// written out.
+template <typename R, typename T, int NR, int RB, int J>
+__device__ __forceinline__ void remap_half(T *amp, T *lds, uint32_t lthr_o, const uint32_t *lbit_o,
+                                           uint32_t lthr_n, const uint32_t *lbit_n) {
+    const uint32_t lowm = lbit_o[J] - 1;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (((i >> J) & 1) != p) continue;
+            uint32_t l = lthr_o;
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+                if ((i >> j) & 1) l |= lbit_o[j];
+            lds[swz<R>(((l >> 1) & ~lowm) | (l & lowm))] = amp[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (((i >> J) & 1) != p) continue;
+            uint32_t l = lthr_n;
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+                if ((i >> j) & 1) l |= lbit_n[j];
+            amp[i] = lds[swz<R>(((l >> 1) & ~lowm) | (l & lowm))];
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T, int NR, int RB, bool CTRL>
 __device__ __forceinline__ void dispatch_g1(T *amp, int j, const T *U, uint64_t gb,
                                             const uint64_t *gbit, uint64_t ctrl) {
@@ -234,41 +269,42 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
         } else if (kind == ROP_DIAG) {
             reg_diag<T, NR, RB>(amp, op, pool, gb, gbit);
         } else {
-            // REMAP: the tile goes through LDS into the new layout
-            uint32_t lreg[NR];
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                uint32_t l = 0;
-#pragma unroll
-                for (int j = 0; j < RB; ++j)
-                    if ((i >> j) & 1) l |= lbit[j];
-                lreg[i] = l;
-            }
-#pragma unroll
-            for (int i = 0; i < NR; ++i) lds[swz<R>(lthr | lreg[i])] = amp[i];
-            __syncthreads();
-            lthr = 0;
-            gthr = 0;
+            // REMAP: the tile goes through LDS into the new layout, half at a
+            // time: register slot op.a holds the same tile bit in both layouts,
+            // so phase p moves exactly the registers whose slot bit is p.
+            uint32_t lbit_n[RB];
+            uint64_t gbit_n[RB];
+            uint32_t lthr_n = 0;
+            uint64_t gthr_n = 0;
 #pragma unroll
             for (int j = 0; j < RB; ++j) {
-                lbit[j] = 1u << op.reg_lbit[j];
-                gbit[j] = 1ull << ta.tpos[op.reg_lbit[j]];
+                lbit_n[j] = 1u << op.reg_lbit[j];
+                gbit_n[j] = 1ull << ta.tpos[op.reg_lbit[j]];
             }
 #pragma unroll
             for (int i = 0; i < TB; ++i)
                 if ((tid >> i) & 1) {
-                    lthr |= 1u << op.thr_lbit[i];
-                    gthr |= 1ull << ta.tpos[op.thr_lbit[i]];
+                    lthr_n |= 1u << op.thr_lbit[i];
+                    gthr_n |= 1ull << ta.tpos[op.thr_lbit[i]];
                 }
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                uint32_t l = 0;
-#pragma unroll
-                for (int j = 0; j < RB; ++j)
-                    if ((i >> j) & 1) l |= lbit[j];
-                amp[i] = lds[swz<R>(lthr | l)];
+            switch (op.a) {
+            case 0: remap_half<R, T, NR, RB, 0>(amp, lds, lthr, lbit, lthr_n, lbit_n); break;
+            case 1: remap_half<R, T, NR, RB, 1>(amp, lds, lthr, lbit, lthr_n, lbit_n); break;
+            case 2: remap_half<R, T, NR, RB, 2>(amp, lds, lthr, lbit, lthr_n, lbit_n); break;
+            case 3:
+                if constexpr (RB > 3) remap_half<R, T, NR, RB, 3>(amp, lds, lthr, lbit, lthr_n, lbit_n);
+                break;
+            case 4:
+                if constexpr (RB > 4) remap_half<R, T, NR, RB, 4>(amp, lds, lthr, lbit, lthr_n, lbit_n);
+                break;
             }
-            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < RB; ++j) {
+                lbit[j] = lbit_n[j];
+                gbit[j] = gbit_n[j];
+            }
+            lthr = lthr_n;
+            gthr = gthr_n;
         }
     }
 #pragma unroll
@@ -311,7 +347,7 @@ static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
                                const void *pool, hipStream_t s) {
     using T = typename VT<R>::T;
     static bool attr = false;
-    const size_t lds = sizeof(T) << (RB + TB);
+    const size_t lds = sizeof(T) << (RB + TB - 1);   // half a tile (two-phase remaps)
     if (!attr) {
         hipError_t e = set_lds_attr(k_tile_reg<R, RB, TB>, lds);
         if (e != hipSuccess) return e;

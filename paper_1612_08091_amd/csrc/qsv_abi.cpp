@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -115,7 +116,20 @@ qsv_status hip_fail(qsv_sim *s, hipError_t e, const char *where) {
         (s)->err.clear();                                                         \
     } while (0)
 
-int default_tile_bits(int dtype) { return dtype == QSV_C128 ? 12 : 13; }
+// 4096-amplitude tiles (256 threads x 16 amplitudes) for both dtypes: 32 KiB
+// (complex128) or 16 KiB (complex64) of LDS for the two-phase remaps.
+int default_tile_bits(int) { return 12; }
+
+// QSV_LOG environment variable: 0 silent (default), 1 flush summaries,
+// 2 one line per planned pass, on stderr.
+int log_level() {
+    static int lvl = -1;
+    if (lvl < 0) {
+        const char *e = std::getenv("QSV_LOG");
+        lvl = e ? std::atoi(e) : 0;
+    }
+    return lvl;
+}
 
 // ------------------------------------------------------------- device memory
 qsv_status ensure_capacity(qsv_sim *s, int nq) {
@@ -399,6 +413,10 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         }
         tend(s, tok, QSV_K_TILE, 2.0 * (double)s->dim() * s->elem());
         account(s, (double)s->dim(), pg.flops_per_amp);
+        if (log_level() >= 2)
+            std::fprintf(stderr, "qsv: pass %zu tile=%#llx m=%d %s ops=%zu remaps=%d flop/amp=%.0f\n",
+                         pi, (unsigned long long)pg.tile, pg.m, pg.reg ? "reg" : "lds",
+                         pg.reg ? nr - pg.remaps : nl, pg.remaps, pg.flops_per_amp);
         s->stats_remaps += pg.remaps;
         ro += nr;
         lo += nl;

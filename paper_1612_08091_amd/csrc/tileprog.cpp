@@ -191,9 +191,30 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
             });
             for (int c = 0; c < (int)cand.size() && __builtin_popcount(Sn) < rb; ++c)
                 Sn |= 1u << cand[c];
+            // The two-phase remap needs one tile bit that stays in its register
+            // slot: keep the old register bit used soonest if none survived.
+            if ((Sn & S) == 0) {
+                int keep = -1, drop = -1;
+                for (int b = 0; b < m; ++b)
+                    if (((S >> b) & 1) && (keep < 0 || next_use[b] < next_use[keep])) keep = b;
+                for (int b = 0; b < m; ++b)
+                    if (((Sn >> b) & 1) && !((it.need >> b) & 1) &&
+                        (drop < 0 || next_use[b] > next_use[drop]))
+                        drop = b;
+                Sn = (Sn & ~(1u << drop)) | (1u << keep);
+            }
+            int split = -1;   // slot of the surviving bit (soonest used)
+            for (int j = 0; j < rb; ++j)
+                if (((Sn >> cur_reg[j]) & 1) &&
+                    (split < 0 || next_use[cur_reg[j]] < next_use[cur_reg[split]]))
+                    split = j;
             dev::RegOp r{};
             r.kind = dev::ROP_REMAP;
+            r.a = split;
             set_layout(Sn, m, rb, r.reg_lbit, r.thr_lbit);
+            // put the surviving bit back into its slot
+            for (int j = 0; j < rb; ++j)
+                if (r.reg_lbit[j] == cur_reg[split]) std::swap(r.reg_lbit[j], r.reg_lbit[split]);
             std::memcpy(cur_reg, r.reg_lbit, 8);
             prog.rops.push_back(r);
             prog.remaps += 1;
