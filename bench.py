@@ -102,6 +102,92 @@ def run_leg(circ, ham, u, steps, warmup, dtype, mode, k_max, tile_bits, timing=T
             "updates_per_step": len(circ.gates) * float(1 << n)}
 
 
+def _timed_circuit(sim, circ):
+    import torch
+    sim.reset()
+    sim.run(circ)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.flush()
+    sim.synchronize()
+    return time.perf_counter() - t0
+
+
+def form_precision(samples: int = 1 << 20):
+    """32-qubit Haar + CZ brick circuit (1900 gates): complex64 state with fused
+    passes versus the same circuit in complex128; the FP32 error is measured on
+    a seeded sample of amplitudes (normwise relative error over the sample)."""
+    import workloads as W
+    from paper_1612_08091_amd import qsv as Q
+    circ = W.config2()
+    idx = np.sort(np.random.default_rng(W.SEED_BASE + 2).integers(0, 1 << 32, size=samples,
+                                                                   dtype=np.uint64))
+    out = {"workload": "config 2: 32-qubit Haar + CZ brick, 40 layers, 1900 gates"}
+    amps = {}
+    for dtype in ("c64", "c128"):
+        sim = Q.Simulator(n_max=32, dtype=dtype, mode="tiled", k_max=2, timing=True)
+        sim.allocate(32)
+        _timed_circuit(sim, circ)                  # allocation + warm-up
+        sim.reset_stats()
+        t = _timed_circuit(sim, circ)
+        st = sim.stats()
+        tile_ms, tile_n, _ = sim.kernel_times()["tile"]
+        amps[dtype] = sim.get_amplitudes(idx)
+        out[dtype] = {"s_per_circuit": t,
+                      "amp_gate_per_s": len(circ.gates) * float(1 << 32) / t,
+                      "pct_hbm_peak": st["alg_bytes"] / t / HBM_PEAK,
+                      "passes": st["passes"], "tile_avg_ms": tile_ms / max(tile_n, 1),
+                      "norm2_drift": abs(sim.norm2() - 1.0)}
+        sim.close()
+    d = amps["c64"] - amps["c128"]
+    out["fp32_rel_err_sampled"] = float(np.linalg.norm(d) / np.linalg.norm(amps["c128"]))
+    out["samples"] = samples
+    return out
+
+
+def form_batched():
+    """Config 3: 4096 HEA circuits (8..20 qubits, depth 6) with 64-term Pauli
+    sums, complex64, one persistent graph-captured launch per evaluation."""
+    import workloads as W
+    from paper_1612_08091_amd import qsv as Q
+    t0 = time.perf_counter()
+    circuits, hams = W.config3()
+    b = Q.Batch(circuits, hams, dtype="c64", autotune=True, use_graph=True)
+    setup = time.perf_counter() - t0
+    b.run()
+    times = []
+    for _ in range(5):
+        t1 = time.perf_counter()
+        b.run()
+        times.append(time.perf_counter() - t1)
+    info = b.info()
+    b.close()
+    best = min(times)
+    return {"workload": "config 3: 4096 circuits, n ~ U{8..20}, 64-term <H> each",
+            "circuits_per_s": len(circuits) / best, "s_per_batch": best,
+            "device_ms": info["last_ms"], "tile_bits": info["tile_bits"], "k_fuse": info["k_fuse"],
+            "setup_s_incl_autotune": setup}
+
+
+def form_adjoint():
+    """Config 4: 24-qubit HEA (480 angles), 200-term Pauli sum: <H> and the full
+    gradient by the adjoint method, complex128."""
+    import workloads as W
+    from paper_1612_08091_amd import qsv as Q
+    circ, ham = W.config4()
+    sim = Q.Simulator(n_max=24, dtype="c128", mode="tiled", k_max=2)
+    Q.adjoint_gradient(sim, circ, ham)
+    times = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        val, grad = Q.adjoint_gradient(sim, circ, ham)
+        times.append(time.perf_counter() - t1)
+    sim.close()
+    return {"workload": "config 4: 24-qubit HEA, 480 angles, 200 Pauli terms",
+            "s_per_value_and_gradient": min(times), "energy": val,
+            "grad_norm": float(np.linalg.norm(grad))}
+
+
 def cpu_baseline(circ, budget_s=15.0):
     """The oracle applying the first gates of the same 30-qubit circuit, one
     at a time, until about budget_s seconds of work (single thread)."""
@@ -140,6 +226,8 @@ def main():
                     help="first run a plain 4 GiB device copy (read 4 GiB, write 4 GiB), the "
                          "reference for scaling profiler byte counters")
     ap.add_argument("--fp32-k-max", type=int, default=2)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the 32-qubit precision, batched and adjoint forms")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -182,8 +270,17 @@ def main():
     achieved = per_launch_bytes / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK, "traffic": None,
-                "kernel": "k_tile<double>" if dom == "tile" else "k_dense<double,1>",
+                "kernel": ("k_tile_reg<double,%d,8>" % (args.reg_bits or 4)) if dom == "tile"
+                          else "k_dense<double,1>",
                 "launches": launches, "avg_ms": avg_ms, "alg_bytes_per_launch": per_launch_bytes}
+    if dom == "tile" and avg_ms > 0:
+        # the same launches against the FP64 arithmetic peak (the pass's
+        # arithmetic intensity sits close to the FP64 ridge point)
+        fl = st["alg_flops"] / max(launches, 1)
+        roofline["fp64_alu"] = {"achieved_TFLOPs": fl / (avg_ms * 1e-3) / 1e12,
+                                "peak_TFLOPs": FP64_PEAK / 1e12,
+                                "frac": fl / (avg_ms * 1e-3) / FP64_PEAK,
+                                "alg_flops_per_launch": fl}
 
     extra = {}
     if not args.no_extra_legs:
@@ -209,6 +306,13 @@ def main():
             "pct_hbm_peak": pg["stats"]["alg_bytes"] / (pg["ms_per_step"] * 1e-3) / HBM_PEAK,
         }
         log("per-gate leg: %.2f ms/step" % pg["ms_per_step"])
+    if not args.no_forms:
+        extra["precision_32q"] = form_precision()
+        log("precision form done")
+        extra["batched"] = form_batched()
+        log("batched form done")
+        extra["adjoint_24q"] = form_adjoint()
+        log("adjoint form done")
 
     cpu = None
     if not args.no_cpu_baseline:

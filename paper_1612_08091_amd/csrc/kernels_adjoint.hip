@@ -4,6 +4,8 @@
 // Im<phi|P|psi> and applies the inverse rotation to psi and phi in one pass.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 
 namespace qsv {
@@ -43,30 +45,31 @@ __global__ __launch_bounds__(kAT) void k_ham_apply(const typename VA<R>::T *__re
                                                    const uint64_t *__restrict__ zm,
                                                    const double *__restrict__ cf,
                                                    const int32_t *__restrict__ ny) {
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= dim) return;
-    double ar = 0.0, ai = 0.0;
-    for (int t = 0; t < nterms; ++t) {
-        const uint64_t i = j ^ xm[t];
-        const auto a = psi[i];
-        double vr = a.x, vi = a.y;
-        if (__popcll(i & zm[t]) & 1) {
-            vr = -vr;
-            vi = -vi;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < dim;
+         j += (uint64_t)gridDim.x * blockDim.x) {
+        double ar = 0.0, ai = 0.0;
+        for (int t = 0; t < nterms; ++t) {
+            const uint64_t i = j ^ xm[t];
+            const auto a = psi[i];
+            double vr = a.x, vi = a.y;
+            if (__popcll(i & zm[t]) & 1) {
+                vr = -vr;
+                vi = -vi;
+            }
+            switch (ny[t] & 3) {   // multiply by i^{ny}
+            case 1: { const double tmp = vr; vr = -vi; vi = tmp; } break;
+            case 2: vr = -vr; vi = -vi; break;
+            case 3: { const double tmp = vr; vr = vi; vi = -tmp; } break;
+            default: break;
+            }
+            ar += cf[t] * vr;
+            ai += cf[t] * vi;
         }
-        switch (ny[t] & 3) {   // multiply by i^{ny}
-        case 1: { const double tmp = vr; vr = -vi; vi = tmp; } break;
-        case 2: vr = -vr; vi = -vi; break;
-        case 3: { const double tmp = vr; vr = vi; vi = -tmp; } break;
-        default: break;
-        }
-        ar += cf[t] * vr;
-        ai += cf[t] * vi;
+        typename VA<R>::T o;
+        o.x = (R)ar;
+        o.y = (R)ai;
+        phi[j] = o;
     }
-    typename VA<R>::T o;
-    o.x = (R)ar;
-    o.y = (R)ai;
-    phi[j] = o;
 }
 
 template <typename R>
@@ -189,7 +192,7 @@ int adjoint_blocks(uint64_t npairs) { return (int)adj_grid(npairs); }
 hipError_t ham_apply(int dtype, const void *psi, void *phi, uint64_t dim, int nterms,
                      const uint64_t *x, const uint64_t *z, const double *c, const int32_t *ny,
                      hipStream_t s) {
-    const dim3 g((unsigned)((dim + kAT - 1) / kAT));
+    const dim3 g((unsigned)std::min<uint64_t>((dim + kAT - 1) / kAT, 1ull << 20));
     if (dtype == 0)
         hipLaunchKernelGGL(k_ham_apply<double>, g, dim3(kAT), 0, s, (const double2 *)psi,
                            (double2 *)phi, dim, nterms, x, z, c, ny);

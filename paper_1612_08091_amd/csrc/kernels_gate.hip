@@ -46,25 +46,26 @@ __global__ __launch_bounds__(256) void k_dense(typename V2<R>::T *__restrict__ p
                                                DenseArgsT<R, (1 << K)> a) {
     using T = typename V2<R>::T;
     constexpr int D = 1 << K;
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ngroups) return;
-    const uint64_t base = expand_index(g, ia);
-    T x[D];
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t base = expand_index(g, ia);
+        T x[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) x[c] = psi[base + a.off[c]];
+        for (int c = 0; c < D; ++c) x[c] = psi[base + a.off[c]];
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
-        R yr = 0, yi = 0;
+        for (int r = 0; r < D; ++r) {
+            R yr = 0, yi = 0;
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            const R mr = a.mr[r * D + c], mi = a.mi[r * D + c];
-            yr += mr * x[c].x - mi * x[c].y;
-            yi += mr * x[c].y + mi * x[c].x;
+            for (int c = 0; c < D; ++c) {
+                const R mr = a.mr[r * D + c], mi = a.mi[r * D + c];
+                yr += mr * x[c].x - mi * x[c].y;
+                yi += mr * x[c].y + mi * x[c].x;
+            }
+            T y;
+            y.x = yr;
+            y.y = yi;
+            psi[base + a.off[r]] = y;
         }
-        T y;
-        y.x = yr;
-        y.y = yi;
-        psi[base + a.off[r]] = y;
     }
 }
 
@@ -73,25 +74,29 @@ __global__ __launch_bounds__(256) void k_mono(typename V2<R>::T *__restrict__ ps
                                               uint64_t ngroups, IndexArgs ia, MonoArgsT<R> a) {
     using T = typename V2<R>::T;
     constexpr int D = 1 << K;
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ngroups) return;
-    const uint64_t base = expand_index(g, ia);
-    T y[D];
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t base = expand_index(g, ia);
+        T y[D];
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
-        if ((a.touch >> r) & 1) {
-            const T s = psi[base + a.srcoff[r]];
-            y[r].x = a.vr[r] * s.x - a.vi[r] * s.y;
-            y[r].y = a.vr[r] * s.y + a.vi[r] * s.x;
+        for (int r = 0; r < D; ++r) {
+            if ((a.touch >> r) & 1) {
+                const T s = psi[base + a.srcoff[r]];
+                y[r].x = a.vr[r] * s.x - a.vi[r] * s.y;
+                y[r].y = a.vr[r] * s.y + a.vi[r] * s.x;
+            }
         }
-    }
 #pragma unroll
-    for (int r = 0; r < D; ++r)
-        if ((a.touch >> r) & 1) psi[base + a.off[r]] = y[r];
+        for (int r = 0; r < D; ++r)
+            if ((a.touch >> r) & 1) psi[base + a.off[r]] = y[r];
+    }
 }
 
+// The per-gate kernels stride over their groups; 2^20 blocks of 256 keep the
+// launch far below 2^32 threads at any state size.
 static inline unsigned grid_for(uint64_t work, unsigned block) {
-    return (unsigned)((work + block - 1) / block);
+    const uint64_t b = (work + block - 1) / block;
+    return (unsigned)(b > (1ull << 20) ? (1ull << 20) : b);
 }
 
 template <typename R, int K>

@@ -4,6 +4,8 @@
 // is accumulated in double precision whatever the state's dtype.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 
 namespace qsv {
@@ -131,14 +133,15 @@ hipError_t prob_split(int dtype, const void *psi, int nq, int q, double *ws, dou
 
 template <typename R>
 __global__ void k_probs(const typename V2r<R>::T *psi, uint64_t dim, double *out) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= dim) return;
-    const auto a = psi[i];
-    out[i] = (double)a.x * a.x + (double)a.y * a.y;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const auto a = psi[i];
+        out[i] = (double)a.x * a.x + (double)a.y * a.y;
+    }
 }
 
 hipError_t probs(int dtype, const void *psi, uint64_t dim, double *out_dev, hipStream_t s) {
-    const unsigned g = (unsigned)((dim + 255) / 256);
+    const unsigned g = (unsigned)std::min<uint64_t>((dim + 255) / 256, 1ull << 20);
     if (dtype == 0)
         hipLaunchKernelGGL(k_probs<double>, dim3(g), dim3(256), 0, s, (const double2 *)psi, dim,
                            out_dev);
@@ -493,73 +496,86 @@ hipError_t sample(int dtype, const void *psi, int nq, int shots, const double *u
 // ------------------------------------------------------------ state ops
 template <typename R>
 __global__ void k_fill_basis0(typename V2r<R>::T *psi, uint64_t dim) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= dim) return;
-    typename V2r<R>::T v;
-    v.x = (i == 0) ? R(1) : R(0);
-    v.y = R(0);
-    psi[i] = v;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        typename V2r<R>::T v;
+        v.x = (i == 0) ? R(1) : R(0);
+        v.y = R(0);
+        psi[i] = v;
+    }
 }
 
 template <typename R>
 __global__ void k_zero(typename V2r<R>::T *psi, uint64_t from, uint64_t to) {
-    const uint64_t i = from + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= to) return;
-    typename V2r<R>::T v;
-    v.x = R(0);
-    v.y = R(0);
-    psi[i] = v;
+    for (uint64_t i = from + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < to;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        typename V2r<R>::T v;
+        v.x = R(0);
+        v.y = R(0);
+        psi[i] = v;
+    }
 }
 
 template <typename R>
 __global__ void k_compact(const typename V2r<R>::T *src, typename V2r<R>::T *dst, uint64_t half,
                           int q, int value) {
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= half) return;
     const uint64_t lowm = (1ull << q) - 1;
-    const uint64_t i = ((j & ~lowm) << 1) | (j & lowm) | ((uint64_t)value << q);
-    dst[j] = src[i];
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < half;
+         j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = ((j & ~lowm) << 1) | (j & lowm) | ((uint64_t)value << q);
+        dst[j] = src[i];
+    }
 }
 
 template <typename R>
 __global__ void k_collapse(typename V2r<R>::T *psi, uint64_t dim, int q, int outcome,
                            double scale) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= dim) return;
-    auto a = psi[i];
-    if ((int)((i >> q) & 1) == outcome) {
-        a.x = (R)((double)a.x * scale);
-        a.y = (R)((double)a.y * scale);
-    } else {
-        a.x = R(0);
-        a.y = R(0);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        auto a = psi[i];
+        if ((int)((i >> q) & 1) == outcome) {
+            a.x = (R)((double)a.x * scale);
+            a.y = (R)((double)a.y * scale);
+        } else {
+            a.x = R(0);
+            a.y = R(0);
+        }
+        psi[i] = a;
     }
-    psi[i] = a;
 }
 
 template <typename R>
 __global__ void k_gather(const typename V2r<R>::T *psi, const uint64_t *idx, uint64_t count,
                          double *out) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const auto a = psi[idx[i]];
-    out[2 * i] = (double)a.x;
-    out[2 * i + 1] = (double)a.y;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const auto a = psi[idx[i]];
+        out[2 * i] = (double)a.x;
+        out[2 * i + 1] = (double)a.y;
+    }
 }
 
 template <typename RS, typename RD>
 __global__ void k_convert(const typename V2r<RS>::T *src, typename V2r<RD>::T *dst,
                           uint64_t dim) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= dim) return;
-    const auto a = src[i];
-    typename V2r<RD>::T b;
-    b.x = (RD)a.x;
-    b.y = (RD)a.y;
-    dst[i] = b;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const auto a = src[i];
+        typename V2r<RD>::T b;
+        b.x = (RD)a.x;
+        b.y = (RD)a.y;
+        dst[i] = b;
+    }
 }
 
-static dim3 g1(uint64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+// Elementwise kernels stride over their range; the grid is capped at 2^20
+// blocks of 256 so that grid x block stays far below 2^32 threads at 2^33
+// amplitudes.
+static dim3 g1(uint64_t n) {
+    uint64_t b = (n + 255) / 256;
+    if (b > (1ull << 20)) b = 1ull << 20;
+    return dim3((unsigned)(b ? b : 1));
+}
 
 hipError_t fill_basis0(int dtype, void *psi, uint64_t dim, hipStream_t s) {
     if (dtype == 0)

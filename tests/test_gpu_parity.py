@@ -364,3 +364,49 @@ def test_brick_30q_then_inverse(mode, k_max):
     amp = s.get_amplitudes([0, 1, 12345])
     assert abs(amp[0] - 1.0) <= 1e-10 and np.max(np.abs(amp[1:])) <= 1e-10
     s.close()
+
+
+# ------------------------------------------------------------- full size, 32 q
+def test_qft_32q_c64_sampled_closed_form():
+    """2^32 amplitudes (complex64, 32 GiB): every launch strides past 2^32
+    threads' worth of work.  QFT of a basis state against its closed form."""
+    n = 32
+    x = int(np.random.default_rng(32).integers(0, 1 << n))
+    log("case qft32 c64 x=%d" % x)
+    s = make(n, mode="tiled", k_max=2, dtype="c64")
+    s.run(W.basis_prep(n, x))
+    s.run(W.qft(n))
+    rng = np.random.default_rng(23)
+    idx = rng.integers(0, 1 << n, size=4096, dtype=np.uint64)
+    idx[:4] = [0, 1, (1 << n) - 1, 1 << (n - 1)]
+    got = s.get_amplitudes(idx)
+    ph = np.array([float((x * int(v)) % (1 << n)) for v in idx.astype(object)]) / (1 << n)
+    want = np.exp(2j * math.pi * ph) / (2 ** (n / 2))
+    check_c64(got, want)
+    assert abs(s.norm2() - 1.0) <= 1e-5
+    s.close()
+
+
+def test_config2_32q_c64_then_inverse_and_measure():
+    """The 32-qubit brick circuit and its inverse return |0...0> (within FP32
+    rounding of 3800 gates); then a GHZ state is measured and collapsed."""
+    n = 32
+    circ = W.config2(n)
+    log("case config2 32q inverse", len(circ.gates))
+    s = make(n, mode="tiled", k_max=2, dtype="c64")
+    s.run(circ)
+    assert abs(s.norm2() - 1.0) <= 1e-4
+    for g in reversed(circ.gates):
+        s.apply(g.matrix.conj().T, g.targets, g.controls)
+    amp = s.get_amplitudes([0, 1, (1 << n) - 1, 123456789])
+    assert abs(amp[0] - 1.0) <= 1e-4 and np.max(np.abs(amp[1:])) <= 1e-4
+    log("case ghz32 measure")
+    s.reset()
+    s.run(W.ghz(n))
+    assert abs(s.get_probability([n - 1], [1]) - 0.5) <= 1e-6
+    out = s.measure([n - 1], [0.75])
+    want = 1 if 0.75 * 1.0 >= 0.5 else 0
+    assert list(out) == [want]
+    amp = s.get_amplitudes([0, (1 << n) - 1])
+    assert abs(abs(amp[want]) - 1.0) <= 1e-6 and abs(amp[1 - want]) == 0.0
+    s.close()
