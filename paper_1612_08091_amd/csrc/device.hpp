@@ -64,7 +64,10 @@ struct TileArgs {
     uint8_t reg_lbit[8];  // register kernel: initial layout, tile bit of register bit j
     uint8_t thr_lbit[16]; //                  tile bit of thread-id bit i
     int32_t rb;           // register bits per thread (threads = 2^(m - rb))
-    int32_t pad;
+    uint32_t pad;
+    uint64_t g_reg[8];    // register kernel, initial layout: global index bit of register
+                          // bit j, and of thread-id bit i
+    uint64_t g_thr[16];
 };
 
 // One operation of the register-resident tile kernel.
@@ -80,6 +83,17 @@ struct RegOp {
     uint8_t gt[8];        // DIAG: global target positions
     uint8_t reg_lbit[8];  // REMAP: new layout
     uint8_t thr_lbit[16];
+    // REMAP (a = register slot whose tile bit stays put): byte offsets into the
+    // half-tile LDS buffer.  The buffer address of an amplitude is a linear map
+    // (over GF(2)) of its local index, so it splits into a register part (per
+    // register, uniform) XOR a thread part (XOR of the parts of the set
+    // thread-id bits): wr/wthr in the old layout, rd/rthr in the new one.
+    uint32_t wr[32];
+    uint32_t rd[32];
+    uint32_t wthr[16];
+    uint32_t rthr[16];
+    uint64_t g_reg[8];    // new layout: global index bit of register bit j
+    uint64_t g_thr[16];   //             and of thread-id bit i
 };
 
 // ------------------------------------------------------------------ gates

@@ -329,8 +329,11 @@ __global__ __launch_bounds__(256) void k_block_sums(const typename V2r<R>::T *ps
     const int per = (1 << bbits) / 256 > 0 ? (1 << bbits) / 256 : 1;
     double acc = 0.0;
     int64_t last = -1;
+    // lanes read consecutive amplitudes (coalesced); the order of the sum
+    // need not match the in-block scan of k_sample, which settles a draw
+    // that lands past its block's rounded end on the block's last nonzero
     for (int j = 0; j < per; ++j) {
-        const uint32_t l = threadIdx.x * per + j;
+        const uint32_t l = (uint32_t)j * 256u + threadIdx.x;
         if (l >= (1u << bbits)) break;
         const auto a = psi[b0 + l];
         const double p = (double)a.x * a.x + (double)a.y * a.y;

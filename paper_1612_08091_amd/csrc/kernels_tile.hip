@@ -145,35 +145,26 @@ __device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const T *__res
 }
 
 // Layout change through an LDS buffer of half a tile.  Slot J holds the same
-// tile bit (local mask lbit_o[J] == lbit_n[J]) before and after; the buffer is
-// indexed by the local index with that bit removed.  In phase p every thread
-// writes its registers whose slot-J bit is p, then reads the same register
-// indices in the new layout, so no register is overwritten before it was
-// written out.
-template <typename R, typename T, int NR, int RB, int J>
-__device__ __forceinline__ void remap_half(T *amp, T *lds, uint32_t lthr_o, const uint32_t *lbit_o,
-                                           uint32_t lthr_n, const uint32_t *lbit_n) {
-    const uint32_t lowm = lbit_o[J] - 1;
+// tile bit before and after, and the buffer drops that bit from the index.
+// In phase p every thread writes its registers whose slot-J bit is p, then
+// reads the same register indices in the new layout, so no register is
+// overwritten before it was written out.  Addresses are the thread part XOR
+// the (uniform) register part, both precomputed on the host.
+template <typename T, int NR, int J>
+__device__ __forceinline__ void remap_half(T *amp, unsigned char *lds, uint32_t wt, uint32_t rt,
+                                           const RegOp &op) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             if (((i >> J) & 1) != p) continue;
-            uint32_t l = lthr_o;
-#pragma unroll
-            for (int j = 0; j < RB; ++j)
-                if ((i >> j) & 1) l |= lbit_o[j];
-            lds[swz<R>(((l >> 1) & ~lowm) | (l & lowm))] = amp[i];
+            *reinterpret_cast<T *>(lds + (wt ^ op.wr[i])) = amp[i];
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             if (((i >> J) & 1) != p) continue;
-            uint32_t l = lthr_n;
-#pragma unroll
-            for (int j = 0; j < RB; ++j)
-                if ((i >> j) & 1) l |= lbit_n[j];
-            amp[i] = lds[swz<R>(((l >> 1) & ~lowm) | (l & lowm))];
+            amp[i] = *reinterpret_cast<const T *>(lds + (rt ^ op.rd[i]));
         }
         __syncthreads();
     }
@@ -188,10 +179,13 @@ __device__ __forceinline__ void dispatch_g1(T *amp, int j, const T *U, uint64_t 
     case 2: reg_g1<T, NR, RB, 2, CTRL>(amp, U, gb, gbit, ctrl); break;
     case 3:
         if constexpr (RB > 3) reg_g1<T, NR, RB, 3, CTRL>(amp, U, gb, gbit, ctrl);
+        else __builtin_unreachable();
         break;
     case 4:
         if constexpr (RB > 4) reg_g1<T, NR, RB, 4, CTRL>(amp, U, gb, gbit, ctrl);
+        else __builtin_unreachable();
         break;
+    default: __builtin_unreachable();   // the host emits only valid slots
     }
 }
 
@@ -203,11 +197,19 @@ __device__ __forceinline__ void dispatch_g2(T *amp, int a, int b, const T *U, ui
     switch (a * 8 + b) {
         QSV_G2(0, 1) QSV_G2(0, 2) QSV_G2(1, 2)
     default:
-        if constexpr (RB > 3) {
-            switch (a * 8 + b) { QSV_G2(0, 3) QSV_G2(1, 3) QSV_G2(2, 3) }
-        }
-        if constexpr (RB > 4) {
-            switch (a * 8 + b) { QSV_G2(0, 4) QSV_G2(1, 4) QSV_G2(2, 4) QSV_G2(3, 4) }
+        if constexpr (RB == 4) {
+            switch (a * 8 + b) {
+                QSV_G2(0, 3) QSV_G2(1, 3) QSV_G2(2, 3)
+            default: __builtin_unreachable();
+            }
+        } else if constexpr (RB == 5) {
+            switch (a * 8 + b) {
+                QSV_G2(0, 3) QSV_G2(1, 3) QSV_G2(2, 3) QSV_G2(0, 4) QSV_G2(1, 4) QSV_G2(2, 4)
+                QSV_G2(3, 4)
+            default: __builtin_unreachable();
+            }
+        } else {
+            __builtin_unreachable();
         }
         break;
     }
@@ -222,7 +224,6 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
     constexpr int NR = 1 << RB;
     constexpr int m = RB + TB;
     extern __shared__ unsigned char smem_raw[];
-    T *lds = reinterpret_cast<T *>(smem_raw);
     uint64_t base = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
 #pragma unroll
     for (int i = 0; i < m; ++i) {
@@ -230,24 +231,14 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
         base = ((base & ~lowm) << 1) | (base & lowm);
     }
     const uint32_t tid = threadIdx.x;
-    // current layout
-    uint32_t lbit[RB];
+    // current layout: global index bit of each register bit (uniform) and
+    // the global bits of this thread
     uint64_t gbit[RB];
-    uint32_t lthr = 0;
+#pragma unroll
+    for (int j = 0; j < RB; ++j) gbit[j] = ta.g_reg[j];
     uint64_t gthr = 0;
-    {
 #pragma unroll
-        for (int j = 0; j < RB; ++j) {
-            lbit[j] = 1u << ta.reg_lbit[j];
-            gbit[j] = 1ull << ta.tpos[ta.reg_lbit[j]];
-        }
-#pragma unroll
-        for (int i = 0; i < TB; ++i)
-            if ((tid >> i) & 1) {
-                lthr |= 1u << ta.thr_lbit[i];
-                gthr |= 1ull << ta.tpos[ta.thr_lbit[i]];
-            }
-    }
+    for (int t = 0; t < TB; ++t) gthr |= (0ull - ((tid >> t) & 1u)) & ta.g_thr[t];
     T amp[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) amp[i] = psi[base | gthr | greg<T, NR, RB>(i, gbit)];
@@ -269,41 +260,36 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
         } else if (kind == ROP_DIAG) {
             reg_diag<T, NR, RB>(amp, op, pool, gb, gbit);
         } else {
-            // REMAP: the tile goes through LDS into the new layout, half at a
-            // time: register slot op.a holds the same tile bit in both layouts,
-            // so phase p moves exactly the registers whose slot bit is p.
-            uint32_t lbit_n[RB];
-            uint64_t gbit_n[RB];
-            uint32_t lthr_n = 0;
+            // REMAP into the layout the op describes
+            // thread parts from the thread-id bits; the empty asm makes the
+            // id opaque so the per-bit masks are not kept live across the loop
+            uint32_t tr = tid;
+            asm volatile("" : "+v"(tr));
+            uint32_t wt = 0, rt = 0;
             uint64_t gthr_n = 0;
 #pragma unroll
-            for (int j = 0; j < RB; ++j) {
-                lbit_n[j] = 1u << op.reg_lbit[j];
-                gbit_n[j] = 1ull << ta.tpos[op.reg_lbit[j]];
+            for (int t = 0; t < TB; ++t) {
+                const uint32_t msk = 0u - ((tr >> t) & 1u);
+                wt ^= msk & op.wthr[t];
+                rt ^= msk & op.rthr[t];
+                gthr_n |= (((uint64_t)msk << 32) | msk) & op.g_thr[t];
             }
-#pragma unroll
-            for (int i = 0; i < TB; ++i)
-                if ((tid >> i) & 1) {
-                    lthr_n |= 1u << op.thr_lbit[i];
-                    gthr_n |= 1ull << ta.tpos[op.thr_lbit[i]];
-                }
             switch (op.a) {
-            case 0: remap_half<R, T, NR, RB, 0>(amp, lds, lthr, lbit, lthr_n, lbit_n); break;
-            case 1: remap_half<R, T, NR, RB, 1>(amp, lds, lthr, lbit, lthr_n, lbit_n); break;
-            case 2: remap_half<R, T, NR, RB, 2>(amp, lds, lthr, lbit, lthr_n, lbit_n); break;
+            case 0: remap_half<T, NR, 0>(amp, smem_raw, wt, rt, op); break;
+            case 1: remap_half<T, NR, 1>(amp, smem_raw, wt, rt, op); break;
+            case 2: remap_half<T, NR, 2>(amp, smem_raw, wt, rt, op); break;
             case 3:
-                if constexpr (RB > 3) remap_half<R, T, NR, RB, 3>(amp, lds, lthr, lbit, lthr_n, lbit_n);
+                if constexpr (RB > 3) remap_half<T, NR, 3>(amp, smem_raw, wt, rt, op);
+                else __builtin_unreachable();
                 break;
             case 4:
-                if constexpr (RB > 4) remap_half<R, T, NR, RB, 4>(amp, lds, lthr, lbit, lthr_n, lbit_n);
+                if constexpr (RB > 4) remap_half<T, NR, 4>(amp, smem_raw, wt, rt, op);
+                else __builtin_unreachable();
                 break;
+            default: __builtin_unreachable();
             }
 #pragma unroll
-            for (int j = 0; j < RB; ++j) {
-                lbit[j] = lbit_n[j];
-                gbit[j] = gbit_n[j];
-            }
-            lthr = lthr_n;
+            for (int j = 0; j < RB; ++j) gbit[j] = op.g_reg[j];
             gthr = gthr_n;
         }
     }

@@ -348,7 +348,7 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
     std::vector<qsv::TileProgram> progs(passes.size());
     size_t n_rops = 0, n_lops = 0;
     for (size_t pi = 0; pi < passes.size(); ++pi) {
-        qsv::compile_pass(passes[pi], rb, mats, progs[pi]);
+        qsv::compile_pass(passes[pi], rb, mats, progs[pi], (int)s->elem());
         n_rops += progs[pi].rops.size();
         n_lops += progs[pi].lops.size();
     }
@@ -400,6 +400,8 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         ta.n_tiles = 1ull << (nq - pg.m);
         std::memcpy(ta.reg_lbit, pg.reg_lbit, 8);
         std::memcpy(ta.thr_lbit, pg.thr_lbit, 16);
+        std::memcpy(ta.g_reg, pg.g_reg, sizeof(ta.g_reg));
+        std::memcpy(ta.g_thr, pg.g_thr, sizeof(ta.g_thr));
         ta.rb = rb;
         const int tok = tbegin(s);
         if (pg.reg) {

@@ -105,7 +105,58 @@ void set_layout(uint32_t regmask, int m, int rb, uint8_t *reg_lbit, uint8_t *thr
 
 }  // namespace
 
-void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram &prog) {
+uint32_t remap_offset(uint32_t l, int kept, int elem_bytes) {
+    const uint32_t lowm = (1u << kept) - 1;
+    const uint32_t h = ((l >> 1) & ~lowm) | (l & lowm);
+    const uint32_t x = elem_bytes == 16 ? (h ^ (((h >> 4) ^ (h >> 8)) & 15u))
+                                        : (h ^ (((h >> 5) ^ (h >> 10)) & 31u));
+    return x * (uint32_t)elem_bytes;
+}
+
+namespace {
+
+// Global-index bits and LDS byte offsets of every layout of a register
+// program (the kernel then needs no per-lane layout arithmetic).
+void fill_layouts(TileProgram &prog, int rb, int elem_bytes) {
+    uint8_t tpos[64];
+    int c = 0;
+    for (int p = 0; p < 64; ++p)
+        if ((prog.tile >> p) & 1) tpos[c++] = (uint8_t)p;
+    const int tb = prog.m - rb;
+    const int nr = 1 << rb;
+    for (int j = 0; j < rb; ++j) prog.g_reg[j] = 1ull << tpos[prog.reg_lbit[j]];
+    for (int t = 0; t < tb; ++t) prog.g_thr[t] = 1ull << tpos[prog.thr_lbit[t]];
+    uint8_t cur_reg[8], cur_thr[16];
+    std::memcpy(cur_reg, prog.reg_lbit, 8);
+    std::memcpy(cur_thr, prog.thr_lbit, 16);
+    for (dev::RegOp &r : prog.rops) {
+        if (r.kind != dev::ROP_REMAP) continue;
+        const int kept = cur_reg[r.a];
+        for (int i = 0; i < nr; ++i) {
+            uint32_t lo = 0, ln = 0;
+            for (int j = 0; j < rb; ++j)
+                if ((i >> j) & 1) {
+                    lo |= 1u << cur_reg[j];
+                    ln |= 1u << r.reg_lbit[j];
+                }
+            r.wr[i] = remap_offset(lo, kept, elem_bytes);
+            r.rd[i] = remap_offset(ln, kept, elem_bytes);
+        }
+        for (int t = 0; t < tb; ++t) {
+            r.wthr[t] = remap_offset(1u << cur_thr[t], kept, elem_bytes);
+            r.rthr[t] = remap_offset(1u << r.thr_lbit[t], kept, elem_bytes);
+            r.g_thr[t] = 1ull << tpos[r.thr_lbit[t]];
+        }
+        for (int j = 0; j < rb; ++j) r.g_reg[j] = 1ull << tpos[r.reg_lbit[j]];
+        std::memcpy(cur_reg, r.reg_lbit, 8);
+        std::memcpy(cur_thr, r.thr_lbit, 16);
+    }
+}
+
+}  // namespace
+
+void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram &prog,
+                  int elem_bytes) {
     prog = TileProgram();
     prog.tile = ps.tile;
     int li[64];
@@ -266,6 +317,7 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         }
         prog.rops.push_back(r);
     }
+    fill_layouts(prog, rb, elem_bytes);
 }
 
 }  // namespace qsv

@@ -17,6 +17,8 @@ struct TileProgram {
     std::vector<dev::TileOp> lops;      // LDS ops (all ops of an LDS-kernel pass)
     uint8_t reg_lbit[8] = {};           // initial layout (register kernel)
     uint8_t thr_lbit[16] = {};
+    uint64_t g_reg[8] = {};             // initial layout as global index bits
+    uint64_t g_thr[16] = {};
     int remaps = 0;
     double flops_per_amp = 0.0;
 };
@@ -25,8 +27,16 @@ struct TileProgram {
 // kernel).  The register kernel is used when the tile has rb + 8 bits
 // (256 threads) or rb + 9 bits (512 threads, rb <= 4).
 // Matrices are appended to `mats` as complex128 (re, im) pairs; ops refer to
-// them by complex-entry offset.
-void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram &prog);
+// them by complex-entry offset.  elem_bytes (16 or 8, the state's complex
+// type) fixes the LDS byte offsets of the remaps.
+void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram &prog,
+                  int elem_bytes = 16);
+
+// Byte offset in the half-tile remap buffer of local index l when local bit
+// `kept` (the one that stays in its register slot) is dropped: the compacted
+// index, XOR-swizzled against bank conflicts, times elem_bytes.  Linear over
+// GF(2) in l.
+uint32_t remap_offset(uint32_t l, int kept, int elem_bytes);
 
 // LDS-kernel form of one op; li maps a global bit position to its tile bit
 // (-1 outside the tile).
