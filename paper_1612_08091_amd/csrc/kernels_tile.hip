@@ -216,6 +216,58 @@ __device__ __forceinline__ void dispatch_g2(T *amp, int a, int b, const T *U, ui
 #undef QSV_G2
 }
 
+// One operation of a register program on the thread's amplitudes.
+template <typename T, int NR, int RB, int TB>
+__device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restrict__ pool,
+                                       unsigned char *lds, uint64_t base, uint64_t &gthr,
+                                       uint64_t *gbit, uint32_t tid) {
+    const int kind = op.kind;
+    const uint64_t gb = base | gthr;
+    if (kind == ROP_G1) {
+        const T *U = pool + op.mat;
+        if (op.ctrl) dispatch_g1<T, NR, RB, true>(amp, op.a, U, gb, gbit, op.ctrl);
+        else dispatch_g1<T, NR, RB, false>(amp, op.a, U, gb, gbit, 0);
+    } else if (kind == ROP_G2) {
+        const T *U = pool + op.mat;
+        if (op.ctrl) dispatch_g2<T, NR, RB, true>(amp, op.a, op.b, U, gb, gbit, op.ctrl);
+        else dispatch_g2<T, NR, RB, false>(amp, op.a, op.b, U, gb, gbit, 0);
+    } else if (kind == ROP_DIAG) {
+        reg_diag<T, NR, RB>(amp, op, pool, gb, gbit);
+    } else {
+        // thread parts from the thread-id bits; the empty asm makes the id
+        // opaque so the per-bit masks are not kept live across the op loop
+        uint32_t tr = tid;
+        asm volatile("" : "+v"(tr));
+        uint32_t wt = 0, rt = 0;
+        uint64_t gthr_n = 0;
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            const uint32_t msk = 0u - ((tr >> t) & 1u);
+            wt ^= msk & op.wthr[t];
+            rt ^= msk & op.rthr[t];
+            gthr_n |= (((uint64_t)msk << 32) | msk) & op.g_thr[t];
+        }
+        switch (op.a) {
+        case 0: remap_half<T, NR, 0>(amp, lds, wt, rt, op); break;
+        case 1: remap_half<T, NR, 1>(amp, lds, wt, rt, op); break;
+        case 2: remap_half<T, NR, 2>(amp, lds, wt, rt, op); break;
+        case 3:
+            if constexpr (RB > 3) remap_half<T, NR, 3>(amp, lds, wt, rt, op);
+            else __builtin_unreachable();
+            break;
+        case 4:
+            if constexpr (RB > 4) remap_half<T, NR, 4>(amp, lds, wt, rt, op);
+            else __builtin_unreachable();
+            break;
+        default: __builtin_unreachable();
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) gbit[j] = op.g_reg[j];
+        gthr = gthr_n;
+    }
+    // ROP_NOP: nothing
+}
+
 template <typename R, int RB, int TB>
 __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restrict__ psi,
                                                   TileArgs ta, const RegOp *__restrict__ ops,
@@ -223,7 +275,9 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
     using T = typename VT<R>::T;
     constexpr int NR = 1 << RB;
     constexpr int m = RB + TB;
-    extern __shared__ unsigned char smem_raw[];
+    // half a tile for the two-phase remaps (static, so addresses need no base)
+    __shared__ T half_tile[1 << (m - 1)];
+    unsigned char *lds = reinterpret_cast<unsigned char *>(half_tile);
     uint64_t base = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
 #pragma unroll
     for (int i = 0; i < m; ++i) {
@@ -243,55 +297,13 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
 #pragma unroll
     for (int i = 0; i < NR; ++i) amp[i] = psi[base | gthr | greg<T, NR, RB>(i, gbit)];
 
-    for (int oi = 0; oi < ta.n_ops; ++oi) {
-        // fields are read through a reference into the uniform op array so
-        // they stay scalar (a local copy would go to per-lane memory)
-        const RegOp &op = ops[oi];
-        const int kind = op.kind;
-        const uint64_t gb = base | gthr;
-        if (kind == ROP_G1) {
-            const T *U = pool + op.mat;
-            if (op.ctrl) dispatch_g1<T, NR, RB, true>(amp, op.a, U, gb, gbit, op.ctrl);
-            else dispatch_g1<T, NR, RB, false>(amp, op.a, U, gb, gbit, 0);
-        } else if (kind == ROP_G2) {
-            const T *U = pool + op.mat;
-            if (op.ctrl) dispatch_g2<T, NR, RB, true>(amp, op.a, op.b, U, gb, gbit, op.ctrl);
-            else dispatch_g2<T, NR, RB, false>(amp, op.a, op.b, U, gb, gbit, 0);
-        } else if (kind == ROP_DIAG) {
-            reg_diag<T, NR, RB>(amp, op, pool, gb, gbit);
-        } else {
-            // REMAP into the layout the op describes
-            // thread parts from the thread-id bits; the empty asm makes the
-            // id opaque so the per-bit masks are not kept live across the loop
-            uint32_t tr = tid;
-            asm volatile("" : "+v"(tr));
-            uint32_t wt = 0, rt = 0;
-            uint64_t gthr_n = 0;
-#pragma unroll
-            for (int t = 0; t < TB; ++t) {
-                const uint32_t msk = 0u - ((tr >> t) & 1u);
-                wt ^= msk & op.wthr[t];
-                rt ^= msk & op.rthr[t];
-                gthr_n |= (((uint64_t)msk << 32) | msk) & op.g_thr[t];
-            }
-            switch (op.a) {
-            case 0: remap_half<T, NR, 0>(amp, smem_raw, wt, rt, op); break;
-            case 1: remap_half<T, NR, 1>(amp, smem_raw, wt, rt, op); break;
-            case 2: remap_half<T, NR, 2>(amp, smem_raw, wt, rt, op); break;
-            case 3:
-                if constexpr (RB > 3) remap_half<T, NR, 3>(amp, smem_raw, wt, rt, op);
-                else __builtin_unreachable();
-                break;
-            case 4:
-                if constexpr (RB > 4) remap_half<T, NR, 4>(amp, smem_raw, wt, rt, op);
-                else __builtin_unreachable();
-                break;
-            default: __builtin_unreachable();
-            }
-#pragma unroll
-            for (int j = 0; j < RB; ++j) gbit[j] = op.g_reg[j];
-            gthr = gthr_n;
-        }
+    // Two ops per iteration (the host pads the program to an even length
+    // with ROP_NOP): the amplitudes then alternate between two register sets
+    // without copies at the loop back edge.  Op fields are read through
+    // references into the uniform op array so they stay scalar.
+    for (int oi = 0; oi < ta.n_ops; oi += 2) {
+        reg_op<T, NR, RB, TB>(amp, ops[oi], pool, lds, base, gthr, gbit, tid);
+        reg_op<T, NR, RB, TB>(amp, ops[oi + 1], pool, lds, base, gthr, gbit, tid);
     }
 #pragma unroll
     for (int i = 0; i < NR; ++i) psi[base | gthr | greg<T, NR, RB>(i, gbit)] = amp[i];
@@ -332,15 +344,9 @@ template <typename R, int RB, int TB>
 static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
                                const void *pool, hipStream_t s) {
     using T = typename VT<R>::T;
-    static bool attr = false;
-    const size_t lds = sizeof(T) << (RB + TB - 1);   // half a tile (two-phase remaps)
-    if (!attr) {
-        hipError_t e = set_lds_attr(k_tile_reg<R, RB, TB>, lds);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
     if (ta.n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_tile_reg<R, RB, TB>), tile_grid(ta.n_tiles), dim3(1 << TB), lds, s,
+    if (ta.n_ops & 1) return hipErrorInvalidValue;   // programs are padded to even length
+    hipLaunchKernelGGL((k_tile_reg<R, RB, TB>), tile_grid(ta.n_tiles), dim3(1 << TB), 0, s,
                        (T *)psi, ta, rops, (const T *)pool);
     return hipGetLastError();
 }

@@ -318,6 +318,15 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         prog.rops.push_back(r);
     }
     fill_layouts(prog, rb, elem_bytes);
+    // the kernel runs ops in pairs
+    if (prog.rops.size() & 1) {
+        dev::RegOp nop{};
+        nop.kind = dev::ROP_G1;
+        nop.a = 0;
+        nop.mat = (int64_t)(mats.size() / 2);
+        push(mats, cd(1, 0)); push(mats, cd(0, 0)); push(mats, cd(0, 0)); push(mats, cd(1, 0));
+        prog.rops.push_back(nop);
+    }
 }
 
 }  // namespace qsv
