@@ -33,6 +33,42 @@ sys.path.insert(0, ROOT)
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 FP64_PEAK = 78.6e12        # MI355X FP64 (vector and matrix), flop/s
 
+# Measured HBM traffic of the dominant kernel (k_tile_reg<double,4,8> on this
+# workload), from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch, mean over the dispatches of one step).  The
+# counters are scaled by what they read for a plain device copy of known size
+# in the same runs (4 GiB read + 4 GiB write: FETCH_SIZE reads half the bytes,
+# WRITE_SIZE all of them).  Valid only for the sources they were taken with:
+# the digest below covers every file that shapes the kernel or its launches.
+TRAFFIC = {"kernel": "k_tile_reg<double,4,8>", "fetch_kib": 8396087.9, "write_kib": 19028467.5,
+           "fetch_scale": 2.0, "write_scale": 1.0, "digest": "2acc30e0ed23f67b"}
+TRAFFIC_SOURCES = ("paper_1612_08091_amd/csrc/kernels_tile.hip",
+                   "paper_1612_08091_amd/csrc/lds_ops.hpp",
+                   "paper_1612_08091_amd/csrc/device.hpp",
+                   "paper_1612_08091_amd/csrc/tileprog.cpp",
+                   "paper_1612_08091_amd/csrc/tileprog.hpp",
+                   "paper_1612_08091_amd/csrc/planner.cpp",
+                   "paper_1612_08091_amd/csrc/qsv_internal.hpp",
+                   "paper_1612_08091_amd/build.py")
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel, or None when the counters
+    were taken from other sources than the ones built here."""
+    t = TRAFFIC
+    if t["fetch_kib"] is None or t["digest"] != kernel_source_digest():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -124,24 +160,82 @@ def form_precision(samples: int = 1 << 20):
                                                                    dtype=np.uint64))
     out = {"workload": "config 2: 32-qubit Haar + CZ brick, 40 layers, 1900 gates"}
     amps = {}
-    for dtype in ("c64", "c128"):
-        sim = Q.Simulator(n_max=32, dtype=dtype, mode="tiled", k_max=2, timing=True)
+    # complex64 with 2-qubit fusion (register tiles), complex64 with 5-qubit
+    # fused unitaries on FP32 MFMA (LDS tiles), and the complex128 reference
+    for key, dtype, k in (("c64", "c64", 2), ("c64_k5_mfma", "c64", 5), ("c128", "c128", 2)):
+        sim = Q.Simulator(n_max=32, dtype=dtype, mode="tiled", k_max=k, timing=True)
         sim.allocate(32)
         _timed_circuit(sim, circ)                  # allocation + warm-up
         sim.reset_stats()
         t = _timed_circuit(sim, circ)
         st = sim.stats()
         tile_ms, tile_n, _ = sim.kernel_times()["tile"]
-        amps[dtype] = sim.get_amplitudes(idx)
-        out[dtype] = {"s_per_circuit": t,
-                      "amp_gate_per_s": len(circ.gates) * float(1 << 32) / t,
-                      "pct_hbm_peak": st["alg_bytes"] / t / HBM_PEAK,
-                      "passes": st["passes"], "tile_avg_ms": tile_ms / max(tile_n, 1),
-                      "norm2_drift": abs(sim.norm2() - 1.0)}
+        amps[key] = sim.get_amplitudes(idx)
+        out[key] = {"s_per_circuit": t,
+                    "amp_gate_per_s": len(circ.gates) * float(1 << 32) / t,
+                    "pct_hbm_peak": st["alg_bytes"] / t / HBM_PEAK,
+                    "passes": st["passes"], "fused_ops": st["fused_ops"],
+                    "tile_avg_ms": tile_ms / max(tile_n, 1),
+                    "norm2_drift": abs(sim.norm2() - 1.0)}
         sim.close()
-    d = amps["c64"] - amps["c128"]
-    out["fp32_rel_err_sampled"] = float(np.linalg.norm(d) / np.linalg.norm(amps["c128"]))
+        log("  precision leg %s: %.3f s" % (key, t))
+    ref = np.linalg.norm(amps["c128"])
+    for key in ("c64", "c64_k5_mfma"):
+        out[key]["fp32_rel_err_sampled"] = float(np.linalg.norm(amps[key] - amps["c128"]) / ref)
     out["samples"] = samples
+    return out
+
+
+def form_fusion_qft(n: int = 30):
+    """Config 1 beside the main leg: the random circuit with fusion widths
+    k = 3..5 (LDS tiles, MFMA for k >= 3), and the n-qubit QFT of a random
+    basis state per gate and fused, checked against its closed form."""
+    import workloads as W
+    from paper_1612_08091_amd import qsv as Q
+    out = {}
+    circ = W.config1_random(n=n)
+    for k in (3, 4, 5):
+        sim = Q.Simulator(n_max=n, dtype="c128", mode="tiled", k_max=k, timing=True)
+        sim.allocate(n)
+        _timed_circuit(sim, circ)
+        sim.reset_stats()
+        t = _timed_circuit(sim, circ)
+        st = sim.stats()
+        tile_ms, tile_n, tile_b = sim.kernel_times()["tile"]
+        out["random_k%d" % k] = {"s_per_circuit": t,
+                                 "amp_gate_per_s": len(circ.gates) * float(1 << n) / t,
+                                 "passes": st["passes"], "fused_ops": st["fused_ops"],
+                                 "tile_GBps": tile_b / (tile_ms * 1e-3) / 1e9 if tile_ms else None}
+        sim.close()
+        log("  fusion k=%d: %.3f s" % (k, t))
+    x, qft = W.config1_qft(n)
+    prep = W.basis_prep(n, x)
+    idx = np.random.default_rng(W.SEED_BASE + 1).integers(0, 1 << n, size=4096, dtype=np.uint64)
+    ph = np.array([float((x * int(v)) % (1 << n)) for v in idx.astype(object)]) / (1 << n)
+    want = np.exp(2j * np.pi * ph) / (2 ** (n / 2))
+    for mode, k in (("pergate", 1), ("tiled", 2)):
+        sim = Q.Simulator(n_max=n, dtype="c128", mode=mode, k_max=k, timing=True)
+        sim.allocate(n)
+        for rep in range(2):
+            sim.reset()
+            sim.run(prep)
+            sim.flush()
+            sim.synchronize()
+            sim.reset_stats()
+            sim.run(qft)
+            t0 = time.perf_counter()
+            sim.flush()
+            sim.synchronize()
+            t = time.perf_counter() - t0
+        st = sim.stats()
+        err = float(np.max(np.abs(sim.get_amplitudes(idx) - want)))
+        out["qft_%s" % mode] = {"s_per_circuit": t,
+                                "amp_gate_per_s": len(qft.gates) * float(1 << n) / t,
+                                "pct_hbm_peak": st["alg_bytes"] / t / HBM_PEAK,
+                                "passes_or_kernels": st["passes"] or st["kernels"],
+                                "max_abs_err_vs_closed_form": err}
+        sim.close()
+        log("  qft %s: %.3f s" % (mode, t))
     return out
 
 
@@ -269,7 +363,8 @@ def main():
     avg_ms = ms / max(launches, 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": None,
+                "frac": achieved / HBM_PEAK,
+                "traffic": measured_traffic() if dom == "tile" and (args.reg_bits or 4) == 4 else None,
                 "kernel": ("k_tile_reg<double,%d,8>" % (args.reg_bits or 4)) if dom == "tile"
                           else "k_dense<double,1>",
                 "launches": launches, "avg_ms": avg_ms, "alg_bytes_per_launch": per_launch_bytes}
@@ -307,6 +402,8 @@ def main():
         }
         log("per-gate leg: %.2f ms/step" % pg["ms_per_step"])
     if not args.no_forms:
+        extra["fusion_and_qft_30q"] = form_fusion_qft(n)
+        log("fusion / QFT form done")
         extra["precision_32q"] = form_precision()
         log("precision form done")
         extra["batched"] = form_batched()

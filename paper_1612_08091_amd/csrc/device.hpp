@@ -71,8 +71,7 @@ struct TileArgs {
 };
 
 // One operation of the register-resident tile kernel.
-enum RegOpKind : int32_t { ROP_G1 = 0, ROP_G2 = 1, ROP_DIAG = 2, ROP_REMAP = 3, ROP_LDS = 4,
-                           ROP_NOP = 5 };
+enum RegOpKind : int32_t { ROP_G1 = 0, ROP_G2 = 1, ROP_DIAG = 2, ROP_REMAP = 3, ROP_LDS = 4 };
 struct RegOp {
     int32_t kind;
     int32_t a;            // G1: register bit; G2: lower register bit (matrix bit 0);

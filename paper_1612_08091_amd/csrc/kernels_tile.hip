@@ -265,7 +265,6 @@ __device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restr
         for (int j = 0; j < RB; ++j) gbit[j] = op.g_reg[j];
         gthr = gthr_n;
     }
-    // ROP_NOP: nothing
 }
 
 template <typename R, int RB, int TB>
@@ -298,8 +297,8 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
     for (int i = 0; i < NR; ++i) amp[i] = psi[base | gthr | greg<T, NR, RB>(i, gbit)];
 
     // Two ops per iteration (the host pads the program to an even length
-    // with ROP_NOP): the amplitudes then alternate between two register sets
-    // without copies at the loop back edge.  Op fields are read through
+    // with an identity 1-qubit op): the amplitudes then alternate between two
+    // register sets without copies at the loop back edge.  Op fields are read through
     // references into the uniform op array so they stay scalar.
     for (int oi = 0; oi < ta.n_ops; oi += 2) {
         reg_op<T, NR, RB, TB>(amp, ops[oi], pool, lds, base, gthr, gbit, tid);

@@ -318,7 +318,7 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         prog.rops.push_back(r);
     }
     fill_layouts(prog, rb, elem_bytes);
-    // the kernel runs ops in pairs
+    // the kernel runs ops in pairs: pad with an identity 1-qubit op
     if (prog.rops.size() & 1) {
         dev::RegOp nop{};
         nop.kind = dev::ROP_G1;
