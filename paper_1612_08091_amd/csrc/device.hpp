@@ -105,9 +105,10 @@ hipError_t launch_mono(int dtype, void *psi, int k, uint64_t ngroups, const Inde
 hipError_t launch_tile_pass(int dtype, void *psi, const TileArgs &ta, const TileOp *ops,
                             const void *pool, hipStream_t s);
 // Register-resident tile pass: ta.rb register bits in {3, 4, 5} and
-// ta.m - ta.rb thread bits in {8, 9}.
+// ta.m - ta.rb thread bits in {8, 9}.  `counter` is a device word that must
+// hold 0 when the pass starts; the persistent workgroups take tiles from it.
 hipError_t launch_tile_reg(int dtype, void *psi, const TileArgs &ta, const RegOp *rops,
-                           const void *pool, hipStream_t s);
+                           const void *pool, unsigned int *counter, hipStream_t s);
 int tile_pass_max_bits(int dtype);
 int tile_reg_bits(int dtype);     // default register bits per thread
 

@@ -17,6 +17,8 @@
 //    sweeps it (used for small states).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "lds_ops.hpp"
 
@@ -267,45 +269,73 @@ __device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restr
     }
 }
 
+// Persistent: a grid of resident workgroups takes tiles from an atomic
+// counter (one per pass, zeroed by the host upload), so a compute unit or XCD
+// that runs slower simply processes fewer tiles and no dispatch gaps open up
+// between tiles.  Every workgroup leaves once the counter has passed the tile
+// count.
 template <typename R, int RB, int TB>
 __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restrict__ psi,
                                                   TileArgs ta, const RegOp *__restrict__ ops,
-                                                  const typename VT<R>::T *__restrict__ pool) {
+                                                  const typename VT<R>::T *__restrict__ pool,
+                                                  unsigned int *__restrict__ counter) {
     using T = typename VT<R>::T;
     constexpr int NR = 1 << RB;
     constexpr int m = RB + TB;
     // half a tile for the two-phase remaps (static, so addresses need no base)
     __shared__ T half_tile[1 << (m - 1)];
+    __shared__ unsigned int s_tile;
     unsigned char *lds = reinterpret_cast<unsigned char *>(half_tile);
-    uint64_t base = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
-#pragma unroll
-    for (int i = 0; i < m; ++i) {
-        const uint64_t lowm = (1ull << ta.tpos[i]) - 1;
-        base = ((base & ~lowm) << 1) | (base & lowm);
-    }
     const uint32_t tid = threadIdx.x;
-    // current layout: global index bit of each register bit (uniform) and
-    // the global bits of this thread
-    uint64_t gbit[RB];
+    // layout at load time (the same for every tile): global index bit of each
+    // register bit (uniform) and the global bits of this thread
+    uint64_t gbit0[RB];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) gbit[j] = ta.g_reg[j];
-    uint64_t gthr = 0;
+    for (int j = 0; j < RB; ++j) gbit0[j] = ta.g_reg[j];
+    uint64_t gthr0 = 0;
 #pragma unroll
-    for (int t = 0; t < TB; ++t) gthr |= (0ull - ((tid >> t) & 1u)) & ta.g_thr[t];
-    T amp[NR];
-#pragma unroll
-    for (int i = 0; i < NR; ++i) amp[i] = psi[base | gthr | greg<T, NR, RB>(i, gbit)];
+    for (int t = 0; t < TB; ++t) gthr0 |= (0ull - ((tid >> t) & 1u)) & ta.g_thr[t];
+    const uint32_t n_tiles = (uint32_t)ta.n_tiles;
 
-    // Two ops per iteration (the host pads the program to an even length
-    // with an identity 1-qubit op): the amplitudes then alternate between two
-    // register sets without copies at the loop back edge.  Op fields are read through
-    // references into the uniform op array so they stay scalar.
-    for (int oi = 0; oi < ta.n_ops; oi += 2) {
-        reg_op<T, NR, RB, TB>(amp, ops[oi], pool, lds, base, gthr, gbit, tid);
-        reg_op<T, NR, RB, TB>(amp, ops[oi + 1], pool, lds, base, gthr, gbit, tid);
-    }
+    if (tid == 0) s_tile = atomicAdd(counter, 1u);
+    __syncthreads();
+    uint32_t tile = __builtin_amdgcn_readfirstlane(s_tile);
+    while (tile < n_tiles) {
+        uint64_t base = tile;
 #pragma unroll
-    for (int i = 0; i < NR; ++i) psi[base | gthr | greg<T, NR, RB>(i, gbit)] = amp[i];
+        for (int i = 0; i < m; ++i) {
+            const uint64_t lowm = (1ull << ta.tpos[i]) - 1;
+            base = ((base & ~lowm) << 1) | (base & lowm);
+        }
+        // the empty asm keeps the per-register load addresses from being
+        // hoisted out of the tile loop (32 VGPRs held for its whole life)
+        uint64_t gthr = gthr0;
+        asm volatile("" : "+v"(gthr));
+        T amp[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) amp[i] = psi[base | gthr | greg<T, NR, RB>(i, gbit0)];
+        // claim the next tile now; the atomic's latency hides behind the ops
+        unsigned int next = 0;
+        if (tid == 0) next = atomicAdd(counter, 1u);
+        uint64_t gbit[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) gbit[j] = gbit0[j];
+        // Two ops per iteration (the host pads the program to an even length
+        // with an identity 1-qubit op): the amplitudes then alternate between
+        // two register sets without copies at the loop back edge.  Op fields
+        // are read through references into the uniform op array so they stay
+        // scalar.
+        for (int oi = 0; oi < ta.n_ops; oi += 2) {
+            reg_op<T, NR, RB, TB>(amp, ops[oi], pool, lds, base, gthr, gbit, tid);
+            reg_op<T, NR, RB, TB>(amp, ops[oi + 1], pool, lds, base, gthr, gbit, tid);
+        }
+#pragma unroll
+        for (int i = 0; i < NR; ++i) psi[base | gthr | greg<T, NR, RB>(i, gbit)] = amp[i];
+        __syncthreads();   // every thread has read s_tile and left the LDS buffer
+        if (tid == 0) s_tile = next;
+        __syncthreads();
+        tile = __builtin_amdgcn_readfirstlane(s_tile);
+    }
 }
 
 int tile_pass_max_bits(int dtype) { return dtype == 0 ? 13 : 14; }
@@ -341,12 +371,25 @@ static hipError_t launch_lds_t(void *psi, const TileArgs &ta, const TileOp *ops,
 
 template <typename R, int RB, int TB>
 static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
-                               const void *pool, hipStream_t s) {
+                               const void *pool, unsigned int *counter, hipStream_t s) {
     using T = typename VT<R>::T;
     if (ta.n_tiles == 0) return hipSuccess;
     if (ta.n_ops & 1) return hipErrorInvalidValue;   // programs are padded to even length
-    hipLaunchKernelGGL((k_tile_reg<R, RB, TB>), tile_grid(ta.n_tiles), dim3(1 << TB), 0, s,
-                       (T *)psi, ta, rops, (const T *)pool);
+    if (ta.n_tiles > 0xffffffffull - 65536) return hipErrorInvalidValue;
+    static unsigned resident = 0;   // workgroups the device holds at once
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void *>(k_tile_reg<R, RB, TB>), 1 << TB, 0);
+        if (e != hipSuccess) return e;
+        resident = (unsigned)std::max(1, cus * std::max(1, per_cu));
+    }
+    const unsigned grid = (unsigned)std::min<uint64_t>(ta.n_tiles, resident);
+    hipLaunchKernelGGL((k_tile_reg<R, RB, TB>), dim3(grid), dim3(1 << TB), 0, s, (T *)psi, ta,
+                       rops, (const T *)pool, counter);
     return hipGetLastError();
 }
 
@@ -358,16 +401,16 @@ hipError_t launch_tile_pass(int dtype, void *psi, const TileArgs &ta, const Tile
 }
 
 hipError_t launch_tile_reg(int dtype, void *psi, const TileArgs &ta, const RegOp *rops,
-                           const void *pool, hipStream_t s) {
+                           const void *pool, unsigned int *counter, hipStream_t s) {
     const int rb = ta.rb, tb = ta.m - ta.rb;
 #define QSV_REG(R)                                                                   \
     if (tb == 8) {                                                                   \
-        if (rb == 3) return launch_reg_t<R, 3, 8>(psi, ta, rops, pool, s);           \
-        if (rb == 4) return launch_reg_t<R, 4, 8>(psi, ta, rops, pool, s);           \
-        if (rb == 5) return launch_reg_t<R, 5, 8>(psi, ta, rops, pool, s);           \
+        if (rb == 3) return launch_reg_t<R, 3, 8>(psi, ta, rops, pool, counter, s);           \
+        if (rb == 4) return launch_reg_t<R, 4, 8>(psi, ta, rops, pool, counter, s);           \
+        if (rb == 5) return launch_reg_t<R, 5, 8>(psi, ta, rops, pool, counter, s);           \
     } else if (tb == 9) {                                                            \
-        if (rb == 3) return launch_reg_t<R, 3, 9>(psi, ta, rops, pool, s);           \
-        if (rb == 4) return launch_reg_t<R, 4, 9>(psi, ta, rops, pool, s);           \
+        if (rb == 3) return launch_reg_t<R, 3, 9>(psi, ta, rops, pool, counter, s);           \
+        if (rb == 4) return launch_reg_t<R, 4, 9>(psi, ta, rops, pool, counter, s);           \
     }
     if (dtype == 0) {
         QSV_REG(double)

@@ -352,12 +352,14 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         n_rops += progs[pi].rops.size();
         n_lops += progs[pi].lops.size();
     }
-    // pool: [RegOp array][TileOp array][matrices in the state dtype]
+    // pool: [RegOp array][TileOp array][one zeroed tile counter per pass]
+    //       [matrices in the state dtype]
     const size_t r_bytes = (n_rops * sizeof(RegOp) + 255) & ~size_t(255);
     const size_t l_bytes = (n_lops * sizeof(TileOp) + 255) & ~size_t(255);
+    const size_t c_bytes = (passes.size() * sizeof(unsigned int) + 255) & ~size_t(255);
     const size_t nmat = mats.size();
     const size_t mat_bytes = s->opt.dtype == QSV_C128 ? nmat * sizeof(double) : nmat * sizeof(float);
-    std::vector<unsigned char> host(r_bytes + l_bytes + mat_bytes + 16, 0);
+    std::vector<unsigned char> host(r_bytes + l_bytes + c_bytes + mat_bytes + 16, 0);
     {
         size_t ro = 0, lo = 0;
         for (const auto &pg : progs) {
@@ -371,16 +373,17 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         }
     }
     if (s->opt.dtype == QSV_C128) {
-        if (nmat) std::memcpy(host.data() + r_bytes + l_bytes, mats.data(), mat_bytes);
+        if (nmat) std::memcpy(host.data() + r_bytes + l_bytes + c_bytes, mats.data(), mat_bytes);
     } else {
-        float *f = reinterpret_cast<float *>(host.data() + r_bytes + l_bytes);
+        float *f = reinterpret_cast<float *>(host.data() + r_bytes + l_bytes + c_bytes);
         for (size_t i = 0; i < nmat; ++i) f[i] = (float)mats[i];
     }
     void *dpool = nullptr;
     QSV_TRY(stage(s, host.data(), host.size(), &dpool));
     const RegOp *drops = reinterpret_cast<const RegOp *>(dpool);
     const TileOp *dlops = reinterpret_cast<const TileOp *>((const unsigned char *)dpool + r_bytes);
-    const void *dmat = (const unsigned char *)dpool + r_bytes + l_bytes;
+    unsigned int *dcount = reinterpret_cast<unsigned int *>((unsigned char *)dpool + r_bytes + l_bytes);
+    const void *dmat = (const unsigned char *)dpool + r_bytes + l_bytes + c_bytes;
     size_t ro = 0, lo = 0;
     for (size_t pi = 0; pi < passes.size(); ++pi) {
         const qsv::TileProgram &pg = progs[pi];
@@ -407,7 +410,7 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         if (pg.reg) {
             ta.n_ops = (int)nr;
             QSV_HIP(s, qsv::dev::launch_tile_reg(s->opt.dtype, s->d_state, ta, drops + ro, dmat,
-                                                 s->stream));
+                                                 dcount + pi, s->stream));
         } else {
             ta.n_ops = (int)nl;
             QSV_HIP(s, qsv::dev::launch_tile_pass(s->opt.dtype, s->d_state, ta, dlops + lo, dmat,
