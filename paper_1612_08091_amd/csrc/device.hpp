@@ -41,17 +41,18 @@ enum TileOpKind : int32_t { TOP_DENSE = 0, TOP_MONO = 1, TOP_DIAG_GLOBAL = 2, TO
 struct TileOp {
     int32_t kind;
     int32_t k;
-    uint32_t lctrl;       // local control bits (forced to 1)
+    int32_t nfree;        // group bits: tile bits that are neither targets nor local controls
     uint32_t touch;       // MONO / DIAG: rows that change
     uint64_t ectrl;       // control bits outside the tile: the op runs only if all are 1
     uint64_t gctrl;       // DIAG_GLOBAL: control mask over the global index
-    int32_t npos;         // local positions where zero bits are inserted (targets + lctrl)
-    uint8_t pos[16];
-    uint8_t gt[8];        // DIAG_GLOBAL: global target positions
-    uint32_t loff[32];    // local offset of matrix index r
-    uint32_t srcoff[32];  // MONO: local offset of the column feeding row r
+    uint32_t gt[8];       // DIAG_GLOBAL: global target positions
+    // Byte offsets in the XOR-swizzled LDS tile.  The swizzle is linear over
+    // GF(2) in the local index, so the address of row r of group g is
+    // sl[r] XOR (XOR of fz[b] over the set bits b of g).
+    uint32_t fz[16];      // free bit b (free bits in ascending local position)
+    uint32_t sl[32];      // row r: its target bits, plus the local controls
+    uint32_t ss[32];      // MONO: the row feeding row r
     int64_t mat;          // offset (in complex entries of the tile dtype) into the pool
-    int32_t pad[2];
 };
 
 struct TileArgs {
@@ -59,15 +60,16 @@ struct TileArgs {
     int32_t n_ops;
     int32_t nq;           // state qubits
     int32_t tile_pos_n;   // == m
-    uint8_t tpos[40];     // tile positions, ascending
+    uint32_t tpos[40];    // tile positions, ascending (words: uniform indexed loads stay scalar)
     uint64_t n_tiles;
     uint8_t reg_lbit[8];  // register kernel: initial layout, tile bit of register bit j
     uint8_t thr_lbit[16]; //                  tile bit of thread-id bit i
     int32_t rb;           // register bits per thread (threads = 2^(m - rb))
-    uint32_t pad;
+    int32_t mfma_k;       // LDS kernel: widest matrix-core op of the pass (0 = none)
     uint64_t g_reg[8];    // register kernel, initial layout: global index bit of register
                           // bit j, and of thread-id bit i
     uint64_t g_thr[16];
+    uint64_t dep_hi[64];  // LDS kernel: global offset of local index 256 * i (tile bits >= 8)
 };
 
 // One operation of the register-resident tile kernel.
@@ -80,7 +82,7 @@ struct RegOp {
     uint32_t pad0;
     uint64_t ctrl;        // G1/G2/DIAG: control bits over the global index
     int64_t mat;          // offset (complex entries of the tile dtype) into the pool
-    uint8_t gt[8];        // DIAG: global target positions
+    uint32_t gt[8];       // DIAG: global target positions (words: scalar loads)
     uint8_t reg_lbit[8];  // REMAP: new layout
     uint8_t thr_lbit[16];
     // REMAP (a = register slot whose tile bit stays put): byte offsets into the
@@ -103,7 +105,7 @@ hipError_t launch_dense(int dtype, void *psi, int k, uint64_t ngroups, const Ind
 hipError_t launch_mono(int dtype, void *psi, int k, uint64_t ngroups, const IndexArgs &ia,
                        const MonoArgs &a, hipStream_t s);
 hipError_t launch_tile_pass(int dtype, void *psi, const TileArgs &ta, const TileOp *ops,
-                            const void *pool, hipStream_t s);
+                            const void *pool, unsigned int *counter, hipStream_t s);
 // Register-resident tile pass: ta.rb register bits in {3, 4, 5} and
 // ta.m - ta.rb thread bits in {8, 9}.  `counter` is a device word that must
 // hold 0 when the pass starts; the persistent workgroups take tiles from it.
@@ -181,7 +183,7 @@ struct BatchPass {
     int32_t op_begin;     // first TileOp
     int32_t op_count;
     int32_t pad;
-    uint8_t tpos[16];     // tile positions, ascending
+    uint32_t tpos[16];    // tile positions, ascending
 };
 struct BatchTerm {
     uint64_t x, z;

@@ -175,14 +175,14 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
                 li[q] = -1;
                 if ((p.tile >> q) & 1) {
                     li[q] = mm;
-                    bp.tpos[mm++] = (uint8_t)q;
+                    bp.tpos[mm++] = (uint32_t)q;
                 }
             }
             bp.m = mm;
             bp.op_begin = (int)tops.size();
             for (const Op &op : p.ops) {
                 if (op.kind == Op::MONO && op.touch == 0) continue;
-                tops.push_back(qsv::lower_to_lds(op, li, mats));
+                tops.push_back(qsv::lower_to_lds(op, li, mats, b->dtype == QSV_C128 ? 16 : 8));
             }
             bp.op_count = (int)tops.size() - bp.op_begin;
             nops += bp.op_count;

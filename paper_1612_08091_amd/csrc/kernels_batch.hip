@@ -14,6 +14,11 @@
 namespace qsv {
 namespace dev {
 
+// tile positions of a state held whole in LDS: local bit i is qubit i
+__constant__ uint32_t kIdentityPos[40] = {0,  1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 11, 12, 13,
+                                          14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27,
+                                          28, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39};
+
 template <typename R>
 __device__ __forceinline__ double block_sum_b(double v, double *sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -108,13 +113,10 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                 tile[swz<R>(l)] = v;
             }
             __syncthreads();
-            TileArgs ta;
-            ta.m = n;
-            for (int i = 0; i < n; ++i) ta.tpos[i] = (uint8_t)i;
             for (int p = 0; p < bc.pass_count; ++p) {
-                const BatchPass bp = passes[bc.pass_begin + p];
+                const BatchPass &bp = passes[bc.pass_begin + p];
                 for (int o = 0; o < bp.op_count; ++o) {
-                    lds_op<R>(tile, n, 0, ta, ops[bp.op_begin + o], pool);
+                    lds_op<R>(tile, n, 0, kIdentityPos, ops[bp.op_begin + o], pool);
                     __syncthreads();
                 }
             }
@@ -122,21 +124,19 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
         } else {
             // state in this workgroup's global slot, updated by tile passes
             for (int p = 0; p < bc.pass_count; ++p) {
-                const BatchPass bp = passes[bc.pass_begin + p];
+                const BatchPass &bp = passes[bc.pass_begin + p];
                 const int m = bp.m;
-                TileArgs ta;
-                ta.m = m;
-                for (int i = 0; i < m; ++i) ta.tpos[i] = bp.tpos[i];
+                const uint32_t *tpos = bp.tpos;
                 const uint32_t tsize = 1u << m;
                 const uint64_t ntiles = 1ull << (n - m);
                 for (uint64_t t = 0; t < ntiles; ++t) {
                     uint64_t base = t;
                     for (int i = 0; i < m; ++i) {
-                        const uint64_t lowm = (1ull << ta.tpos[i]) - 1;
+                        const uint64_t lowm = (1ull << tpos[i]) - 1;
                         base = ((base & ~lowm) << 1) | (base & lowm);
                     }
                     for (uint32_t l = tid; l < tsize; l += kNT) {
-                        const uint64_t gi = base | deposit_bits(l, ta.tpos, m);
+                        const uint64_t gi = base | deposit_bits(l, tpos, m);
                         T v;
                         if (p == 0) {       // the first pass starts from |0...0>
                             v.x = (gi == 0) ? R(1) : R(0);
@@ -148,11 +148,11 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                     }
                     __syncthreads();
                     for (int o = 0; o < bp.op_count; ++o) {
-                        lds_op<R>(tile, m, base, ta, ops[bp.op_begin + o], pool);
+                        lds_op<R>(tile, m, base, tpos, ops[bp.op_begin + o], pool);
                         __syncthreads();
                     }
                     for (uint32_t l = tid; l < tsize; l += kNT)
-                        slot[base | deposit_bits(l, ta.tpos, m)] = tile[swz<R>(l)];
+                        slot[base | deposit_bits(l, tpos, m)] = tile[swz<R>(l)];
                     __syncthreads();
                 }
             }

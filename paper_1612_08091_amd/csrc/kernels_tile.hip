@@ -26,34 +26,73 @@ namespace qsv {
 namespace dev {
 
 // ------------------------------------------------------- k_tile_lds
-template <typename R>
+// Persistent like k_tile_reg: resident workgroups take tiles from a per-pass
+// counter that the host zeroes.
+template <typename R, int KM>
 __global__ __launch_bounds__(kNT) void k_tile_lds(typename VT<R>::T *__restrict__ psi,
                                                   TileArgs ta, const TileOp *__restrict__ ops,
-                                                  const typename VT<R>::T *__restrict__ pool) {
+                                                  const typename VT<R>::T *__restrict__ pool,
+                                                  unsigned int *__restrict__ counter) {
     using T = typename VT<R>::T;
     extern __shared__ unsigned char smem_raw[];
+    __shared__ unsigned int s_tile;
     T *tile = reinterpret_cast<T *>(smem_raw);
     const int m = ta.m;
     const uint32_t tsize = 1u << m;
-    uint64_t base = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
-    for (int i = 0; i < m; ++i) {
-        const uint64_t lowm = (1ull << ta.tpos[i]) - 1;
-        base = ((base & ~lowm) << 1) | (base & lowm);
-    }
     const uint32_t tid = threadIdx.x;
+    // this thread's share of every tile: local indices j + tid, j = 0, kNT, ...
     const uint64_t dep_tid = deposit_bits(tid & (tsize - 1), ta.tpos, m);
-    for (uint32_t j = 0; j < tsize; j += kNT) {
-        const uint32_t l = j + tid;
-        if (l < tsize) tile[swz<R>(l)] = psi[base | dep_tid | deposit_bits(j, ta.tpos, m)];
-    }
+    const uint32_t swz_tid = swz<R>(tid & (tsize - 1));
+    const uint32_t n_tiles = (uint32_t)ta.n_tiles;
+    if (tid == 0) s_tile = atomicAdd(counter, 1u);
     __syncthreads();
-    for (int oi = 0; oi < ta.n_ops; ++oi) {
-        lds_op<R>(tile, m, base, ta, ops[oi], pool);
+    uint32_t t = __builtin_amdgcn_readfirstlane(s_tile);
+    while (t < n_tiles) {
+        uint64_t base = t;
+        for (int i = 0; i < m; ++i) {
+            const uint64_t lowm = (1ull << ta.tpos[i]) - 1;
+            base = ((base & ~lowm) << 1) | (base & lowm);
+        }
+        // loads in batches of 8 per thread, all in flight before their LDS
+        // writes (one HBM round trip per batch, not per amplitude)
+        if (tsize >= 8 * kNT) {
+            for (uint32_t j0 = 0; j0 < tsize; j0 += 8 * kNT) {
+                T v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    v[u] = psi[base | dep_tid | ta.dep_hi[(j0 >> 8) + u]];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) tile[swz_tid ^ swz<R>(j0 + u * kNT)] = v[u];
+            }
+        } else {
+            for (uint32_t j = 0; j < tsize; j += kNT)
+                if (j + tid < tsize)
+                    tile[swz_tid ^ swz<R>(j)] = psi[base | dep_tid | ta.dep_hi[j >> 8]];
+        }
+        unsigned int next = 0;
+        if (tid == 0) next = atomicAdd(counter, 1u);
         __syncthreads();
-    }
-    for (uint32_t j = 0; j < tsize; j += kNT) {
-        const uint32_t l = j + tid;
-        if (l < tsize) psi[base | dep_tid | deposit_bits(j, ta.tpos, m)] = tile[swz<R>(l)];
+        for (int oi = 0; oi < ta.n_ops; ++oi) {
+            lds_op<R, KM>(tile, m, base, ta.tpos, ops[oi], pool, ta.dep_hi);
+            __syncthreads();
+        }
+        if (tsize >= 8 * kNT) {
+            for (uint32_t j0 = 0; j0 < tsize; j0 += 8 * kNT) {
+                T v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = tile[swz_tid ^ swz<R>(j0 + u * kNT)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    psi[base | dep_tid | ta.dep_hi[(j0 >> 8) + u]] = v[u];
+            }
+        } else {
+            for (uint32_t j = 0; j < tsize; j += kNT)
+                if (j + tid < tsize)
+                    psi[base | dep_tid | ta.dep_hi[j >> 8]] = tile[swz_tid ^ swz<R>(j)];
+        }
+        if (tid == 0) s_tile = next;
+        __syncthreads();
+        t = __builtin_amdgcn_readfirstlane(s_tile);
     }
 }
 
@@ -353,20 +392,51 @@ static dim3 tile_grid(uint64_t nt) {
     return dim3(1u << 30, (unsigned)(nt >> 30), 1);
 }
 
-template <typename R>
+template <typename R, int KM>
 static hipError_t launch_lds_t(void *psi, const TileArgs &ta, const TileOp *ops, const void *pool,
-                               hipStream_t s) {
+                               unsigned int *counter, hipStream_t s) {
     using T = typename VT<R>::T;
+    const int max_bits = tile_pass_max_bits(sizeof(R) == 8 ? 0 : 1);
     static bool attr = false;
     if (!attr) {
-        hipError_t e = set_lds_attr(k_tile_lds<R>, sizeof(T) << tile_pass_max_bits(sizeof(R) == 8 ? 0 : 1));
+        hipError_t e = set_lds_attr(k_tile_lds<R, KM>, sizeof(T) << max_bits);
         if (e != hipSuccess) return e;
         attr = true;
     }
     if (ta.n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_tile_lds<R>), tile_grid(ta.n_tiles), dim3(kNT), sizeof(T) << ta.m, s,
-                       (T *)psi, ta, ops, (const T *)pool);
+    if (ta.n_tiles > 0xffffffffull - 65536) return hipErrorInvalidValue;
+    // resident workgroups per compute unit for each tile size
+    static int per_cu[16] = {0};
+    static int cus = 0;
+    const size_t lds = sizeof(T) << ta.m;
+    if (per_cu[ta.m] == 0) {
+        int dev = 0, occ = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess && cus == 0)
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &occ, reinterpret_cast<const void *>(k_tile_lds<R, KM>), kNT, lds);
+        if (e != hipSuccess) return e;
+        per_cu[ta.m] = std::max(1, occ);
+    }
+    const uint64_t resident = (uint64_t)std::max(1, cus) * per_cu[ta.m];
+    const unsigned grid = (unsigned)std::min<uint64_t>(ta.n_tiles, resident);
+    hipLaunchKernelGGL((k_tile_lds<R, KM>), dim3(grid), dim3(kNT), lds, s, (T *)psi, ta, ops,
+                       (const T *)pool, counter);
     return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_lds_k(void *psi, const TileArgs &ta, const TileOp *ops, const void *pool,
+                               unsigned int *counter, hipStream_t s) {
+    switch (ta.mfma_k) {
+    case 0: return launch_lds_t<R, 0>(psi, ta, ops, pool, counter, s);
+    case 3: return launch_lds_t<R, 3>(psi, ta, ops, pool, counter, s);
+    case 4: return launch_lds_t<R, 4>(psi, ta, ops, pool, counter, s);
+    case 5: return launch_lds_t<R, 5>(psi, ta, ops, pool, counter, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename R, int RB, int TB>
@@ -394,10 +464,10 @@ static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
 }
 
 hipError_t launch_tile_pass(int dtype, void *psi, const TileArgs &ta, const TileOp *ops,
-                            const void *pool, hipStream_t s) {
+                            const void *pool, unsigned int *counter, hipStream_t s) {
     if (ta.m < 1 || ta.m > tile_pass_max_bits(dtype)) return hipErrorInvalidValue;
-    return dtype == 0 ? launch_lds_t<double>(psi, ta, ops, pool, s)
-                      : launch_lds_t<float>(psi, ta, ops, pool, s);
+    return dtype == 0 ? launch_lds_k<double>(psi, ta, ops, pool, counter, s)
+                      : launch_lds_k<float>(psi, ta, ops, pool, counter, s);
 }
 
 hipError_t launch_tile_reg(int dtype, void *psi, const TileArgs &ta, const RegOp *rops,

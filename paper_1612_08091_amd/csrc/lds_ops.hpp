@@ -45,86 +45,89 @@ template <typename T> __device__ __forceinline__ T csel(bool c, const T &a, cons
 
 constexpr int kNT = 256;
 
-__device__ __forceinline__ uint32_t insert_local(uint32_t g, const uint8_t *pos, int npos) {
-    for (int i = 0; i < npos; ++i) {
-        const uint32_t lowm = (1u << pos[i]) - 1;
-        g = ((g & ~lowm) << 1) | (g & lowm);
-    }
-    return g;
+__device__ __forceinline__ uint64_t deposit_bits(uint32_t l, const uint32_t *tpos, int m) {
+    uint64_t out = 0;
+    for (int i = 0; i < m; ++i) out |= (uint64_t)((l >> i) & 1u) << tpos[i];
+    return out;
+}
+
+// XOR of parts[b] over the set bits b of x (b < nbits, nbits <= 16).
+__device__ __forceinline__ uint32_t xor_parts(uint32_t x, const uint32_t *parts, int nbits) {
+    uint32_t o = 0;
+    for (int b = 0; b < nbits; ++b) o ^= (0u - ((x >> b) & 1u)) & parts[b];
+    return o;
 }
 
 // ----------------------------------------------------- ops on an LDS tile
-// The tile is addressed through swz(); l is the logical local index.
+// The tile is addressed in bytes through the op's precomputed offsets.
+// Group g = threadIdx.x + kNT * it: the thread part of its address is fixed
+// for the op, the iteration part is uniform.
 template <typename R, int K>
-__device__ __forceinline__ void lds_dense(typename VT<R>::T *tile, int m, const TileOp &op,
+__device__ __forceinline__ void lds_dense(unsigned char *tb, const TileOp &op,
                                           const typename VT<R>::T *__restrict__ mat) {
     using T = typename VT<R>::T;
     constexpr int D = 1 << K;
-    const int npos = op.npos;
-    const uint32_t ngroups = 1u << (m - npos);
-    const uint32_t lctrl = op.lctrl;
-    for (uint32_t g = threadIdx.x; g < ngroups; g += kNT) {
-        const uint32_t l0 = insert_local(g, op.pos, npos) | lctrl;
+    const int nfree = op.nfree;
+    const uint32_t ngroups = 1u << nfree;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t toff = xor_parts(tid, op.fz, nfree < 8 ? nfree : 8);
+    for (uint32_t it = 0; it * kNT < ngroups; ++it) {
+        if (tid >= ngroups) break;   // fewer groups than threads
+        const uint32_t go = toff ^ xor_parts(it, op.fz + 8, nfree > 8 ? nfree - 8 : 0);
         T x[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) x[c] = tile[swz<R>(l0 + op.loff[c])];
+        for (int c = 0; c < D; ++c) x[c] = *reinterpret_cast<const T *>(tb + (go ^ op.sl[c]));
         // the whole group is in registers, so rows can be written one by one
         if constexpr (K <= 3) {
 #pragma unroll
             for (int r = 0; r < D; ++r) {
-                T y;
-                y.x = 0;
-                y.y = 0;
+                T y = cmul(mat[r * D], x[0]);
 #pragma unroll
-                for (int c = 0; c < D; ++c) y = cmadd(y, mat[r * D + c], x[c]);
-                tile[swz<R>(l0 + op.loff[r])] = y;
+                for (int c = 1; c < D; ++c) y = cmadd(y, mat[r * D + c], x[c]);
+                *reinterpret_cast<T *>(tb + (go ^ op.sl[r])) = y;
             }
         } else {
 #pragma unroll 1
             for (int r = 0; r < D; ++r) {
-                T y;
-                y.x = 0;
-                y.y = 0;
+                T y = cmul(mat[r * D], x[0]);
 #pragma unroll
-                for (int c = 0; c < D; ++c) y = cmadd(y, mat[r * D + c], x[c]);
-                tile[swz<R>(l0 + op.loff[r])] = y;
+                for (int c = 1; c < D; ++c) y = cmadd(y, mat[r * D + c], x[c]);
+                *reinterpret_cast<T *>(tb + (go ^ op.sl[r])) = y;
             }
         }
     }
 }
 
 template <typename R, int K>
-__device__ __forceinline__ void lds_mono(typename VT<R>::T *tile, int m, const TileOp &op,
+__device__ __forceinline__ void lds_mono(unsigned char *tb, const TileOp &op,
                                          const typename VT<R>::T *__restrict__ val) {
     using T = typename VT<R>::T;
     constexpr int D = 1 << K;
-    const int npos = op.npos;
-    const uint32_t ngroups = 1u << (m - npos);
-    const uint32_t lctrl = op.lctrl, touch = op.touch;
-    for (uint32_t g = threadIdx.x; g < ngroups; g += kNT) {
-        const uint32_t l0 = insert_local(g, op.pos, npos) | lctrl;
+    const int nfree = op.nfree;
+    const uint32_t ngroups = 1u << nfree;
+    const uint32_t tid = threadIdx.x, touch = op.touch;
+    const uint32_t toff = xor_parts(tid, op.fz, nfree < 8 ? nfree : 8);
+    for (uint32_t it = 0; it * kNT < ngroups; ++it) {
+        if (tid >= ngroups) break;
+        const uint32_t go = toff ^ xor_parts(it, op.fz + 8, nfree > 8 ? nfree - 8 : 0);
         T y[D];
 #pragma unroll
         for (int r = 0; r < D; ++r)
-            if ((touch >> r) & 1) y[r] = cmul(val[r], tile[swz<R>(l0 + op.srcoff[r])]);
+            if ((touch >> r) & 1)
+                y[r] = cmul(val[r], *reinterpret_cast<const T *>(tb + (go ^ op.ss[r])));
 #pragma unroll
         for (int r = 0; r < D; ++r)
-            if ((touch >> r) & 1) tile[swz<R>(l0 + op.loff[r])] = y[r];
+            if ((touch >> r) & 1) *reinterpret_cast<T *>(tb + (go ^ op.sl[r])) = y[r];
     }
-}
-
-__device__ __forceinline__ uint64_t deposit_bits(uint32_t l, const uint8_t *tpos, int m) {
-    uint64_t out = 0;
-    for (int i = 0; i < m; ++i) out |= (uint64_t)((l >> i) & 1u) << tpos[i];
-    return out;
 }
 
 // ------------------------------------------------------ matrix-core ops
 // A dense k-qubit op (k = 3..5) on the tile as a real GEMM Y = W X on the
 // 16x16x4 MFMA: X holds one group of 2^k amplitudes per column as
 // [Re x; Im x] (2^(k+1) rows), W is the real embedding of U.  A wave takes 16
-// groups at a time (one B column per lane % 16); the W fragments a lane
-// feeds to the A operand stay in registers for the whole op.
+// groups at a time (one B column per lane % 16, lane bits 0..3 = free bits
+// 0..3 of the group).  The host stores W in fragment order, so the A operand
+// of each MFMA is one contiguous, cache-resident read across the wave.
 typedef float qsv_v4f __attribute__((ext_vector_type(4)));
 typedef double qsv_v4d __attribute__((ext_vector_type(4)));
 
@@ -146,95 +149,97 @@ template <> struct Mfma<double> {
 };
 
 template <typename R, int K>
-__device__ __forceinline__ void lds_dense_mfma(typename VT<R>::T *tile, int m, const TileOp &op,
+__device__ __forceinline__ void lds_dense_mfma(unsigned char *tb, const TileOp &op,
                                                const R *__restrict__ W) {
     using V = typename Mfma<R>::V;
     constexpr int D = 1 << K, D2 = 2 * D;
     constexpr int MB = D2 / 16, KC = D2 / 4;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwaves = blockDim.x >> 6;
-    const int npos = op.npos;
-    const uint32_t ngroups = 1u << (m - npos);
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t nwaves = blockDim.x >> 6;
+    const int nfree = op.nfree;
+    const uint32_t ngroups = 1u << nfree;
     const uint32_t ncb = (ngroups + 15) >> 4;
-    R a[MB][KC];
-    uint32_t in_off[KC];
-    int in_part[KC];
+    const uint32_t loff = xor_parts((uint32_t)lane & 15u, op.fz, nfree < 4 ? nfree : 4);
+    const bool valid = ((uint32_t)lane & 15u) < ngroups;
+    // the lane's row offsets (read once per op, kept in registers)
+    uint32_t in_off[KC], out_off[MB][4];
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
         const int rho = 4 * kc + (lane >> 4);
-        in_off[kc] = op.loff[rho & (D - 1)];
-        in_part[kc] = rho >= D;
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) a[mb][kc] = W[(16 * mb + (lane & 15)) * D2 + rho];
+        in_off[kc] = op.sl[rho & (D - 1)] | (rho >= D ? (uint32_t)sizeof(R) : 0u);
     }
-    uint32_t out_off[MB][4];
-    int out_part[MB][4];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * mb + Mfma<R>::row(lane, r);
-            out_off[mb][r] = op.loff[row & (D - 1)];
-            out_part[mb][r] = row >= D;
+            out_off[mb][r] = op.sl[row & (D - 1)] | (row >= D ? (uint32_t)sizeof(R) : 0u);
         }
-    R *tr = reinterpret_cast<R *>(tile);
+    const R *wl = W + lane;
     for (uint32_t cb = wave; cb < ncb; cb += nwaves) {
-        const uint32_t g = cb * 16 + (lane & 15);
-        const bool valid = g < ngroups;
-        const uint32_t l0 = valid ? (insert_local(g, op.pos, npos) | op.lctrl) : 0u;
+        const uint32_t go = loff ^ xor_parts(cb, op.fz + 4, nfree > 4 ? nfree - 4 : 0);
         V acc[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) acc[mb] = V{0, 0, 0, 0};
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
-            const R b = valid ? tr[2 * swz<R>(l0 + in_off[kc]) + in_part[kc]] : R(0);
+            const R b = valid ? *reinterpret_cast<const R *>(tb + (go ^ in_off[kc])) : R(0);
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb] = Mfma<R>::op(a[mb][kc], b, acc[mb]);
+            for (int mb = 0; mb < MB; ++mb)
+                acc[mb] = Mfma<R>::op(wl[(mb * KC + kc) * 64], b, acc[mb]);
         }
         if (valid) {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    tr[2 * swz<R>(l0 + out_off[mb][r]) + out_part[mb][r]] = acc[mb][r];
+                    *reinterpret_cast<R *>(tb + (go ^ out_off[mb][r])) = acc[mb][r];
         }
     }
 }
 
-// Apply LDS op `op` to the whole tile (all threads take part).
-template <typename R>
-__device__ void lds_op(typename VT<R>::T *tile, int m, uint64_t base, const TileArgs &ta,
-                       const TileOp &op, const typename VT<R>::T *__restrict__ pool) {
+// Apply LDS op `op` to the whole tile (all threads take part).  KM is the
+// widest matrix-core op the caller can meet (0: none); the host emits dense
+// ops of 3 or more qubits only in matrix-core form.
+template <typename R, int KM = 5>
+__device__ void lds_op(typename VT<R>::T *tile, int m, uint64_t base, const uint32_t *tpos,
+                       const TileOp &op, const typename VT<R>::T *__restrict__ pool,
+                       const uint64_t *dep_hi = nullptr) {
     using T = typename VT<R>::T;
     if ((base & op.ectrl) != op.ectrl) return;
     const T *mat = pool + op.mat;
+    unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
     if (op.kind == TOP_DENSE_MFMA) {
         const R *W = reinterpret_cast<const R *>(mat);
-        switch (op.k) {
-        case 3: lds_dense_mfma<R, 3>(tile, m, op, W); break;
-        case 4: lds_dense_mfma<R, 4>(tile, m, op, W); break;
-        case 5: lds_dense_mfma<R, 5>(tile, m, op, W); break;
+        if constexpr (KM >= 3) {
+            if (op.k == 3) lds_dense_mfma<R, 3>(tb, op, W);
+        }
+        if constexpr (KM >= 4) {
+            if (op.k == 4) lds_dense_mfma<R, 4>(tb, op, W);
+        }
+        if constexpr (KM >= 5) {
+            if (op.k == 5) lds_dense_mfma<R, 5>(tb, op, W);
         }
     } else if (op.kind == TOP_DENSE) {
-        switch (op.k) {
-        case 1: lds_dense<R, 1>(tile, m, op, mat); break;
-        case 2: lds_dense<R, 2>(tile, m, op, mat); break;
-        case 3: lds_dense<R, 3>(tile, m, op, mat); break;
-        case 4: lds_dense<R, 4>(tile, m, op, mat); break;
-        case 5: lds_dense<R, 5>(tile, m, op, mat); break;
-        }
+        if (op.k == 1) lds_dense<R, 1>(tb, op, mat);
+        else lds_dense<R, 2>(tb, op, mat);
     } else if (op.kind == TOP_MONO) {
-        switch (op.k) {
-        case 1: lds_mono<R, 1>(tile, m, op, mat); break;
-        case 2: lds_mono<R, 2>(tile, m, op, mat); break;
-        case 3: lds_mono<R, 3>(tile, m, op, mat); break;
-        case 4: lds_mono<R, 4>(tile, m, op, mat); break;
-        case 5: lds_mono<R, 5>(tile, m, op, mat); break;
-        }
+        // (the host lowers monomial ops of 4 or more qubits as dense ops)
+        if (op.k == 1) lds_mono<R, 1>(tb, op, mat);
+        else if (op.k == 2) lds_mono<R, 2>(tb, op, mat);
+        else lds_mono<R, 3>(tb, op, mat);
     } else {
+        // diagonal op with targets outside the tile: the phase index and the
+        // controls come from the global index of each amplitude
         const uint32_t tsize = 1u << m;
-        for (uint32_t l = threadIdx.x; l < tsize; l += kNT) {
-            const uint64_t gi = base | deposit_bits(l, ta.tpos, m);
+        const uint32_t tid = threadIdx.x;
+        const uint64_t dep_tid = deposit_bits(tid & (tsize - 1), tpos, m);
+        for (uint32_t j = 0; j < tsize; j += kNT) {
+            const uint32_t l = j + tid;
+            if (l >= tsize) break;
+            const uint64_t gi =
+                base | dep_tid | (dep_hi ? dep_hi[j >> 8] : deposit_bits(j, tpos, m));
             if ((gi & op.gctrl) != op.gctrl) continue;
             uint32_t r = 0;
             for (int q = 0; q < op.k; ++q) r |= (uint32_t)((gi >> op.gt[q]) & 1u) << q;

@@ -399,13 +399,20 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         ta.tile_pos_n = pg.m;
         int c = 0;
         for (int p = 0; p < 64; ++p)
-            if ((pg.tile >> p) & 1) ta.tpos[c++] = (uint8_t)p;
+            if ((pg.tile >> p) & 1) ta.tpos[c++] = (uint32_t)p;
         ta.n_tiles = 1ull << (nq - pg.m);
         std::memcpy(ta.reg_lbit, pg.reg_lbit, 8);
         std::memcpy(ta.thr_lbit, pg.thr_lbit, 16);
         std::memcpy(ta.g_reg, pg.g_reg, sizeof(ta.g_reg));
         std::memcpy(ta.g_thr, pg.g_thr, sizeof(ta.g_thr));
         ta.rb = rb;
+        ta.mfma_k = pg.mfma_k;
+        for (int i = 0; i < 64 && (i << 8) < (1 << pg.m); ++i) {
+            uint64_t d = 0;
+            for (int b = 8; b < pg.m; ++b)
+                if (((i << 8) >> b) & 1) d |= 1ull << ta.tpos[b];
+            ta.dep_hi[i] = d;
+        }
         const int tok = tbegin(s);
         if (pg.reg) {
             ta.n_ops = (int)nr;
@@ -414,7 +421,7 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         } else {
             ta.n_ops = (int)nl;
             QSV_HIP(s, qsv::dev::launch_tile_pass(s->opt.dtype, s->d_state, ta, dlops + lo, dmat,
-                                                  s->stream));
+                                                  dcount + pi, s->stream));
         }
         tend(s, tok, QSV_K_TILE, 2.0 * (double)s->dim() * s->elem());
         account(s, (double)s->dim(), pg.flops_per_amp);

@@ -23,23 +23,41 @@ void push(std::vector<double> &mats, const cd &v) {
     mats.push_back(v.imag());
 }
 
-// TileOp (LDS kernel form) of an op whose mixing targets lie in the tile.
-dev::TileOp lds_form(const Op &op, const int *li, std::vector<double> &mats) {
+// Swizzled element index of local index l (the same XOR swizzle as the
+// device's swz<R>: bits above the 256-byte bank span folded into the bits
+// below it).
+uint32_t swz_elem(uint32_t l, int elem_bytes) {
+    return elem_bytes == 16 ? (l ^ (((l >> 4) ^ (l >> 8)) & 15u))
+                            : (l ^ (((l >> 5) ^ (l >> 10)) & 31u));
+}
+
+// TileOp (LDS kernel form) of an op whose mixing targets lie in the tile;
+// li maps global positions to local bits, m = number of tile bits.
+dev::TileOp lds_form(const Op &op, const int *li, std::vector<double> &mats, int elem_bytes,
+                     double *flops) {
     dev::TileOp t{};
     t.k = op.k;
     t.touch = op.touch;
     t.mat = (int64_t)(mats.size() / 2);
+    int m = 0;
+    for (int p = 0; p < 64; ++p)
+        if (li[p] >= 0) ++m;
     bool inside = true;
     for (int j = 0; j < op.k; ++j)
         if (li[op.t[j]] < 0) inside = false;
     if (op.kind == Op::MONO && op.diag && !inside) {
         t.kind = dev::TOP_DIAG_GLOBAL;
-        for (int j = 0; j < op.k; ++j) t.gt[j] = (uint8_t)op.t[j];
+        for (int j = 0; j < op.k; ++j) t.gt[j] = (uint32_t)op.t[j];
         t.gctrl = op.ctrl;
         for (int r = 0; r < (1 << op.k); ++r) push(mats, op.U[r]);
+        *flops = 6.0 * __builtin_popcount(op.touch) / (double)(1 << op.k) /
+                 (double)(1ull << popc(op.ctrl));
         return t;
     }
-    t.kind = op.kind == Op::MONO ? dev::TOP_MONO : dev::TOP_DENSE;
+    // monomial ops of 4 or more qubits run as dense (matrix-core) ops, which
+    // keeps the per-thread register arrays of the LDS kernel small
+    const bool mono = op.kind == Op::MONO && op.k <= 3;
+    t.kind = mono ? dev::TOP_MONO : dev::TOP_DENSE;
     uint32_t lctrl = 0;
     uint64_t ectrl = 0;
     for (int p = 0; p < 64; ++p)
@@ -47,7 +65,6 @@ dev::TileOp lds_form(const Op &op, const int *li, std::vector<double> &mats) {
             if (li[p] >= 0) lctrl |= 1u << li[p];
             else ectrl |= 1ull << p;
         }
-    t.lctrl = lctrl;
     t.ectrl = ectrl;
     uint32_t ins = lctrl;
     int lt[kMaxK];
@@ -55,43 +72,46 @@ dev::TileOp lds_form(const Op &op, const int *li, std::vector<double> &mats) {
         lt[j] = li[op.t[j]];
         ins |= 1u << lt[j];
     }
-    t.npos = 0;
-    for (int b = 0; b < 32; ++b)
-        if ((ins >> b) & 1) t.pos[t.npos++] = (uint8_t)b;
+    t.nfree = 0;
+    for (int b = 0; b < m; ++b)
+        if (!((ins >> b) & 1)) t.fz[t.nfree++] = swz_elem(1u << b, elem_bytes) * elem_bytes;
     for (int r = 0; r < (1 << op.k); ++r) {
         uint32_t o = 0;
         for (int j = 0; j < op.k; ++j)
             if ((r >> j) & 1) o |= 1u << lt[j];
-        t.loff[r] = o;
+        t.sl[r] = swz_elem(o | lctrl, elem_bytes) * elem_bytes;
     }
-    if (op.kind == Op::MONO) {
+    const double frac = 1.0 / (double)(1ull << popc(op.ctrl));
+    if (mono) {
         for (int r = 0; r < (1 << op.k); ++r) {
-            t.srcoff[r] = t.loff[op.perm[r]];
+            t.ss[r] = t.sl[op.perm[r]];
             push(mats, op.U[r]);
         }
+        *flops = frac * 6.0 * __builtin_popcount(op.touch) / (double)(1 << op.k);
     } else if (op.k >= 3) {
-        // matrix cores: real embedding W = [[Re U, -Im U], [Im U, Re U]]
+        // matrix cores: real embedding W = [[Re U, -Im U], [Im U, Re U]],
+        // stored in the order the 16x16x4 A operand is read: fragment
+        // (mb, kc) is 64 consecutive values, lane l holding
+        // W[16 mb + l % 16][4 kc + l / 16], so each fragment load is one
+        // contiguous read across the wave.  The pool is in complex entries;
+        // the fragments take 2 D * 2 D reals = 2 D^2 complex slots.
         t.kind = dev::TOP_DENSE_MFMA;
-        const int D = 1 << op.k;
-        for (int i = 0; i < 2 * D; ++i)
-            for (int j = 0; j < 2 * D; ++j) {
-                const cd u = op.U[(size_t)(i % D) * D + (j % D)];
-                double w;
-                if (i < D) w = (j < D) ? u.real() : -u.imag();
-                else w = (j < D) ? u.imag() : u.real();
-                mats.push_back(w);
-            }
+        const int D = 1 << op.k, D2 = 2 * D, MB = D2 / 16, KC = D2 / 4;
+        const std::vector<cd> U = dense_matrix(op);
+        auto w_at = [&](int i, int j) {
+            const cd u = U[(size_t)(i % D) * D + (j % D)];
+            if (i < D) return (j < D) ? u.real() : -u.imag();
+            return (j < D) ? u.imag() : u.real();
+        };
+        for (int mb = 0; mb < MB; ++mb)
+            for (int kc = 0; kc < KC; ++kc)
+                for (int l = 0; l < 64; ++l) mats.push_back(w_at(16 * mb + l % 16, 4 * kc + l / 16));
+        *flops = frac * (8.0 * D - 2.0);
     } else {
-        for (const cd &v : op.U) push(mats, v);
+        for (const cd &v : dense_matrix(op)) push(mats, v);
+        *flops = frac * (8.0 * (1 << op.k) - 2.0);
     }
     return t;
-}
-
-double lds_flops(const dev::TileOp &t) {
-    const double frac = 1.0 / (double)(1ull << __builtin_popcount(t.lctrl));
-    if (t.kind == dev::TOP_DENSE || t.kind == dev::TOP_DENSE_MFMA)
-        return frac * (8.0 * (1 << t.k) - 2.0);
-    return frac * 6.0 * __builtin_popcount(t.touch) / (double)(1 << t.k);
 }
 
 void set_layout(uint32_t regmask, int m, int rb, uint8_t *reg_lbit, uint8_t *thr_lbit) {
@@ -108,9 +128,7 @@ void set_layout(uint32_t regmask, int m, int rb, uint8_t *reg_lbit, uint8_t *thr
 uint32_t remap_offset(uint32_t l, int kept, int elem_bytes) {
     const uint32_t lowm = (1u << kept) - 1;
     const uint32_t h = ((l >> 1) & ~lowm) | (l & lowm);
-    const uint32_t x = elem_bytes == 16 ? (h ^ (((h >> 4) ^ (h >> 8)) & 15u))
-                                        : (h ^ (((h >> 5) ^ (h >> 10)) & 31u));
-    return x * (uint32_t)elem_bytes;
+    return swz_elem(h, elem_bytes) * (uint32_t)elem_bytes;
 }
 
 namespace {
@@ -179,8 +197,10 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
     if (!prog.reg) {
         for (const Op &op : ps.ops) {
             if (op.kind == Op::MONO && op.touch == 0) continue;
-            dev::TileOp t = lds_form(op, li, mats);
-            prog.flops_per_amp += lds_flops(t);
+            double fl = 0.0;
+            dev::TileOp t = lds_form(op, li, mats, elem_bytes, &fl);
+            prog.flops_per_amp += fl;
+            if (t.kind == dev::TOP_DENSE_MFMA) prog.mfma_k = std::max(prog.mfma_k, t.k);
             prog.lops.push_back(t);
         }
         return;
@@ -276,14 +296,15 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         if (it.kind == dev::ROP_DIAG) {
             r.a = op.k;
             r.ctrl = op.ctrl;
-            for (int j = 0; j < op.k; ++j) r.gt[j] = (uint8_t)op.t[j];
+            for (int j = 0; j < op.k; ++j) r.gt[j] = (uint32_t)op.t[j];
             r.mat = (int64_t)(mats.size() / 2);
             for (int e = 0; e < (1 << op.k); ++e) push(mats, op.U[e]);
             prog.flops_per_amp += 6.0 * __builtin_popcount(op.touch) / (double)(1 << op.k) /
                                   (double)(1ull << popc(op.ctrl));
         } else if (it.kind == dev::ROP_LDS) {
-            dev::TileOp t = lds_form(op, li, mats);
-            prog.flops_per_amp += lds_flops(t);
+            double fl = 0.0;
+            dev::TileOp t = lds_form(op, li, mats, elem_bytes, &fl);
+            prog.flops_per_amp += fl;
             r.a = (int32_t)prog.lops.size();
             prog.lops.push_back(t);
         } else {
@@ -332,7 +353,8 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
 }  // namespace qsv
 
 namespace qsv {
-dev::TileOp lower_to_lds(const Op &op, const int *li, std::vector<double> &mats) {
-    return lds_form(op, li, mats);
+dev::TileOp lower_to_lds(const Op &op, const int *li, std::vector<double> &mats, int elem_bytes) {
+    double fl = 0.0;
+    return lds_form(op, li, mats, elem_bytes, &fl);
 }
 }  // namespace qsv

@@ -20,6 +20,7 @@ struct TileProgram {
     uint64_t g_reg[8] = {};             // initial layout as global index bits
     uint64_t g_thr[16] = {};
     int remaps = 0;
+    int mfma_k = 0;                     // widest matrix-core op (LDS kernel)
     double flops_per_amp = 0.0;
 };
 
@@ -39,7 +40,7 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
 uint32_t remap_offset(uint32_t l, int kept, int elem_bytes);
 
 // LDS-kernel form of one op; li maps a global bit position to its tile bit
-// (-1 outside the tile).
-dev::TileOp lower_to_lds(const Op &op, const int *li, std::vector<double> &mats);
+// (-1 outside the tile); elem_bytes is the state's complex size (16 or 8).
+dev::TileOp lower_to_lds(const Op &op, const int *li, std::vector<double> &mats, int elem_bytes);
 
 }  // namespace qsv
