@@ -205,9 +205,10 @@ struct BatchLaunch {
     unsigned int *counter;
     double *out;
     unsigned int grid;
+    int32_t mfma_k;           // widest matrix-core op (0 = none), at most 5
 };
 hipError_t batch_launch(int dtype, const BatchLaunch &L, hipStream_t s);
-int batch_occupancy(int dtype, int mb);   // resident workgroups per CU
+int batch_occupancy(int dtype, int mb, int mfma_k);   // resident workgroups per CU
 
 // Sampling: out_dev[shots] indices.
 size_t sample_workspace_bytes(int nq);

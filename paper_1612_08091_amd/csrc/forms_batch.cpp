@@ -155,6 +155,7 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     std::vector<double> mats;
     std::vector<double> cost(b->count);
     int max_big = 0;
+    int mfma_k = 0;
     for (int i = 0; i < b->count; ++i) {
         const int n = b->nq[i];
         const int m = std::min(n, mb);
@@ -183,6 +184,8 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
             for (const Op &op : p.ops) {
                 if (op.kind == Op::MONO && op.touch == 0) continue;
                 tops.push_back(qsv::lower_to_lds(op, li, mats, b->dtype == QSV_C128 ? 16 : 8));
+                if (tops.back().kind == qsv::dev::TOP_DENSE_MFMA)
+                    mfma_k = std::max(mfma_k, tops.back().k);
             }
             bp.op_count = (int)tops.size() - bp.op_begin;
             nops += bp.op_count;
@@ -220,7 +223,7 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int occ = std::max(1, qsv::dev::batch_occupancy(b->dtype, mb));
+    const int occ = std::max(1, qsv::dev::batch_occupancy(b->dtype, mb, mfma_k));
     const unsigned grid = (unsigned)std::max(1, std::min(cus * occ, b->count));
     const size_t elem = b->dtype == QSV_C128 ? 16 : 8;
     const uint64_t slot = max_big > 0 ? (1ull << max_big) : 1;
@@ -247,6 +250,7 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     L.counter = (unsigned int *)(d + o_ctr);
     L.out = (double *)(d + o_out);
     L.grid = grid;
+    L.mfma_k = mfma_k;
     b->mb = mb;
     b->kfuse = kf;
     if (b->use_graph) {

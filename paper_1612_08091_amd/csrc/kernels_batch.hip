@@ -77,7 +77,7 @@ __device__ __forceinline__ double pauli_partial(const typename VT<R>::T *st, int
     return acc;
 }
 
-template <typename R>
+template <typename R, int KM>
 __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ circuits,
                                                const int32_t *__restrict__ order, int count,
                                                const BatchPass *__restrict__ passes,
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
             for (int p = 0; p < bc.pass_count; ++p) {
                 const BatchPass &bp = passes[bc.pass_begin + p];
                 for (int o = 0; o < bp.op_count; ++o) {
-                    lds_op<R>(tile, n, 0, kIdentityPos, ops[bp.op_begin + o], pool);
+                    lds_op<R, KM>(tile, n, 0, kIdentityPos, ops[bp.op_begin + o], pool);
                     __syncthreads();
                 }
             }
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                     }
                     __syncthreads();
                     for (int o = 0; o < bp.op_count; ++o) {
-                        lds_op<R>(tile, m, base, tpos, ops[bp.op_begin + o], pool);
+                        lds_op<R, KM>(tile, m, base, tpos, ops[bp.op_begin + o], pool);
                         __syncthreads();
                     }
                     for (uint32_t l = tid; l < tsize; l += kNT)
@@ -176,44 +176,47 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
 
 __global__ void k_reset_counter(unsigned int *counter) { *counter = 0u; }
 
-template <typename R>
+template <typename R, int KM>
 static hipError_t batch_t(const BatchLaunch &L, hipStream_t s) {
     using T = typename VT<R>::T;
     const size_t lds = sizeof(T) << L.mb;
     static size_t attr = 0;
     if (attr < lds) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_batch<R>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_batch<R, KM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr = lds;
     }
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, L.counter);
-    hipLaunchKernelGGL((k_batch<R>), dim3(L.grid), dim3(kNT), lds, s, L.circuits, L.order, L.count,
-                       L.passes, L.ops, (const T *)L.pool, L.terms, (T *)L.scratch, L.slot_amps,
-                       L.mb, L.counter, L.out);
+    hipLaunchKernelGGL((k_batch<R, KM>), dim3(L.grid), dim3(kNT), lds, s, L.circuits, L.order,
+                       L.count, L.passes, L.ops, (const T *)L.pool, L.terms, (T *)L.scratch,
+                       L.slot_amps, L.mb, L.counter, L.out);
     return hipGetLastError();
 }
 
+// Kernel variant for the widest matrix-core op of the batch: up to 3 qubits
+// (the autotuned fusion widths) or up to 5 (wider user gates).
 hipError_t batch_launch(int dtype, const BatchLaunch &L, hipStream_t s) {
-    return dtype == 0 ? batch_t<double>(L, s) : batch_t<float>(L, s);
+    if (L.mfma_k > 5) return hipErrorInvalidValue;
+    if (dtype == 0)
+        return L.mfma_k <= 3 ? batch_t<double, 3>(L, s) : batch_t<double, 5>(L, s);
+    return L.mfma_k <= 3 ? batch_t<float, 3>(L, s) : batch_t<float, 5>(L, s);
 }
 
-int batch_occupancy(int dtype, int mb) {
+template <typename R, int KM>
+static int batch_occ_t(int mb) {
+    using T = typename VT<R>::T;
     int blocks = 0;
-    hipError_t e;
-    if (dtype == 0) {
-        (void)hipFuncSetAttribute((const void *)k_batch<double>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(16u << mb));
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<double>, kNT,
-                                                         (size_t)16 << mb);
-    } else {
-        (void)hipFuncSetAttribute((const void *)k_batch<float>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(8u << mb));
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<float>, kNT,
-                                                         (size_t)8 << mb);
-    }
-    if (e != hipSuccess) return 0;
-    return blocks;
+    (void)hipFuncSetAttribute((const void *)k_batch<R, KM>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(T) << mb));
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &blocks, k_batch<R, KM>, kNT, sizeof(T) << mb);
+    return e == hipSuccess ? blocks : 0;
+}
+
+int batch_occupancy(int dtype, int mb, int mfma_k) {
+    if (dtype == 0) return mfma_k <= 3 ? batch_occ_t<double, 3>(mb) : batch_occ_t<double, 5>(mb);
+    return mfma_k <= 3 ? batch_occ_t<float, 3>(mb) : batch_occ_t<float, 5>(mb);
 }
 
 }  // namespace dev
