@@ -129,30 +129,60 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                 const uint32_t *tpos = bp.tpos;
                 const uint32_t tsize = 1u << m;
                 const uint64_t ntiles = 1ull << (n - m);
+                // thread part of local index j0 + tid (used when tsize >= 4 kNT)
+                const uint64_t dep_tid = deposit_bits(tid, tpos, m < 8 ? m : 8);
+                const uint32_t swz_tid = swz<R>(tid);
                 for (uint64_t t = 0; t < ntiles; ++t) {
                     uint64_t base = t;
                     for (int i = 0; i < m; ++i) {
                         const uint64_t lowm = (1ull << tpos[i]) - 1;
                         base = ((base & ~lowm) << 1) | (base & lowm);
                     }
-                    for (uint32_t l = tid; l < tsize; l += kNT) {
-                        const uint64_t gi = base | deposit_bits(l, tpos, m);
-                        T v;
-                        if (p == 0) {       // the first pass starts from |0...0>
-                            v.x = (gi == 0) ? R(1) : R(0);
-                            v.y = R(0);
-                        } else {
-                            v = slot[gi];
+                    // loads go out 4 at a time, before their LDS writes (tiles of
+                    // at least 4 * kNT amplitudes; smaller ones one at a time)
+                    if (tsize < 4 * kNT) {
+                        for (uint32_t l = tid; l < tsize; l += kNT) {
+                            const uint64_t gi = base | deposit_bits(l, tpos, m);
+                            T v;
+                            if (p == 0) {
+                                v.x = (gi == 0) ? R(1) : R(0);
+                                v.y = R(0);
+                            } else {
+                                v = slot[gi];
+                            }
+                            tile[swz<R>(l)] = v;
                         }
-                        tile[swz<R>(l)] = v;
+                    } else for (uint32_t j0 = 0; j0 < tsize; j0 += 4 * kNT) {
+                        T v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const uint64_t gi = base | dep_tid | deposit_bits(j0 + u * kNT, tpos, m);
+                            if (p == 0) {   // the first pass starts from |0...0>
+                                v[u].x = (gi == 0) ? R(1) : R(0);
+                                v[u].y = R(0);
+                            } else {
+                                v[u] = slot[gi];
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) tile[swz_tid ^ swz<R>(j0 + u * kNT)] = v[u];
                     }
                     __syncthreads();
                     for (int o = 0; o < bp.op_count; ++o) {
                         lds_op<R, KM>(tile, m, base, tpos, ops[bp.op_begin + o], pool);
                         __syncthreads();
                     }
-                    for (uint32_t l = tid; l < tsize; l += kNT)
-                        slot[base | deposit_bits(l, tpos, m)] = tile[swz<R>(l)];
+                    if (tsize < 4 * kNT) {
+                        for (uint32_t l = tid; l < tsize; l += kNT)
+                            slot[base | deposit_bits(l, tpos, m)] = tile[swz<R>(l)];
+                    } else for (uint32_t j0 = 0; j0 < tsize; j0 += 4 * kNT) {
+                        T v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) v[u] = tile[swz_tid ^ swz<R>(j0 + u * kNT)];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            slot[base | dep_tid | deposit_bits(j0 + u * kNT, tpos, m)] = v[u];
+                    }
                     __syncthreads();
                 }
             }
