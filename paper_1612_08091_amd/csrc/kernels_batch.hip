@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                                                uint64_t slot_amps, int mb,
                                                unsigned int *counter, double *out) {
     using T = typename VT<R>::T;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);
     __shared__ int s_next;
     __shared__ double sh[16];

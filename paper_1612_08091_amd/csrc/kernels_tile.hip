@@ -34,9 +34,11 @@ __global__ __launch_bounds__(kNT) void k_tile_lds(typename VT<R>::T *__restrict_
                                                   const typename VT<R>::T *__restrict__ pool,
                                                   unsigned int *__restrict__ counter) {
     using T = typename VT<R>::T;
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ unsigned int s_tile;
+    // the tile at the start of dynamic LDS (address 0), the tile counter's
+    // broadcast slot right after it
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);
+    unsigned int &s_tile = *reinterpret_cast<unsigned int *>(smem_raw + (sizeof(T) << ta.m));
     const int m = ta.m;
     const uint32_t tsize = 1u << m;
     const uint32_t tid = threadIdx.x;
@@ -399,7 +401,7 @@ static hipError_t launch_lds_t(void *psi, const TileArgs &ta, const TileOp *ops,
     const int max_bits = tile_pass_max_bits(sizeof(R) == 8 ? 0 : 1);
     static bool attr = false;
     if (!attr) {
-        hipError_t e = set_lds_attr(k_tile_lds<R, KM>, sizeof(T) << max_bits);
+        hipError_t e = set_lds_attr(k_tile_lds<R, KM>, (sizeof(T) << max_bits) + 16);
         if (e != hipSuccess) return e;
         attr = true;
     }
@@ -408,7 +410,7 @@ static hipError_t launch_lds_t(void *psi, const TileArgs &ta, const TileOp *ops,
     // resident workgroups per compute unit for each tile size
     static int per_cu[16] = {0};
     static int cus = 0;
-    const size_t lds = sizeof(T) << ta.m;
+    const size_t lds = (sizeof(T) << ta.m) + 16;   // tile + counter slot
     if (per_cu[ta.m] == 0) {
         int dev = 0, occ = 0;
         hipError_t e = hipGetDevice(&dev);

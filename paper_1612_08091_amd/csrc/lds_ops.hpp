@@ -58,10 +58,29 @@ __device__ __forceinline__ uint32_t xor_parts(uint32_t x, const uint32_t *parts,
     return o;
 }
 
+// The same over N parts read once into registers (parts beyond nbits are
+// zero), so a loop over x costs no memory reads.
+template <int N> struct Parts {
+    uint32_t v[N];
+    __device__ __forceinline__ Parts(const uint32_t *parts, int nbits) {
+#pragma unroll
+        for (int b = 0; b < N; ++b) v[b] = b < nbits ? parts[b] : 0u;
+    }
+    __device__ __forceinline__ uint32_t of(uint32_t x) const {
+        uint32_t o = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) o ^= (0u - ((x >> b) & 1u)) & v[b];
+        return o;
+    }
+};
+
 // ----------------------------------------------------- ops on an LDS tile
 // The tile is addressed in bytes through the op's precomputed offsets.
 // Group g = threadIdx.x + kNT * it: the thread part of its address is fixed
 // for the op, the iteration part is uniform.
+// (Op fields and matrix entries are read into registers before the loops:
+// inside them, the LDS stores would otherwise force the compiler to read
+// them again on every iteration.)
 template <typename R, int K>
 __device__ __forceinline__ void lds_dense(unsigned char *tb, const TileOp &op,
                                           const typename VT<R>::T *__restrict__ mat) {
@@ -71,29 +90,26 @@ __device__ __forceinline__ void lds_dense(unsigned char *tb, const TileOp &op,
     const uint32_t ngroups = 1u << nfree;
     const uint32_t tid = threadIdx.x;
     const uint32_t toff = xor_parts(tid, op.fz, nfree < 8 ? nfree : 8);
+    const Parts<8> hi(op.fz + 8, nfree - 8);
+    uint32_t sl[D];
+    T u[D * D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) sl[r] = op.sl[r];
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) u[e] = mat[e];
     for (uint32_t it = 0; it * kNT < ngroups; ++it) {
         if (tid >= ngroups) break;   // fewer groups than threads
-        const uint32_t go = toff ^ xor_parts(it, op.fz + 8, nfree > 8 ? nfree - 8 : 0);
+        const uint32_t go = toff ^ hi.of(it);
         T x[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) x[c] = *reinterpret_cast<const T *>(tb + (go ^ op.sl[c]));
+        for (int c = 0; c < D; ++c) x[c] = *reinterpret_cast<const T *>(tb + (go ^ sl[c]));
         // the whole group is in registers, so rows can be written one by one
-        if constexpr (K <= 3) {
 #pragma unroll
-            for (int r = 0; r < D; ++r) {
-                T y = cmul(mat[r * D], x[0]);
+        for (int r = 0; r < D; ++r) {
+            T y = cmul(u[r * D], x[0]);
 #pragma unroll
-                for (int c = 1; c < D; ++c) y = cmadd(y, mat[r * D + c], x[c]);
-                *reinterpret_cast<T *>(tb + (go ^ op.sl[r])) = y;
-            }
-        } else {
-#pragma unroll 1
-            for (int r = 0; r < D; ++r) {
-                T y = cmul(mat[r * D], x[0]);
-#pragma unroll
-                for (int c = 1; c < D; ++c) y = cmadd(y, mat[r * D + c], x[c]);
-                *reinterpret_cast<T *>(tb + (go ^ op.sl[r])) = y;
-            }
+            for (int c = 1; c < D; ++c) y = cmadd(y, u[r * D + c], x[c]);
+            *reinterpret_cast<T *>(tb + (go ^ sl[r])) = y;
         }
     }
 }
@@ -105,19 +121,32 @@ __device__ __forceinline__ void lds_mono(unsigned char *tb, const TileOp &op,
     constexpr int D = 1 << K;
     const int nfree = op.nfree;
     const uint32_t ngroups = 1u << nfree;
-    const uint32_t tid = threadIdx.x, touch = op.touch;
+    const uint32_t tid = threadIdx.x;
     const uint32_t toff = xor_parts(tid, op.fz, nfree < 8 ? nfree : 8);
+    const Parts<8> hi(op.fz + 8, nfree - 8);
+    // untouched rows read and write their own amplitude with phase 1
+    uint32_t sl[D], ss[D];
+    T v[D];
+    const uint32_t touch = op.touch;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        const bool t = (touch >> r) & 1;
+        sl[r] = op.sl[r];
+        ss[r] = t ? op.ss[r] : sl[r];
+        T one;
+        one.x = R(1);
+        one.y = R(0);
+        v[r] = t ? val[r] : one;
+    }
     for (uint32_t it = 0; it * kNT < ngroups; ++it) {
         if (tid >= ngroups) break;
-        const uint32_t go = toff ^ xor_parts(it, op.fz + 8, nfree > 8 ? nfree - 8 : 0);
+        const uint32_t go = toff ^ hi.of(it);
         T y[D];
 #pragma unroll
         for (int r = 0; r < D; ++r)
-            if ((touch >> r) & 1)
-                y[r] = cmul(val[r], *reinterpret_cast<const T *>(tb + (go ^ op.ss[r])));
+            y[r] = cmul(v[r], *reinterpret_cast<const T *>(tb + (go ^ ss[r])));
 #pragma unroll
-        for (int r = 0; r < D; ++r)
-            if ((touch >> r) & 1) *reinterpret_cast<T *>(tb + (go ^ op.sl[r])) = y[r];
+        for (int r = 0; r < D; ++r) *reinterpret_cast<T *>(tb + (go ^ sl[r])) = y[r];
     }
 }
 
@@ -177,8 +206,9 @@ __device__ __forceinline__ void lds_dense_mfma(unsigned char *tb, const TileOp &
             out_off[mb][r] = op.sl[row & (D - 1)] | (row >= D ? (uint32_t)sizeof(R) : 0u);
         }
     const R *wl = W + lane;
+    const Parts<12> hi(op.fz + 4, nfree - 4);
     for (uint32_t cb = wave; cb < ncb; cb += nwaves) {
-        const uint32_t go = loff ^ xor_parts(cb, op.fz + 4, nfree > 4 ? nfree - 4 : 0);
+        const uint32_t go = loff ^ hi.of(cb);
         V acc[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) acc[mb] = V{0, 0, 0, 0};
