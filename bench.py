@@ -40,8 +40,8 @@ FP64_PEAK = 78.6e12        # MI355X FP64 (vector and matrix), flop/s
 # in the same runs (4 GiB read + 4 GiB write: FETCH_SIZE reads half the bytes,
 # WRITE_SIZE all of them).  Valid only for the sources they were taken with:
 # the digest below covers every file that shapes the kernel or its launches.
-TRAFFIC = {"kernel": "k_tile_reg<double,4,8>", "fetch_kib": 8396087.9, "write_kib": 19028467.5,
-           "fetch_scale": 2.0, "write_scale": 1.0, "digest": "2acc30e0ed23f67b"}
+TRAFFIC = {"kernel": "k_tile_reg<double,4,8>", "fetch_kib": 8389730.0, "write_kib": 17287610.0,
+           "fetch_scale": 2.0, "write_scale": 1.0, "digest": "c0203f026667bcdb"}
 TRAFFIC_SOURCES = ("paper_1612_08091_amd/csrc/kernels_tile.hip",
                    "paper_1612_08091_amd/csrc/lds_ops.hpp",
                    "paper_1612_08091_amd/csrc/device.hpp",
@@ -311,6 +311,8 @@ def main():
     ap.add_argument("--qubits", type=int, default=30)
     ap.add_argument("--mode", default="tiled")
     ap.add_argument("--k-max", type=int, default=2)
+    ap.add_argument("--dtype", default="c128", choices=["c128", "c64"],
+                    help="state type of the main leg (the workload's is complex128)")
     ap.add_argument("--reg-bits", type=int, default=0)
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -347,7 +349,7 @@ def main():
     u = W.streams(1)[3].random(1000)
     log("bench: %d qubits, %d gates, mode=%s k_max=%d" % (n, len(circ.gates), args.mode, args.k_max))
 
-    main_leg = run_leg(circ, ham, u, args.steps, args.warmup, "c128", args.mode, args.k_max,
+    main_leg = run_leg(circ, ham, u, args.steps, args.warmup, args.dtype, args.mode, args.k_max,
                        args.tile_bits, reg_bits=args.reg_bits)
     log("main leg: %.2f ms/step" % main_leg["ms_per_step"])
     steps = args.steps
@@ -362,20 +364,29 @@ def main():
     per_launch_bytes = kbytes / max(launches, 1)
     avg_ms = ms / max(launches, 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+    rname = "double" if args.dtype == "c128" else "float"
+    default_cfg = (args.dtype == "c128" and args.mode == "tiled" and args.k_max == 2
+                   and args.reg_bits in (0, 4) and args.tile_bits in (0, 12))
+    if dom != "tile":
+        kname = "k_dense<%s,1>" % rname
+    elif args.k_max <= 2:
+        kname = "k_tile_reg<%s,%d,8>" % (rname, args.reg_bits or 4)
+    else:
+        kname = "k_tile_lds<%s,k<=%d> (MFMA for k>=3)" % (rname, args.k_max)
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK,
-                "traffic": measured_traffic() if dom == "tile" and (args.reg_bits or 4) == 4 else None,
-                "kernel": ("k_tile_reg<double,%d,8>" % (args.reg_bits or 4)) if dom == "tile"
-                          else "k_dense<double,1>",
+                "traffic": measured_traffic() if default_cfg else None,
+                "kernel": kname,
                 "launches": launches, "avg_ms": avg_ms, "alg_bytes_per_launch": per_launch_bytes}
     if dom == "tile" and avg_ms > 0:
-        # the same launches against the FP64 arithmetic peak (the pass's
-        # arithmetic intensity sits close to the FP64 ridge point)
+        # the same launches against the vector-ALU peak (FP64, and FP32 with
+        # packed math off, are both 78.6 TFLOP/s): the pass's arithmetic
+        # intensity sits close to the FP64 ridge point
         fl = st["alg_flops"] / max(launches, 1)
-        roofline["fp64_alu"] = {"achieved_TFLOPs": fl / (avg_ms * 1e-3) / 1e12,
-                                "peak_TFLOPs": FP64_PEAK / 1e12,
-                                "frac": fl / (avg_ms * 1e-3) / FP64_PEAK,
-                                "alg_flops_per_launch": fl}
+        roofline["alu"] = {"achieved_TFLOPs": fl / (avg_ms * 1e-3) / 1e12,
+                           "peak_TFLOPs": FP64_PEAK / 1e12,
+                           "frac": fl / (avg_ms * 1e-3) / FP64_PEAK,
+                           "alg_flops_per_launch": fl}
 
     extra = {}
     if not args.no_extra_legs:
@@ -427,11 +438,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.dtype == "c128" else "f32",
         "data": "synthetic",
         "config": {"workload": "%d-qubit random circuit, 40 layers of Haar 1q + CNOT brick "
-                               "(%d gates), complex128 from |0..0>, then norm, 8-term <H>, "
-                               "1000 samples" % (n, len(circ.gates)),
+                               "(%d gates), %s from |0..0>, then norm, 8-term <H>, "
+                               "1000 samples" % (n, len(circ.gates),
+                                                 "complex128" if args.dtype == "c128" else "complex64"),
                    "n_qubits": n, "gates": len(circ.gates), "mode": args.mode,
                    "k_max": args.k_max, "tile_bits": args.tile_bits or 12,
                    "reg_bits": args.reg_bits or 4},
