@@ -239,6 +239,31 @@ def form_fusion_qft(n: int = 30):
     return out
 
 
+def form_simcomparison(n: int = 30):
+    """The paper's own simulator benchmark circuit (Sec. 4.3.2): H on every
+    qubit, a chain of controlled Rz, H on every qubit, at 30 qubits complex128,
+    fused tile passes versus per gate.  The paper reports only a relative
+    speed-up over its predecessor for this circuit, no absolute figure."""
+    import workloads as W
+    from paper_1612_08091_amd import qsv as Q
+    circ = W.simcomparison(n, np.random.default_rng(W.SEED_BASE + 5))
+    out = {"workload": "%d-qubit H-transform, %d-gate CRz chain, H-transform (%d gates), "
+                       "complex128" % (n, n - 1, len(circ.gates))}
+    for mode, k in (("tiled", 2), ("pergate", 1)):
+        sim = Q.Simulator(n_max=n, dtype="c128", mode=mode, k_max=k, timing=True)
+        sim.allocate(n)
+        _timed_circuit(sim, circ)
+        sim.reset_stats()
+        t = _timed_circuit(sim, circ)
+        st = sim.stats()
+        out[mode] = {"s_per_circuit": t, "amp_gate_per_s": len(circ.gates) * float(1 << n) / t,
+                     "pct_hbm_peak": st["alg_bytes"] / t / HBM_PEAK,
+                     "passes_or_kernels": st["passes"] or st["kernels"]}
+        sim.close()
+        log("  simcomparison %s: %.3f s" % (mode, t))
+    return out
+
+
 def form_batched():
     """Config 3: 4096 HEA circuits (8..20 qubits, depth 6) with 64-term Pauli
     sums, complex64, one persistent graph-captured launch per evaluation."""
@@ -415,6 +440,8 @@ def main():
     if not args.no_forms:
         extra["fusion_and_qft_30q"] = form_fusion_qft(n)
         log("fusion / QFT form done")
+        extra["paper_benchmark_circuit_30q"] = form_simcomparison(n)
+        log("paper benchmark circuit form done")
         extra["precision_32q"] = form_precision()
         log("precision form done")
         extra["batched"] = form_batched()

@@ -410,3 +410,38 @@ def test_config2_32q_c64_then_inverse_and_measure():
     amp = s.get_amplitudes([0, (1 << n) - 1])
     assert abs(abs(amp[want]) - 1.0) <= 1e-6 and abs(amp[1 - want]) == 0.0
     s.close()
+
+
+# ------------------------------------- the paper's benchmark circuit (Sec. 4.3.2)
+def _fwht(a):
+    """Unnormalised Walsh-Hadamard transform: out_y = sum_x (-1)^popcount(x & y) a_x."""
+    h = 1
+    while h < a.size:
+        v = a.reshape(-1, 2, h)
+        a = np.stack((v[:, 0, :] + v[:, 1, :], v[:, 0, :] - v[:, 1, :]), axis=1).reshape(-1)
+        h *= 2
+    return a
+
+
+@pytest.mark.parametrize("mode,k_max", [("tiled", 2), ("pergate", 1)])
+def test_simcomparison_22q_walsh_closed_form(mode, k_max):
+    """H on every qubit, a chain of controlled Rz, H on every qubit:
+    psi_y = 2^-n sum_x e^{i phi(x)} (-1)^{x.y}, with phi(x) collecting
+    +-theta_i / 2 from every control bit x_i = 1 (the sign is the target bit)."""
+    n = 22
+    circ = W.simcomparison(n, np.random.default_rng(7))
+    log("case simcomparison", n, mode)
+    s = make(n, mode=mode, k_max=k_max)
+    s.run(circ)
+    got = s.get_state()
+    s.close()
+    xs = np.arange(1 << n, dtype=np.int64)
+    phi = np.zeros(1 << n)
+    for g in circ.gates:
+        if g.name == "crz":
+            c, t = g.controls[0], g.targets[0]
+            half = np.angle(g.matrix[1, 1])           # Rz(theta)[1,1] = e^{i theta/2}
+            on = ((xs >> c) & 1) == 1
+            phi += np.where(on, np.where(((xs >> t) & 1) == 1, half, -half), 0.0)
+    want = _fwht(np.exp(1j * phi)) / float(1 << n)
+    check_c128(got, want, 1e-12)
