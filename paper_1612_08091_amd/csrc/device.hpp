@@ -161,11 +161,15 @@ hipError_t dot_re(int dtype, const void *a, const void *b, uint64_t dim, double 
 int adjoint_blocks(uint64_t npairs);
 // Reverse step for exp(-i theta P/2), P = X/Y/Z (axis 1/2/3), on the pairs
 // given by ia (target bit cleared, controls set) and partner offset toff;
-// c = cos(theta/2), sn = sin(theta/2).  partial[adjoint_blocks(npairs)].
+// c = cos(theta/2), sn = sin(theta/2).  Runs nb workgroups and writes
+// partial[0..nb) (one sum per workgroup, zero for those without pairs), so
+// that rows of rotations with and without controls have the same width.
 hipError_t adjoint_rotation(int dtype, void *psi, void *phi, uint64_t npairs,
                             const IndexArgs &ia, uint64_t toff, int axis, double c, double sn,
-                            double *partial, hipStream_t s);
-hipError_t grad_finish(const double *partial, int ng, int nb, const int32_t *param, double *grad,
+                            double *partial, int nb, hipStream_t s);
+// grad[p] = sum over rotations g with param[g] = p of sum_b partial[g * nb + b]
+// (the rows are summed in place; their first entries are overwritten).
+hipError_t grad_finish(double *partial, int ng, int nb, const int32_t *param, double *grad,
                        int nparams, hipStream_t s);
 
 // ---------------------------------------------------------------- batched

@@ -164,21 +164,24 @@ __global__ __launch_bounds__(kAT) void k_adj_rot(typename VA<R>::T *__restrict__
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
-// grad[param[g]] += sum_b partial[g * nb + b] for the ng rotation gates, in
-// reverse gate order (one workgroup).
-__global__ __launch_bounds__(kAT) void k_grad_finish(const double *partial, int ng, int nb,
-                                                     const int32_t *param, double *grad,
-                                                     int nparams) {
+// Row sums of the partials, one workgroup per rotation, written in place to
+// the row's first entry.
+__global__ __launch_bounds__(kAT) void k_grad_rows(double *partial, int nb) {
     __shared__ double sh[16];
-    for (int p = threadIdx.x; p < nparams; p += blockDim.x) grad[p] = 0.0;
-    __syncthreads();
-    for (int g = 0; g < ng; ++g) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partial[(size_t)g * nb + b];
-        acc = bsum(acc, sh);
-        if (threadIdx.x == 0) grad[param[g]] += acc;
-        __syncthreads();
-    }
+    double *row = partial + (size_t)blockIdx.x * nb;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += row[b];
+    acc = bsum(acc, sh);
+    if (threadIdx.x == 0) row[0] = acc;
+}
+
+// grad[param[g]] += row sum g, for the ng rotations in reverse gate order
+// (one thread: a fixed summation order for parameters shared by gates).
+__global__ void k_grad_finish(const double *partial, int ng, int nb, const int32_t *param,
+                              double *grad, int nparams) {
+    if (threadIdx.x != 0) return;
+    for (int p = 0; p < nparams; ++p) grad[p] = 0.0;
+    for (int g = 0; g < ng; ++g) grad[param[g]] += partial[(size_t)g * nb];
 }
 
 static unsigned adj_grid(uint64_t work) {
@@ -217,8 +220,10 @@ hipError_t dot_re(int dtype, const void *a, const void *b, uint64_t dim, double 
 
 hipError_t adjoint_rotation(int dtype, void *psi, void *phi, uint64_t npairs,
                             const IndexArgs &ia, uint64_t toff, int axis, double c, double sn,
-                            double *partial, hipStream_t s) {
-    const unsigned g = adj_grid(npairs);
+                            double *partial, int nb, hipStream_t s) {
+    // nb workgroups whatever npairs is: every entry of the row is written
+    if (nb < 1) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)nb;
     if (dtype == 0)
         hipLaunchKernelGGL(k_adj_rot<double>, dim3(g), dim3(kAT), 0, s, (double2 *)psi,
                            (double2 *)phi, npairs, ia, toff, axis, c, sn, partial);
@@ -228,9 +233,10 @@ hipError_t adjoint_rotation(int dtype, void *psi, void *phi, uint64_t npairs,
     return hipGetLastError();
 }
 
-hipError_t grad_finish(const double *partial, int ng, int nb, const int32_t *param, double *grad,
+hipError_t grad_finish(double *partial, int ng, int nb, const int32_t *param, double *grad,
                        int nparams, hipStream_t s) {
-    hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(kAT), 0, s, partial, ng, nb, param, grad,
+    if (ng > 0) hipLaunchKernelGGL(k_grad_rows, dim3(ng), dim3(kAT), 0, s, partial, nb);
+    hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(64), 0, s, partial, ng, nb, param, grad,
                        nparams);
     return hipGetLastError();
 }

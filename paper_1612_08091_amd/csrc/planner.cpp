@@ -245,44 +245,65 @@ std::vector<Op> fuse(const std::vector<Op> &ops, int k_max) {
 }
 
 // ---------------------------------------------------------- pass planning
-std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_bits,
-                              int k_max) {
-    std::vector<Pass> passes;
-    if (ops.empty()) return passes;
+std::vector<PlanGroup> plan_groups(const std::vector<PlanItem> &items, int n, int m,
+                                   int low_bits) {
+    std::vector<PlanGroup> groups;
+    if (items.empty()) return groups;
     const uint64_t all_bits = (n >= 64) ? ~0ull : ((1ull << n) - 1);
     if (n <= m) {
-        Pass p;
-        p.tile = all_bits;
-        p.ops = fuse_impl(ops, k_max, all_bits);
-        passes.push_back(std::move(p));
-        return passes;
+        PlanGroup g;
+        g.tile = all_bits;
+        for (int i = 0; i < (int)items.size(); ++i) g.idx.push_back(i);
+        groups.push_back(std::move(g));
+        return groups;
     }
     const int L = std::max(0, std::min(low_bits, m - kMaxK));
     const uint64_t low = (1ull << L) - 1;
-    std::vector<Op> remaining = ops;
+    std::vector<int> remaining(items.size());
+    for (int i = 0; i < (int)items.size(); ++i) remaining[i] = i;
     while (!remaining.empty()) {
         uint64_t tile = low;
-        std::vector<Op> in_pass, deferred;
+        std::vector<int> in_pass, deferred;
         uint64_t dmix = 0, dall = 0;
-        for (Op &op : remaining) {
-            const uint64_t om = op.mixing(), oa = op.qubits();
-            const bool blocked = !commute_masks(dmix, dall, om, oa);
-            if (!blocked && popc(tile | om) <= m) {
-                tile |= om;
-                in_pass.push_back(std::move(op));
+        for (int i : remaining) {
+            const PlanItem &it = items[i];
+            const bool blocked = !commute_masks(dmix, dall, it.mix, it.all);
+            if (!blocked && popc(tile | it.need) <= m) {
+                tile |= it.need;
+                in_pass.push_back(i);
             } else {
-                deferred.push_back(std::move(op));
-                dmix |= om;
-                dall |= oa;
+                deferred.push_back(i);
+                dmix |= it.mix;
+                dall |= it.all;
             }
         }
         // Fill the tile up to m bits with the lowest free positions.
         for (int p = 0; p < n && popc(tile) < m; ++p) tile |= 1ull << p;
-        Pass ps;
-        ps.tile = tile;
-        ps.ops = fuse_impl(in_pass, k_max, tile);
-        passes.push_back(std::move(ps));
+        PlanGroup g;
+        g.tile = tile;
+        g.idx = std::move(in_pass);
+        groups.push_back(std::move(g));
         remaining.swap(deferred);
+    }
+    return groups;
+}
+
+std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_bits,
+                              int k_max) {
+    std::vector<PlanItem> items(ops.size());
+    for (size_t i = 0; i < ops.size(); ++i) {
+        items[i].need = items[i].mix = ops[i].mixing();
+        items[i].all = ops[i].qubits();
+    }
+    std::vector<Pass> passes;
+    for (const PlanGroup &g : plan_groups(items, n, m, low_bits)) {
+        std::vector<Op> in_pass;
+        in_pass.reserve(g.idx.size());
+        for (int i : g.idx) in_pass.push_back(ops[i]);
+        Pass ps;
+        ps.tile = g.tile;
+        ps.ops = fuse_impl(in_pass, k_max, g.tile);
+        passes.push_back(std::move(ps));
     }
     return passes;
 }

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/qsv.h"
+#include "adjoint_tile.hpp"
 #include "device.hpp"
 #include "qsv_internal.hpp"
 #include "tileprog.hpp"
@@ -1129,6 +1130,196 @@ qsv_status run_ops(qsv_sim *s, const std::vector<Op> &ops) {
     return run_tile_passes(s, qsv::plan_tiled(ops, s->n, m, s->opt.k_max));
 }
 
+// Tile bits of the tiled reverse sweep: two tiles (psi, phi) per workgroup,
+// sized so that two workgroups share a compute unit's LDS by default.
+int adjoint_tile_bits(const qsv_sim *s, int n) {
+    const int mmax = s->opt.dtype == QSV_C128 ? 12 : 13;
+    int m = s->opt.tile_bits > 0 ? s->opt.tile_bits : (s->opt.dtype == QSV_C128 ? 11 : 12);
+    return std::max(1, std::min({m, mmax, n}));
+}
+
+// The reverse sweep as LDS tile passes.  Steps are U_g^dagger in reverse
+// gate order; rotation g keeps its slot (its index in reverse order) for the
+// partial sums.  Steps move across each other only where the planner's
+// commutation test allows; a rotation's generator commutes with everything
+// its gate commutes with (diagonal on shared qubits, or disjoint), so moving
+// steps leaves every recorded inner product unchanged.  Rotations that follow
+// each other in a pass on the same target with the same controls become one
+// chain step (up to kAdjChain), so their pairs pass through LDS once.
+qsv_status adjoint_reverse_tiled(qsv_sim *s, const std::vector<Gate> &gates,
+                                 const std::vector<int> &axis, const double *params,
+                                 const std::vector<int> &param, void *psi, void *phi,
+                                 double *partial, int grid, int mfma_k) {
+    using qsv::dev::AdjOp;
+    const int n = s->n;
+    const int m = adjoint_tile_bits(s, n);
+    std::vector<Op> steps;
+    std::vector<int> saxis, sslot;
+    std::vector<double> stheta;
+    std::vector<qsv::PlanItem> items;
+    int slot = 0;
+    for (int g = (int)gates.size() - 1; g >= 0; --g) {
+        const Gate &gt = gates[g];
+        Op op;
+        qsv::PlanItem it;
+        if (axis[g]) {
+            // addressing only: a dense one-target op on the gate's qubits
+            op.kind = Op::DENSE;
+            op.k = 1;
+            op.t[0] = gt.t[0];
+            op.ctrl = gt.ctrl;
+            op.U = gt.U;
+            it.need = 1ull << gt.t[0];
+            it.mix = axis[g] == QSV_OP_RZ ? 0 : it.need;
+            it.all = it.need | gt.ctrl;
+            sslot.push_back(slot++);
+            stheta.push_back(params[param[g]]);
+        } else {
+            const int D = 1 << gt.k;
+            Gate d = gt;
+            for (int r = 0; r < D; ++r)
+                for (int c = 0; c < D; ++c)
+                    d.U[(size_t)r * D + c] = std::conj(gt.U[(size_t)c * D + r]);
+            if (!qsv::canonicalize(d, op)) continue;
+            it.need = it.mix = op.mixing();
+            it.all = op.qubits();
+            sslot.push_back(-1);
+            stheta.push_back(0.0);
+        }
+        saxis.push_back(axis[g]);
+        steps.push_back(std::move(op));
+        items.push_back(it);
+    }
+    const std::vector<qsv::PlanGroup> groups = qsv::plan_groups(items, n, m, 3);
+    struct Launch {
+        int group;
+        size_t first, count;
+        int nrot;
+    };
+    std::vector<double> mats;
+    std::vector<AdjOp> aops;
+    std::vector<Launch> launches;
+    for (int gi = 0; gi < (int)groups.size(); ++gi) {
+        int li[64];
+        int c = 0;
+        for (int p = 0; p < 64; ++p) li[p] = ((groups[gi].tile >> p) & 1) ? c++ : -1;
+        Launch L{gi, aops.size(), 0, 0};
+        int prev = -1;   // step index of the launch's last op if it is a chain
+        for (int i : groups[gi].idx) {
+            const bool rot = sslot[i] >= 0;
+            if (rot && L.nrot == qsv::dev::kAdjMaxRot) {
+                launches.push_back(L);
+                L = Launch{gi, aops.size(), 0, 0};
+                prev = -1;
+            }
+            if (rot && prev >= 0 && aops.back().nsub < qsv::dev::kAdjChain &&
+                steps[prev].t[0] == steps[i].t[0] && steps[prev].ctrl == steps[i].ctrl) {
+                AdjOp &a = aops.back();
+                const int j = a.nsub++;
+                a.axis[j] = saxis[i];
+                a.lslot[j] = L.nrot++;
+                a.gslot[j] = sslot[i];
+                a.c[j] = std::cos(stheta[i] / 2);
+                a.s[j] = std::sin(stheta[i] / 2);
+                continue;
+            }
+            AdjOp a{};
+            const Op &st = steps[i];
+            bool outside = st.kind == Op::MONO && st.diag;
+            for (int j = 0; j < st.k; ++j)
+                if (li[st.t[j]] >= 0) outside = false;
+            if (outside) {
+                // diagonal, all targets outside the tile: a phase per tile
+                const int eb = (int)s->elem();
+                qsv::dev::TileOp &t = a.op;
+                t.k = st.k;
+                t.touch = st.touch;
+                for (int j = 0; j < st.k; ++j) t.gt[j] = (uint32_t)st.t[j];
+                uint32_t lctrl = 0;
+                for (int p = 0; p < 64; ++p)
+                    if ((st.ctrl >> p) & 1) {
+                        if (li[p] >= 0) lctrl |= 1u << li[p];
+                        else t.ectrl |= 1ull << p;
+                    }
+                const int mt = popc(groups[gi].tile);
+                for (int b = 0; b < mt; ++b)
+                    if (!((lctrl >> b) & 1)) t.fz[t.nfree++] = qsv::swz_elem(1u << b, eb) * eb;
+                t.sl[0] = qsv::swz_elem(lctrl, eb) * eb;
+                t.mat = (int64_t)(mats.size() / 2);
+                for (int r = 0; r < (1 << st.k); ++r) {
+                    mats.push_back(st.U[r].real());
+                    mats.push_back(st.U[r].imag());
+                }
+                a.kind = qsv::dev::ADJ_PHASE;
+                aops.push_back(a);
+                ++L.count;
+                prev = -1;
+                continue;
+            }
+            a.op = qsv::lower_to_lds(st, li, mats, (int)s->elem());
+            if (rot) {
+                a.kind = qsv::dev::ADJ_ROT;
+                a.nsub = 1;
+                a.axis[0] = saxis[i];
+                a.lslot[0] = L.nrot++;
+                a.gslot[0] = sslot[i];
+                a.c[0] = std::cos(stheta[i] / 2);
+                a.s[0] = std::sin(stheta[i] / 2);
+                prev = i;
+            } else {
+                a.kind = qsv::dev::ADJ_APPLY;
+                prev = -1;
+            }
+            aops.push_back(a);
+            ++L.count;
+        }
+        if (L.count) launches.push_back(L);
+    }
+    if (launches.empty()) return QSV_OK;
+    const size_t a_bytes = (aops.size() * sizeof(AdjOp) + 255) & ~size_t(255);
+    const size_t nmat = mats.size();
+    const size_t mat_bytes = s->opt.dtype == QSV_C128 ? nmat * sizeof(double) : nmat * sizeof(float);
+    std::vector<unsigned char> host(a_bytes + mat_bytes + 16, 0);
+    std::memcpy(host.data(), aops.data(), aops.size() * sizeof(AdjOp));
+    if (s->opt.dtype == QSV_C128) {
+        if (nmat) std::memcpy(host.data() + a_bytes, mats.data(), mat_bytes);
+    } else {
+        float *f = reinterpret_cast<float *>(host.data() + a_bytes);
+        for (size_t i = 0; i < nmat; ++i) f[i] = (float)mats[i];
+    }
+    void *dpool = nullptr;
+    QSV_TRY(stage(s, host.data(), host.size(), &dpool));
+    const AdjOp *daops = reinterpret_cast<const AdjOp *>(dpool);
+    const void *dmat = (const unsigned char *)dpool + a_bytes;
+    for (const Launch &L : launches) {
+        const uint64_t tile = groups[L.group].tile;
+        qsv::dev::TileArgs ta{};
+        ta.m = popc(tile);
+        ta.nq = n;
+        ta.tile_pos_n = ta.m;
+        ta.n_ops = (int)L.count;
+        int c = 0;
+        for (int p = 0; p < 64; ++p)
+            if ((tile >> p) & 1) ta.tpos[c++] = (uint32_t)p;
+        ta.n_tiles = 1ull << (n - ta.m);
+        ta.mfma_k = mfma_k;
+        for (int i = 0; i < 64 && (i << 8) < (1 << ta.m); ++i) {
+            uint64_t d = 0;
+            for (int b = 8; b < ta.m; ++b)
+                if (((i << 8) >> b) & 1) d |= 1ull << ta.tpos[b];
+            ta.dep_hi[i] = d;
+        }
+        const int tok = tbegin(s);
+        QSV_HIP(s, qsv::dev::adjoint_tile_pass(s->opt.dtype, psi, phi, ta, daops + L.first, dmat,
+                                               L.nrot, partial, grid, s->stream));
+        tend(s, tok, QSV_K_TILE, 4.0 * (double)s->dim() * s->elem());
+        if (log_level() >= 2)
+            std::fprintf(stderr, "qsv: adjoint pass tile=%#llx m=%d steps=%zu rotations=%d\n",
+                         (unsigned long long)tile, ta.m, L.count, L.nrot);
+    }
+    return QSV_OK;
+}
+
 }  // namespace
 
 extern "C" qsv_status qsv_adjoint_gradient(qsv_sim *s, const qsv_circuit *circ,
@@ -1159,15 +1350,30 @@ extern "C" qsv_status qsv_adjoint_gradient(qsv_sim *s, const qsv_circuit *circ,
     QSV_TRY(ensure_vectors(s, dim));
     if (!s->d_small) QSV_HIP(s, hipMalloc((void **)&s->d_small, 64 * sizeof(double)));
     void *psi = s->d_vec[0], *phi = s->d_vec[1];
-    const uint64_t npairs_max = dim >> 1;
-    const int nb = qsv::dev::adjoint_blocks(npairs_max);
+    // partial sums per rotation: nb per workgroup-wave of the tiled sweep
+    // (mode TILED), else per workgroup of the per-gate reverse kernels
+    const bool tiled = s->opt.mode == QSV_MODE_TILED;
+    int grid = 0, nb = 0, mfma_k = 0;
+    if (tiled) {
+        // widest step that may run on the matrix cores (dense, 3+ targets)
+        for (int g = 0; g < G; ++g)
+            if (!axis[g] && gates[g].k >= 3) mfma_k = std::max(mfma_k, gates[g].k);
+        const int m = adjoint_tile_bits(s, n);
+        grid = qsv::dev::adjoint_tile_grid(s->opt.dtype, m, mfma_k);
+        if (grid < 1) return fail(s, QSV_EDEVICE, "adjoint tiles do not fit in LDS");
+        grid = (int)std::min<uint64_t>((uint64_t)grid, 1ull << (n - m));
+        nb = grid * qsv::dev::kAdjWaves;
+    } else {
+        nb = qsv::dev::adjoint_blocks(dim >> 1);
+    }
     // workspace: [x z c ny | param order | grad | partials]
     const int T = ham->n_terms;
     const size_t off_z = 8 * (size_t)(T + 1), off_c = 16 * (size_t)(T + 1), off_ny = 24 * (size_t)(T + 1);
     const size_t off_po = (off_ny + 4 * (size_t)(T + 1) + 255) & ~size_t(255);
     const size_t off_gr = (off_po + 4 * (size_t)(nrot + 1) + 255) & ~size_t(255);
     const size_t off_pa = (off_gr + 8 * (size_t)(circ->n_params + 1) + 255) & ~size_t(255);
-    const size_t need = off_pa + 8 * (size_t)nb * (nrot + 1) + 4096;
+    // (the inner product <psi|H psi> uses up to 1024 partials after the rows)
+    const size_t need = off_pa + 8 * ((size_t)nb * nrot + 1024) + 4096;
     QSV_TRY(ensure_ws(s, need));
     unsigned char *w = (unsigned char *)s->d_ws;
     std::vector<unsigned char> meta(off_gr, 0);
@@ -1203,8 +1409,11 @@ extern "C" qsv_status qsv_adjoint_gradient(qsv_sim *s, const qsv_circuit *circ,
     QSV_HIP(s, qsv::dev::dot_re(s->opt.dtype, psi, phi, dim, partial + (size_t)nb * nrot,
                                 s->d_small, s->stream));
     // reverse sweep
+    if (tiled)
+        QSV_TRY(adjoint_reverse_tiled(s, gates, axis, circ->params, param, psi, phi, partial, grid,
+                                      mfma_k));
     int slot = 0;
-    for (int g = G - 1; g >= 0; --g) {
+    for (int g = G - 1; g >= 0 && !tiled; --g) {
         const Gate &gt = gates[g];
         if (axis[g]) {
             const int c = popc(gt.ctrl);
@@ -1215,7 +1424,7 @@ extern "C" qsv_status qsv_adjoint_gradient(qsv_sim *s, const qsv_circuit *circ,
             QSV_HIP(s, qsv::dev::adjoint_rotation(s->opt.dtype, psi, phi, dim >> (1 + c), ia,
                                                   1ull << gt.t[0], axis[g], std::cos(th / 2),
                                                   std::sin(th / 2), partial + (size_t)nb * slot,
-                                                  s->stream));
+                                                  nb, s->stream));
             tend(s, tok, QSV_K_DENSE, 4.0 * (double)(dim >> c) * s->elem());
             ++slot;
         } else {

@@ -78,6 +78,23 @@ struct Pass {
     std::vector<Op> ops;
 };
 
+// Greedy grouping behind the pass planner, on plain bit masks: item i needs
+// the bits `need` inside the tile, changes the bits `mix` and touches `all`.
+// Walking the remaining items in order, an item joins the current group if
+// it commutes with every item deferred before it and its bits still fit in m
+// (the lowest min(low_bits, m - kMaxK) positions are always in the tile);
+// the group's tile is then filled up to m bits with the lowest free
+// positions.  For n <= m there is one group holding everything.
+struct PlanItem {
+    uint64_t need = 0, mix = 0, all = 0;
+};
+struct PlanGroup {
+    uint64_t tile = 0;
+    std::vector<int> idx;         // item indices, in the order they are applied
+};
+std::vector<PlanGroup> plan_groups(const std::vector<PlanItem> &items, int n, int m,
+                                   int low_bits);
+
 // Group ops into passes whose mixing qubits fit in m tile bits, the lowest
 // `low_bits` positions always included (contiguous HBM runs).  Ops are moved
 // across each other only when they commute.  Then each pass is fused to

@@ -16,19 +16,16 @@
 
 namespace qsv {
 
+uint32_t swz_elem(uint32_t l, int elem_bytes) {
+    return elem_bytes == 16 ? (l ^ (((l >> 4) ^ (l >> 8)) & 15u))
+                            : (l ^ (((l >> 5) ^ (l >> 10)) & 31u));
+}
+
 namespace {
 
 void push(std::vector<double> &mats, const cd &v) {
     mats.push_back(v.real());
     mats.push_back(v.imag());
-}
-
-// Swizzled element index of local index l (the same XOR swizzle as the
-// device's swz<R>: bits above the 256-byte bank span folded into the bits
-// below it).
-uint32_t swz_elem(uint32_t l, int elem_bytes) {
-    return elem_bytes == 16 ? (l ^ (((l >> 4) ^ (l >> 8)) & 15u))
-                            : (l ^ (((l >> 5) ^ (l >> 10)) & 31u));
 }
 
 // TileOp (LDS kernel form) of an op whose mixing targets lie in the tile;

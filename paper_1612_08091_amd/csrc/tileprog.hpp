@@ -33,6 +33,11 @@ struct TileProgram {
 void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram &prog,
                   int elem_bytes = 16);
 
+// Swizzled element index of local index l in an LDS tile (the same XOR
+// swizzle as the device's swz<R>: the bits above the 256-byte bank span are
+// folded into the bits below it); elem_bytes is 16 or 8.
+uint32_t swz_elem(uint32_t l, int elem_bytes);
+
 // Byte offset in the half-tile remap buffer of local index l when local bit
 // `kept` (the one that stays in its register slot) is dropped: the compacted
 // index, XOR-swizzled against bank conflicts, times elem_bytes.  Linear over

@@ -135,3 +135,120 @@ def test_torch_autograd_function():
     assert torch.autograd.gradcheck(lambda t: expectation(t, s, circ, ham), (theta,),
                                     eps=1e-6, atol=1e-7)
     s.close()
+
+
+def _mixed_circuit(n, rng, layers=2):
+    """Rotations (some controlled from far qubits), CZ ladders, 3-qubit dense
+    blocks, diagonal 2- and 3-qubit gates and a Toffoli: every kind of
+    reverse step (in a tile smaller than the state: phases from qubits
+    outside the tile, with and without controls inside it)."""
+    c = W.Circuit(n, theta=np.zeros(0))
+    th = []
+
+    def rot(axis, q, ctrls=()):
+        p = len(th)
+        th.append(rng.uniform(0, 2 * math.pi))
+        f = {"X": W.rx, "Y": W.ry, "Z": W.rz}[axis]
+        c.add(f(th[p]), (q,), ctrls, name="r" + axis.lower(), param=p, axis=axis)
+
+    for layer in range(layers):
+        for q in range(n):
+            rot("Y", q)
+            rot("Z", q)
+        for q in range(layer % 2, n - 1, 2):
+            c.add(W.Z, (q + 1,), (q,), name="cz")
+        c.add(W.haar_unitary(8, rng), (1, n // 2, n - 1))
+        # diagonal gates: two targets far up, three targets spread out
+        c.add(np.diag(np.exp(1j * rng.uniform(0, 2 * math.pi, 4))), (n - 1, n - 2))
+        c.add(np.diag(np.exp(1j * rng.uniform(0, 2 * math.pi, 8))), (0, n // 2, n - 1))
+        rot("X", n - 2, (0,))
+        rot("Z", 2, (n - 1, n - 3))
+        c.add(W.X, (n // 2,), (1, n - 1), name="ccx")
+        rot("Y", 0, (n - 1,))
+    c.theta = np.array(th)
+    return c
+
+
+@pytest.mark.parametrize("dtype,n,tile_bits", [("c128", 10, 6), ("c128", 13, 8),
+                                               ("c64", 12, 7)])
+def test_adjoint_tiled_passes_against_oracle(dtype, n, tile_bits):
+    """Many reverse tile passes (tile smaller than the state): steps with
+    controls outside the tile, diagonal steps on qubits outside it, dense
+    3-qubit steps on the matrix cores; gradient against central differences
+    of the oracle and against the per-gate reverse sweep."""
+    from paper_1612_08091_amd import qsv as Q
+    rng = np.random.default_rng(40 + n)
+    circ = _mixed_circuit(n, rng)
+    ham = W.random_pauli_local(n, 30, 4, rng)
+    s = sim(n, dtype=dtype, tile_bits=tile_bits)
+    val, grad = Q.adjoint_gradient(s, circ, ham)
+    s.close()
+    p = sim(n, dtype=dtype, mode="pergate")
+    val_p, grad_p = Q.adjoint_gradient(p, circ, ham)
+    p.close()
+    scale = np.sum(np.abs(ham.coeff))
+    tol_v, tol_g = (1e-12 * scale, 1e-6) if dtype == "c128" else (1e-5 * scale, 1e-5 * scale)
+    assert abs(val - oracle.energy(circ, ham)) <= tol_v
+    fd = oracle.grad_fd(circ, ham, h=1e-5)
+    assert np.max(np.abs(grad - fd)) <= tol_g
+    if dtype == "c128":
+        assert np.max(np.abs(grad - grad_p)) <= 1e-11 * max(1.0, np.max(np.abs(grad_p)))
+
+
+def test_adjoint_tiled_more_rotations_than_one_launch_holds():
+    """A pass with more rotations than one launch's accumulators (256) is
+    split into several launches over the same tile."""
+    from paper_1612_08091_amd import qsv as Q
+    rng = np.random.default_rng(41)
+    n, layers = 4, 40
+    circ = W.hea(n, layers, rng.uniform(0, 2 * math.pi, 2 * n * layers))
+    ham = W.random_pauli_dense(n, 10, rng)
+    s = sim(n)
+    val, grad = Q.adjoint_gradient(s, circ, ham)
+    s.close()
+    assert len(grad) == 320
+    assert abs(val - oracle.energy(circ, ham)) <= 1e-12 * np.sum(np.abs(ham.coeff))
+    want = oracle.grad_param_shift(circ, ham)
+    assert np.max(np.abs(grad - want)) <= 1e-9 * max(1.0, np.max(np.abs(want)))
+
+
+def test_adjoint_tiled_is_deterministic():
+    """Static tile assignment: two runs give bit-identical gradients."""
+    from paper_1612_08091_amd import qsv as Q
+    rng = np.random.default_rng(42)
+    n, layers = 16, 3
+    circ = W.hea(n, layers, rng.uniform(0, 2 * math.pi, 2 * n * layers))
+    ham = W.random_pauli_local(n, 20, 4, rng)
+    s = sim(n, tile_bits=9)
+    v1, g1 = Q.adjoint_gradient(s, circ, ham)
+    v2, g2 = Q.adjoint_gradient(s, circ, ham)
+    s.close()
+    assert v1 == v2 and np.array_equal(g1, g2)
+    ps = oracle.grad_param_shift(circ, ham, params=range(0, len(circ.theta), 9))
+    assert np.max(np.abs(g1[::9] - ps)) <= 1e-9 * max(1.0, np.max(np.abs(ps)))
+
+
+def test_adjoint_pergate_controlled_rows_fully_written():
+    """Per-gate reverse sweep: a controlled rotation has fewer pairs than the
+    row of partial sums is wide; every entry of its row must still be
+    written, not left from an earlier call on the same handle."""
+    from paper_1612_08091_amd import qsv as Q
+    rng = np.random.default_rng(43)
+    n = 12
+    s = sim(n, mode="pergate")
+    first = W.hea(n, 1, rng.uniform(0, 2 * math.pi, 2 * n))
+    ham = W.random_pauli_local(n, 20, 3, rng)
+    Q.adjoint_gradient(s, first, ham)
+    th = rng.uniform(0, 2 * math.pi, 4)
+    c = W.Circuit(n, theta=th)
+    for q in range(n):
+        c.add(W.haar_2x2(rng), (q,))
+    c.add(W.rx(th[0]), (3,), (0,), name="crx", param=0, axis="X")
+    c.add(W.ry(th[1]), (9,), (2, 5), name="ccry", param=1, axis="Y")
+    c.add(W.rz(th[2]), (11,), (1,), name="crz", param=2, axis="Z")
+    c.add(W.ry(th[3]), (4,), name="ry", param=3, axis="Y")
+    val, grad = Q.adjoint_gradient(s, c, ham)
+    s.close()
+    assert abs(val - oracle.energy(c, ham)) <= 1e-12 * np.sum(np.abs(ham.coeff))
+    fd = oracle.grad_fd(c, ham, h=1e-5)
+    assert np.max(np.abs(grad - fd)) <= 1e-6
