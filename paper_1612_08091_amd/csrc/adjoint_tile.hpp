@@ -39,7 +39,11 @@ constexpr int kAdjChain = 4;            // rotations fused into one step
 //    op.fz / op.sl[0] / op.nfree address the amplitudes whose in-tile
 //    control bits are set (nfree = m: no in-tile controls); the pool holds
 //    the 2^k diagonal values at op.mat.
-enum AdjKind { ADJ_APPLY = 0, ADJ_ROT = 1, ADJ_PHASE = 2 };
+//  kind ADJ_BLOCK: nsub sub-steps (AdjSub sub0 .. sub0 + nsub - 1) on three
+//    tile bits, the block: each thread loads the 8 amplitudes of a group
+//    (op.sl[0..7] the block rows, op.fz / op.nfree the other tile bits) of
+//    both tiles, runs the sub-steps on them in registers and stores them.
+enum AdjKind { ADJ_APPLY = 0, ADJ_ROT = 1, ADJ_PHASE = 2, ADJ_BLOCK = 3 };
 struct AdjOp {
     TileOp op;
     int32_t kind;
@@ -47,9 +51,35 @@ struct AdjOp {
     int32_t axis[kAdjChain];
     int32_t lslot[kAdjChain];
     int32_t gslot[kAdjChain];
-    int32_t pad;
+    int32_t sub0;
     double c[kAdjChain];
     double s[kAdjChain];
+};
+
+// Sub-steps of a block, on block rows r = 0..7 (bit j of r = block bit j):
+//  SUB_ROT: rotation about `axis` on block bit j (as in a chain), on the
+//    pairs whose rows contain cmask; lslot / gslot as for chains.
+//  SUB_U1: the 2x2 matrix at pool[mat] on block bit j, rows containing cmask.
+//  SUB_DIAG: row r multiplied by pool[mat + r] for the rows in `touch`.
+//  SUB_PHASE: a diagonal op with k targets outside the tile: row index
+//    r_out from the tile base's bits gt[0..k-1]; if r_out is in `touch`, the
+//    rows containing cmask are multiplied by pool[mat + r_out] (cmask = 0:
+//    the whole tile, recorded as a pending phase).
+//  All: skipped on tiles whose base lacks one of the ectrl bits.
+enum AdjSubKind { SUB_ROT = 0, SUB_U1 = 1, SUB_DIAG = 2, SUB_PHASE = 3 };
+struct AdjSub {
+    int32_t kind;
+    int32_t j;
+    int32_t cmask;
+    int32_t axis;
+    int32_t lslot;
+    int32_t gslot;
+    int32_t k;
+    uint32_t touch;
+    uint32_t gt[6];
+    uint64_t ectrl;
+    double c, s;
+    int64_t mat;
 };
 
 constexpr int kAdjWaves = 4;            // waves per workgroup (256 threads)
@@ -66,14 +96,15 @@ inline size_t adjoint_tile_lds(int dtype, int m) {
 int adjoint_tile_grid(int dtype, int m, int mfma_k);
 
 // One pass: ta.m, ta.n_ops, ta.tpos, ta.n_tiles, ta.dep_hi and ta.mfma_k
-// (widest matrix-core step of the sweep) as for the forward LDS tile kernel; `ops` are ta.n_ops steps in order, holding at most
-// kAdjMaxRot rotations (lslot 0..nrot-1, each used once); `pool` the
-// matrices in the state's complex type.  Writes
+// (widest matrix-core step of the sweep) as for the forward LDS tile
+// kernel; `ops` are ta.n_ops steps in order, holding at most kAdjMaxRot
+// rotations (lslot 0..nrot-1, each used once); `subs` the sub-steps of
+// their blocks; `pool` the matrices in the state's complex type.  Writes
 // partial[gslot * nb + 4 * block + wave] for every rotation of the pass,
 // nb = 4 * grid.
 hipError_t adjoint_tile_pass(int dtype, void *psi, void *phi, const TileArgs &ta,
-                             const AdjOp *ops, const void *pool, int nrot, double *partial,
-                             int grid, hipStream_t s);
+                             const AdjOp *ops, const AdjSub *subs, const void *pool, int nrot,
+                             double *partial, int grid, hipStream_t s);
 
 }  // namespace dev
 }  // namespace qsv

@@ -280,15 +280,173 @@ __device__ __forceinline__ void lds2_phase(unsigned char *tp, unsigned char *tf,
     }
 }
 
+// ------------------------------------------------------------ blocks
+// Sub-steps on the 8 rows of one group held in registers (x: psi, y: phi).
+// J (block bit) and AX (rotation axis) are template arguments so that every
+// row index is a compile-time constant and the rows stay in registers.
+template <typename T, typename R, int J, int AX>
+__device__ __forceinline__ double blk_rot(T *x, T *y, int cmask, R c, R s) {
+    double part = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        if (r & (1 << J)) continue;
+        if ((r & cmask) != cmask) continue;
+        const int r1 = r | (1 << J);
+        part += rot_grad(AX, x[r], x[r1], y[r], y[r1]);
+        rot_apply(AX, c, s, x[r], x[r1]);
+        rot_apply(AX, c, s, y[r], y[r1]);
+    }
+    return part;
+}
+
+template <typename T, int J>
+__device__ __forceinline__ void blk_u1(T *x, T *y, int cmask, const T *u) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        if (r & (1 << J)) continue;
+        if ((r & cmask) != cmask) continue;
+        const int r1 = r | (1 << J);
+        const T x0 = x[r], x1 = x[r1], y0 = y[r], y1 = y[r1];
+        x[r] = cmadd(cmul(u[0], x0), u[1], x1);
+        x[r1] = cmadd(cmul(u[2], x0), u[3], x1);
+        y[r] = cmadd(cmul(u[0], y0), u[1], y1);
+        y[r1] = cmadd(cmul(u[2], y0), u[3], y1);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void blk_scale(T *x, T *y, uint32_t rows, const T *d, bool same) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        if (!((rows >> r) & 1u)) continue;
+        const T f = same ? d[0] : d[r];
+        x[r] = cmul(f, x[r]);
+        y[r] = cmul(f, y[r]);
+    }
+}
+
+template <typename T, typename R, int J>
+__device__ __forceinline__ double blk_rot_axis(T *x, T *y, int axis, int cmask, R c, R s) {
+    if (axis == 1) return blk_rot<T, R, J, 1>(x, y, cmask, c, s);
+    if (axis == 2) return blk_rot<T, R, J, 2>(x, y, cmask, c, s);
+    return blk_rot<T, R, J, 3>(x, y, cmask, c, s);
+}
+
+// A block step.  Each thread takes groups tid, tid + kNT, ... one at a time
+// (all sub-steps on one group, then the next).  With fewer than kNT groups
+// the idle lanes hold zeros, which add nothing to the inner products, and
+// store nothing; every lane takes part in the wave sums.
+template <typename R>
+__device__ __forceinline__ void lds2_block(unsigned char *tp, unsigned char *tf, uint64_t base,
+                                           const AdjOp &ao, const AdjSub *__restrict__ subs,
+                                           const typename VT<R>::T *__restrict__ pool,
+                                           double *acc, typename VT<R>::T &pend) {
+    using T = typename VT<R>::T;
+    const TileOp &op = ao.op;
+    const int nfree = op.nfree;
+    const uint32_t ngroups = 1u << nfree;
+    const uint32_t tid = threadIdx.x;
+    const bool valid = tid < ngroups;
+    const uint32_t toff = xor_parts(tid, op.fz, nfree < 8 ? nfree : 8);
+    const Parts<8> hi(op.fz + 8, nfree - 8);
+    uint32_t sl[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) sl[r] = op.sl[r];
+    const uint32_t wave = tid >> 6;
+    const int nsub = ao.nsub;
+    const AdjSub *sb = subs + ao.sub0;
+    // the pending phase is uniform: record it on the first group only
+    bool first = true;
+    for (uint32_t it = 0; it * kNT < ngroups || it == 0; ++it) {
+        const uint32_t go = toff ^ hi.of(it);
+        T x[8], y[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (valid) {
+                x[r] = *reinterpret_cast<const T *>(tp + (go ^ sl[r]));
+                y[r] = *reinterpret_cast<const T *>(tf + (go ^ sl[r]));
+            } else {
+                x[r].x = x[r].y = y[r].x = y[r].y = R(0);
+            }
+        }
+        for (int si = 0; si < nsub; ++si) {
+            const AdjSub &u = sb[si];
+            if ((base & u.ectrl) != u.ectrl) continue;
+            const int kind = u.kind;
+            if (kind == SUB_ROT) {
+                const int j = u.j, axis = u.axis, cmask = u.cmask;
+                const R c = (R)u.c, s = (R)u.s;
+                double part;
+                if (j == 0) part = blk_rot_axis<T, R, 0>(x, y, axis, cmask, c, s);
+                else if (j == 1) part = blk_rot_axis<T, R, 1>(x, y, axis, cmask, c, s);
+                else part = blk_rot_axis<T, R, 2>(x, y, axis, cmask, c, s);
+                const double tot = wave_sum(part);
+                if ((tid & 63u) == 0) acc[u.lslot * kAdjWaves + wave] += tot;
+            } else if (kind == SUB_U1) {
+                const int j = u.j, cmask = u.cmask;
+                const T *m = pool + u.mat;
+                T um[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) um[e] = m[e];
+                if (j == 0) blk_u1<T, 0>(x, y, cmask, um);
+                else if (j == 1) blk_u1<T, 1>(x, y, cmask, um);
+                else blk_u1<T, 2>(x, y, cmask, um);
+            } else if (kind == SUB_DIAG) {
+                const uint32_t touch = u.touch;
+                const T *m = pool + u.mat;
+                T d[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) d[r] = ((touch >> r) & 1u) ? m[r] : T{};
+                blk_scale(x, y, touch, d, false);
+            } else {
+                uint32_t r = 0;
+                for (int q = 0; q < u.k; ++q) r |= (uint32_t)((base >> u.gt[q]) & 1u) << q;
+                if (!((u.touch >> r) & 1u)) continue;
+                const T p = pool[u.mat + r];
+                const int cmask = u.cmask;
+                if (cmask == 0) {
+                    if (first) pend = cmul(pend, p);
+                    continue;
+                }
+                uint32_t rows = 0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if ((q & cmask) == cmask) rows |= 1u << q;
+                blk_scale(x, y, rows, &p, true);
+            }
+        }
+        if (valid) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                *reinterpret_cast<T *>(tp + (go ^ sl[r])) = x[r];
+                *reinterpret_cast<T *>(tf + (go ^ sl[r])) = y[r];
+            }
+        }
+        first = false;
+    }
+}
+
+// One step; returns false if it did not touch the tiles in LDS (a pending
+// tile phase), so that no barrier is needed after it.
 template <typename R, int KM>
-__device__ __forceinline__ void adj_step(typename VT<R>::T *tp, typename VT<R>::T *tf, int m,
+__device__ __forceinline__ bool adj_step(typename VT<R>::T *tp, typename VT<R>::T *tf, int m,
                                          uint64_t base, const TileArgs &ta, const AdjOp &ao,
+                                         const AdjSub *__restrict__ subs,
                                          const typename VT<R>::T *__restrict__ pool,
                                          double *acc, typename VT<R>::T &pend) {
     unsigned char *bp = reinterpret_cast<unsigned char *>(tp);
     unsigned char *bf = reinterpret_cast<unsigned char *>(tf);
     const TileOp &op = ao.op;
-    if ((base & op.ectrl) != op.ectrl) return;
+    if (ao.kind == ADJ_BLOCK) {
+        lds2_block<R>(bp, bf, base, ao, subs, pool, acc, pend);
+        return true;
+    }
+    if (ao.kind == ADJ_PHASE && op.nfree == m) {
+        if ((base & op.ectrl) == op.ectrl)
+            lds2_phase<R>(bp, bf, m, base, op, pool + op.mat, pend);
+        return false;
+    }
+    if ((base & op.ectrl) != op.ectrl) return true;
     if (ao.kind == ADJ_ROT) {
         double part[kAdjChain] = {0.0, 0.0, 0.0, 0.0};
         lds2_chain<R>(bp, bf, ao, part);
@@ -303,7 +461,7 @@ __device__ __forceinline__ void adj_step(typename VT<R>::T *tp, typename VT<R>::
             for (int j = 0; j < kAdjChain; ++j)
                 if (j < nsub) acc[ao.lslot[j] * kAdjWaves + wave] += tot[j];
         }
-        return;
+        return true;
     }
     const typename VT<R>::T *mat = pool + op.mat;
     if (ao.kind == ADJ_PHASE) {
@@ -324,6 +482,7 @@ __device__ __forceinline__ void adj_step(typename VT<R>::T *tp, typename VT<R>::
         lds_op<R, KM>(tp, m, base, ta.tpos, op, pool, ta.dep_hi);
         lds_op<R, KM>(tf, m, base, ta.tpos, op, pool, ta.dep_hi);
     }
+    return true;
 }
 
 // Tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... (a static assignment, so
@@ -333,6 +492,7 @@ template <typename R, int KM>
 __global__ __launch_bounds__(kNT) void k_adj_tile(typename VT<R>::T *__restrict__ psi,
                                                   typename VT<R>::T *__restrict__ phi,
                                                   TileArgs ta, const AdjOp *__restrict__ ops,
+                                                  const AdjSub *__restrict__ subs,
                                                   const typename VT<R>::T *__restrict__ pool,
                                                   int nrot, double *__restrict__ partial) {
     using T = typename VT<R>::T;
@@ -382,10 +542,9 @@ __global__ __launch_bounds__(kNT) void k_adj_tile(typename VT<R>::T *__restrict_
         T pend;
         pend.x = R(1);
         pend.y = R(0);
-        for (int oi = 0; oi < ta.n_ops; ++oi) {
-            adj_step<R, KM>(tp, tf, m, base, ta, ops[oi], pool, acc, pend);
-            __syncthreads();
-        }
+        for (int oi = 0; oi < ta.n_ops; ++oi)
+            if (adj_step<R, KM>(tp, tf, m, base, ta, ops[oi], subs, pool, acc, pend))
+                __syncthreads();
         const bool ph = pend.x != R(1) || pend.y != R(0);
         if (tsize >= 4 * kNT) {
             for (uint32_t j0 = 0; j0 < tsize; j0 += 4 * kNT) {
@@ -425,12 +584,20 @@ __global__ __launch_bounds__(kNT) void k_adj_tile(typename VT<R>::T *__restrict_
     }
     __syncthreads();
     const size_t nb = (size_t)gridDim.x * kAdjWaves;
-    for (int oi = 0; oi < ta.n_ops; ++oi) {
+    for (int oi = 0; oi < ta.n_ops && tid < (uint32_t)kAdjWaves; ++oi) {
         const AdjOp &ao = ops[oi];
-        if (ao.kind != ADJ_ROT || tid >= (uint32_t)kAdjWaves) continue;
-        for (int j = 0; j < ao.nsub; ++j)
-            partial[(size_t)ao.gslot[j] * nb + (size_t)blockIdx.x * kAdjWaves + tid] =
-                acc[ao.lslot[j] * kAdjWaves + tid];
+        if (ao.kind == ADJ_ROT) {
+            for (int j = 0; j < ao.nsub; ++j)
+                partial[(size_t)ao.gslot[j] * nb + (size_t)blockIdx.x * kAdjWaves + tid] =
+                    acc[ao.lslot[j] * kAdjWaves + tid];
+        } else if (ao.kind == ADJ_BLOCK) {
+            for (int j = 0; j < ao.nsub; ++j) {
+                const AdjSub &u = subs[ao.sub0 + j];
+                if (u.kind == SUB_ROT)
+                    partial[(size_t)u.gslot * nb + (size_t)blockIdx.x * kAdjWaves + tid] =
+                        acc[u.lslot * kAdjWaves + tid];
+            }
+        }
     }
 }
 
@@ -465,8 +632,8 @@ int adjoint_tile_grid(int dtype, int m, int mfma_k) {
 
 template <typename R, int KM>
 static hipError_t adj_tile_t(void *psi, void *phi, const TileArgs &ta, const AdjOp *ops,
-                             const void *pool, int nrot, double *partial, int grid,
-                             hipStream_t s) {
+                             const AdjSub *subs, const void *pool, int nrot, double *partial,
+                             int grid, hipStream_t s) {
     using T = typename VT<R>::T;
     const size_t lds = adjoint_tile_lds(sizeof(R) == 8 ? 0 : 1, ta.m);
     if (lds > 64 * 1024) {
@@ -475,27 +642,30 @@ static hipError_t adj_tile_t(void *psi, void *phi, const TileArgs &ta, const Adj
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_adj_tile<R, KM>), dim3((unsigned)grid), dim3(kNT), lds, s, (T *)psi,
-                       (T *)phi, ta, ops, (const T *)pool, nrot, partial);
+                       (T *)phi, ta, ops, subs, (const T *)pool, nrot, partial);
     return hipGetLastError();
 }
 
 template <typename R>
 static hipError_t adj_tile_k(void *psi, void *phi, const TileArgs &ta, const AdjOp *ops,
-                             const void *pool, int nrot, double *partial, int grid,
-                             hipStream_t s) {
-    if (ta.mfma_k == 0) return adj_tile_t<R, 0>(psi, phi, ta, ops, pool, nrot, partial, grid, s);
-    if (ta.mfma_k <= 3) return adj_tile_t<R, 3>(psi, phi, ta, ops, pool, nrot, partial, grid, s);
-    return adj_tile_t<R, 5>(psi, phi, ta, ops, pool, nrot, partial, grid, s);
+                             const AdjSub *subs, const void *pool, int nrot, double *partial,
+                             int grid, hipStream_t s) {
+    if (ta.mfma_k == 0)
+        return adj_tile_t<R, 0>(psi, phi, ta, ops, subs, pool, nrot, partial, grid, s);
+    if (ta.mfma_k <= 3)
+        return adj_tile_t<R, 3>(psi, phi, ta, ops, subs, pool, nrot, partial, grid, s);
+    return adj_tile_t<R, 5>(psi, phi, ta, ops, subs, pool, nrot, partial, grid, s);
 }
 
 hipError_t adjoint_tile_pass(int dtype, void *psi, void *phi, const TileArgs &ta,
-                             const AdjOp *ops, const void *pool, int nrot, double *partial,
-                             int grid, hipStream_t s) {
+                             const AdjOp *ops, const AdjSub *subs, const void *pool, int nrot,
+                             double *partial, int grid, hipStream_t s) {
     if (grid < 1 || nrot < 0 || nrot > kAdjMaxRot || ta.m < 1 ||
         ta.m > (dtype == 0 ? 12 : 13) || ta.mfma_k < 0 || ta.mfma_k > 5)
         return hipErrorInvalidValue;
-    return dtype == 0 ? adj_tile_k<double>(psi, phi, ta, ops, pool, nrot, partial, grid, s)
-                      : adj_tile_k<float>(psi, phi, ta, ops, pool, nrot, partial, grid, s);
+    return dtype == 0
+               ? adj_tile_k<double>(psi, phi, ta, ops, subs, pool, nrot, partial, grid, s)
+               : adj_tile_k<float>(psi, phi, ta, ops, subs, pool, nrot, partial, grid, s);
 }
 
 }  // namespace dev

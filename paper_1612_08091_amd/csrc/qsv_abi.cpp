@@ -1196,67 +1196,183 @@ qsv_status adjoint_reverse_tiled(qsv_sim *s, const std::vector<Gate> &gates,
         size_t first, count;
         int nrot;
     };
+    // a step waiting in the open block
+    struct Pending {
+        int i;            // step index
+        uint32_t lctrl;   // in-tile controls (tile bits)
+        uint64_t ectrl;   // controls outside the tile
+        int kind;         // AdjSubKind
+        int lslot;
+    };
+    const int eb = (int)s->elem();
     std::vector<double> mats;
     std::vector<AdjOp> aops;
+    std::vector<qsv::dev::AdjSub> subs;
     std::vector<Launch> launches;
+    auto push_c = [&](const cd &v) {
+        mats.push_back(v.real());
+        mats.push_back(v.imag());
+    };
     for (int gi = 0; gi < (int)groups.size(); ++gi) {
+        const uint64_t tile = groups[gi].tile;
+        const int mt = popc(tile);
         int li[64];
         int c = 0;
-        for (int p = 0; p < 64; ++p) li[p] = ((groups[gi].tile >> p) & 1) ? c++ : -1;
+        for (int p = 0; p < 64; ++p) li[p] = ((tile >> p) & 1) ? c++ : -1;
+        // blocks of three tile bits take the one-target and diagonal steps
+        const bool use_blocks = mt >= 3;
         Launch L{gi, aops.size(), 0, 0};
         int prev = -1;   // step index of the launch's last op if it is a chain
+        bool bopen = false;
+        uint32_t bbits = 0;
+        std::vector<Pending> bq;
+        auto close_block = [&]() {
+            if (!bopen) return;
+            for (int b = 0; b < mt && popc(bbits) < 3; ++b) bbits |= 1u << b;
+            int bl[3], nb3 = 0;
+            for (int b = 0; b < mt; ++b)
+                if ((bbits >> b) & 1) bl[nb3++] = b;
+            auto jpos = [&](int lb) { return lb == bl[0] ? 0 : lb == bl[1] ? 1 : 2; };
+            auto bmask = [&](uint32_t lm) {
+                int cm = 0;
+                for (int j = 0; j < 3; ++j)
+                    if ((lm >> bl[j]) & 1) cm |= 1 << j;
+                return cm;
+            };
+            AdjOp a{};
+            a.kind = qsv::dev::ADJ_BLOCK;
+            qsv::dev::TileOp &t = a.op;
+            t.k = 3;
+            for (int r = 0; r < 8; ++r) {
+                uint32_t o = 0;
+                for (int j = 0; j < 3; ++j)
+                    if ((r >> j) & 1) o |= 1u << bl[j];
+                t.sl[r] = qsv::swz_elem(o, eb) * eb;
+            }
+            for (int b = 0; b < mt; ++b)
+                if (!((bbits >> b) & 1)) t.fz[t.nfree++] = qsv::swz_elem(1u << b, eb) * eb;
+            a.sub0 = (int32_t)subs.size();
+            a.nsub = (int32_t)bq.size();
+            for (const Pending &pq : bq) {
+                const Op &st = steps[pq.i];
+                qsv::dev::AdjSub u{};
+                u.kind = pq.kind;
+                u.ectrl = pq.ectrl;
+                u.cmask = bmask(pq.lctrl);
+                if (pq.kind == qsv::dev::SUB_ROT) {
+                    u.j = jpos(li[st.t[0]]);
+                    u.axis = saxis[pq.i];
+                    u.lslot = pq.lslot;
+                    u.gslot = sslot[pq.i];
+                    u.c = std::cos(stheta[pq.i] / 2);
+                    u.s = std::sin(stheta[pq.i] / 2);
+                } else if (pq.kind == qsv::dev::SUB_U1) {
+                    u.j = jpos(li[st.t[0]]);
+                    u.mat = (int64_t)(mats.size() / 2);
+                    for (const cd &v : qsv::dense_matrix(st)) push_c(v);
+                } else if (pq.kind == qsv::dev::SUB_DIAG) {
+                    u.mat = (int64_t)(mats.size() / 2);
+                    for (int r = 0; r < 8; ++r) {
+                        cd d(1, 0);
+                        if ((r & u.cmask) == u.cmask) {
+                            int idx = 0;
+                            for (int q = 0; q < st.k; ++q)
+                                idx |= ((r >> jpos(li[st.t[q]])) & 1) << q;
+                            d = st.U[idx];
+                        }
+                        if (d != cd(1, 0)) u.touch |= 1u << r;
+                        push_c(d);
+                    }
+                    u.cmask = 0;
+                } else {   // SUB_PHASE
+                    u.k = st.k;
+                    u.touch = st.touch;
+                    for (int q = 0; q < st.k; ++q) u.gt[q] = (uint32_t)st.t[q];
+                    u.mat = (int64_t)(mats.size() / 2);
+                    for (int r = 0; r < (1 << st.k); ++r) push_c(st.U[r]);
+                }
+                subs.push_back(u);
+            }
+            aops.push_back(a);
+            ++L.count;
+            bopen = false;
+            bbits = 0;
+            bq.clear();
+            prev = -1;
+        };
         for (int i : groups[gi].idx) {
             const bool rot = sslot[i] >= 0;
             if (rot && L.nrot == qsv::dev::kAdjMaxRot) {
+                close_block();
                 launches.push_back(L);
                 L = Launch{gi, aops.size(), 0, 0};
                 prev = -1;
             }
-            if (rot && prev >= 0 && aops.back().nsub < qsv::dev::kAdjChain &&
-                steps[prev].t[0] == steps[i].t[0] && steps[prev].ctrl == steps[i].ctrl) {
-                AdjOp &a = aops.back();
-                const int j = a.nsub++;
-                a.axis[j] = saxis[i];
-                a.lslot[j] = L.nrot++;
-                a.gslot[j] = sslot[i];
-                a.c[j] = std::cos(stheta[i] / 2);
-                a.s[j] = std::sin(stheta[i] / 2);
-                continue;
+            const Op &st = steps[i];
+            uint32_t lctrl = 0;
+            uint64_t ectrl = 0;
+            for (int p = 0; p < 64; ++p)
+                if ((st.ctrl >> p) & 1) {
+                    if (li[p] >= 0) lctrl |= 1u << li[p];
+                    else ectrl |= 1ull << p;
+                }
+            const bool diag = st.kind == Op::MONO && st.diag;
+            int nin = 0;
+            uint32_t tin = 0;
+            for (int j = 0; j < st.k; ++j)
+                if (li[st.t[j]] >= 0) {
+                    ++nin;
+                    tin |= 1u << li[st.t[j]];
+                }
+            const bool outside = !rot && diag && nin == 0;
+            if (use_blocks) {
+                int kind = -1;
+                if (rot) kind = qsv::dev::SUB_ROT;
+                else if (outside) kind = qsv::dev::SUB_PHASE;
+                else if (diag && nin == st.k) kind = qsv::dev::SUB_DIAG;
+                else if (st.k == 1) kind = qsv::dev::SUB_U1;
+                const uint32_t need = lctrl | (outside ? 0u : tin);
+                if (kind == qsv::dev::SUB_PHASE && lctrl == 0 && !bopen) kind = -1;
+                if (kind >= 0 && popc(need) <= 3) {
+                    if (bopen && popc(bbits | need) > 3) close_block();
+                    bopen = true;
+                    bbits |= need;
+                    bq.push_back(Pending{i, lctrl, ectrl, kind, rot ? L.nrot++ : -1});
+                    continue;
+                }
+                close_block();
             }
             AdjOp a{};
-            const Op &st = steps[i];
-            bool outside = st.kind == Op::MONO && st.diag;
-            for (int j = 0; j < st.k; ++j)
-                if (li[st.t[j]] >= 0) outside = false;
             if (outside) {
                 // diagonal, all targets outside the tile: a phase per tile
-                const int eb = (int)s->elem();
                 qsv::dev::TileOp &t = a.op;
                 t.k = st.k;
                 t.touch = st.touch;
                 for (int j = 0; j < st.k; ++j) t.gt[j] = (uint32_t)st.t[j];
-                uint32_t lctrl = 0;
-                for (int p = 0; p < 64; ++p)
-                    if ((st.ctrl >> p) & 1) {
-                        if (li[p] >= 0) lctrl |= 1u << li[p];
-                        else t.ectrl |= 1ull << p;
-                    }
-                const int mt = popc(groups[gi].tile);
+                t.ectrl = ectrl;
                 for (int b = 0; b < mt; ++b)
                     if (!((lctrl >> b) & 1)) t.fz[t.nfree++] = qsv::swz_elem(1u << b, eb) * eb;
                 t.sl[0] = qsv::swz_elem(lctrl, eb) * eb;
                 t.mat = (int64_t)(mats.size() / 2);
-                for (int r = 0; r < (1 << st.k); ++r) {
-                    mats.push_back(st.U[r].real());
-                    mats.push_back(st.U[r].imag());
-                }
+                for (int r = 0; r < (1 << st.k); ++r) push_c(st.U[r]);
                 a.kind = qsv::dev::ADJ_PHASE;
                 aops.push_back(a);
                 ++L.count;
                 prev = -1;
                 continue;
             }
-            a.op = qsv::lower_to_lds(st, li, mats, (int)s->elem());
+            if (rot && prev >= 0 && aops.back().nsub < qsv::dev::kAdjChain &&
+                steps[prev].t[0] == st.t[0] && steps[prev].ctrl == st.ctrl) {
+                AdjOp &ch = aops.back();
+                const int j = ch.nsub++;
+                ch.axis[j] = saxis[i];
+                ch.lslot[j] = L.nrot++;
+                ch.gslot[j] = sslot[i];
+                ch.c[j] = std::cos(stheta[i] / 2);
+                ch.s[j] = std::sin(stheta[i] / 2);
+                continue;
+            }
+            a.op = qsv::lower_to_lds(st, li, mats, eb);
             if (rot) {
                 a.kind = qsv::dev::ADJ_ROT;
                 a.nsub = 1;
@@ -1273,24 +1389,30 @@ qsv_status adjoint_reverse_tiled(qsv_sim *s, const std::vector<Gate> &gates,
             aops.push_back(a);
             ++L.count;
         }
+        close_block();
         if (L.count) launches.push_back(L);
     }
     if (launches.empty()) return QSV_OK;
     const size_t a_bytes = (aops.size() * sizeof(AdjOp) + 255) & ~size_t(255);
+    const size_t u_bytes = (subs.size() * sizeof(qsv::dev::AdjSub) + 255) & ~size_t(255);
     const size_t nmat = mats.size();
     const size_t mat_bytes = s->opt.dtype == QSV_C128 ? nmat * sizeof(double) : nmat * sizeof(float);
-    std::vector<unsigned char> host(a_bytes + mat_bytes + 16, 0);
+    std::vector<unsigned char> host(a_bytes + u_bytes + mat_bytes + 16, 0);
     std::memcpy(host.data(), aops.data(), aops.size() * sizeof(AdjOp));
+    if (!subs.empty())
+        std::memcpy(host.data() + a_bytes, subs.data(), subs.size() * sizeof(qsv::dev::AdjSub));
     if (s->opt.dtype == QSV_C128) {
-        if (nmat) std::memcpy(host.data() + a_bytes, mats.data(), mat_bytes);
+        if (nmat) std::memcpy(host.data() + a_bytes + u_bytes, mats.data(), mat_bytes);
     } else {
-        float *f = reinterpret_cast<float *>(host.data() + a_bytes);
+        float *f = reinterpret_cast<float *>(host.data() + a_bytes + u_bytes);
         for (size_t i = 0; i < nmat; ++i) f[i] = (float)mats[i];
     }
     void *dpool = nullptr;
     QSV_TRY(stage(s, host.data(), host.size(), &dpool));
     const AdjOp *daops = reinterpret_cast<const AdjOp *>(dpool);
-    const void *dmat = (const unsigned char *)dpool + a_bytes;
+    const qsv::dev::AdjSub *dsubs =
+        reinterpret_cast<const qsv::dev::AdjSub *>((const unsigned char *)dpool + a_bytes);
+    const void *dmat = (const unsigned char *)dpool + a_bytes + u_bytes;
     for (const Launch &L : launches) {
         const uint64_t tile = groups[L.group].tile;
         qsv::dev::TileArgs ta{};
@@ -1310,8 +1432,8 @@ qsv_status adjoint_reverse_tiled(qsv_sim *s, const std::vector<Gate> &gates,
             ta.dep_hi[i] = d;
         }
         const int tok = tbegin(s);
-        QSV_HIP(s, qsv::dev::adjoint_tile_pass(s->opt.dtype, psi, phi, ta, daops + L.first, dmat,
-                                               L.nrot, partial, grid, s->stream));
+        QSV_HIP(s, qsv::dev::adjoint_tile_pass(s->opt.dtype, psi, phi, ta, daops + L.first, dsubs,
+                                               dmat, L.nrot, partial, grid, s->stream));
         tend(s, tok, QSV_K_TILE, 4.0 * (double)s->dim() * s->elem());
         if (log_level() >= 2)
             std::fprintf(stderr, "qsv: adjoint pass tile=%#llx m=%d steps=%zu rotations=%d\n",
