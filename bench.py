@@ -40,8 +40,8 @@ FP64_PEAK = 78.6e12        # MI355X FP64 (vector and matrix), flop/s
 # in the same runs (4 GiB read + 4 GiB write: FETCH_SIZE reads half the bytes,
 # WRITE_SIZE all of them).  Valid only for the sources they were taken with:
 # the digest below covers every file that shapes the kernel or its launches.
-TRAFFIC = {"kernel": "k_tile_reg<double,4,8>", "fetch_kib": 8389730.0, "write_kib": 17287610.0,
-           "fetch_scale": 2.0, "write_scale": 1.0, "digest": "c0203f026667bcdb"}
+TRAFFIC = {"kernel": "k_tile_reg<double,4,8>", "fetch_kib": 8389845.0, "write_kib": 17283378.0,
+           "fetch_scale": 2.0, "write_scale": 1.0, "digest": "772ad4a25c1f0f48"}
 TRAFFIC_SOURCES = ("paper_1612_08091_amd/csrc/kernels_tile.hip",
                    "paper_1612_08091_amd/csrc/lds_ops.hpp",
                    "paper_1612_08091_amd/csrc/device.hpp",
@@ -349,6 +349,9 @@ def main():
     ap.add_argument("--fp32-k-max", type=int, default=2)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the 32-qubit precision, batched and adjoint forms")
+    ap.add_argument("--only-form", default="",
+                    choices=["", "adjoint", "batched", "precision", "fusion", "simcomparison"],
+                    help="run just this form, print its JSON object and exit (for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -367,6 +370,13 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    if args.only_form:
+        forms = {"adjoint": form_adjoint, "batched": form_batched, "precision": form_precision,
+                 "fusion": lambda: form_fusion_qft(args.qubits),
+                 "simcomparison": lambda: form_simcomparison(args.qubits)}
+        print(json.dumps({args.only_form: forms[args.only_form]()}))
+        return
 
     n = args.qubits
     circ = W.config1_random(n=n)

@@ -36,7 +36,8 @@ __device__ __forceinline__ double bsum(double v, double *sh) {
 }
 
 // phi_j = sum_t c_t i^{ny_t} (-1)^{popcount((j ^ x_t) & z_t)} psi_{j ^ x_t}
-// (P|i> = i^{ny} (-1)^{popcount(i & z)} |i ^ x>).
+// (P|i> = i^{ny} (-1)^{popcount(i & z)} |i ^ x>).  Terms sorted by X mask
+// share their gathers.
 template <typename R>
 __global__ __launch_bounds__(kAT) void k_ham_apply(const typename VA<R>::T *__restrict__ psi,
                                                    typename VA<R>::T *__restrict__ phi,
@@ -48,9 +49,15 @@ __global__ __launch_bounds__(kAT) void k_ham_apply(const typename VA<R>::T *__re
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < dim;
          j += (uint64_t)gridDim.x * blockDim.x) {
         double ar = 0.0, ai = 0.0;
+        // terms with equal X masks read the same amplitude: one load each run
+        uint64_t lastx = ~0ull, i = 0;
+        typename VA<R>::T a;
         for (int t = 0; t < nterms; ++t) {
-            const uint64_t i = j ^ xm[t];
-            const auto a = psi[i];
+            if (xm[t] != lastx) {
+                lastx = xm[t];
+                i = j ^ lastx;
+                a = psi[i];
+            }
             double vr = a.x, vi = a.y;
             if (__popcll(i & zm[t]) & 1) {
                 vr = -vr;

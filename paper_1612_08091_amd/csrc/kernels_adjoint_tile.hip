@@ -284,17 +284,22 @@ __device__ __forceinline__ void lds2_phase(unsigned char *tp, unsigned char *tf,
 // Sub-steps on the 8 rows of one group held in registers (x: psi, y: phi).
 // J (block bit) and AX (rotation axis) are template arguments so that every
 // row index is a compile-time constant and the rows stay in registers.
-template <typename T, typename R, int J, int AX>
+// Rows of the p-th pair (p = 0..3) on block bit J: bit J of the row
+// inserted as 0 (lo) or 1 (hi).
+template <int J> __device__ constexpr int pair_lo(int p) {
+    return (p & ((1 << J) - 1)) | ((p >> J) << (J + 1));
+}
+
+template <typename T, typename R, int J, int AX, bool CTRL>
 __device__ __forceinline__ double blk_rot(T *x, T *y, int cmask, R c, R s) {
     double part = 0.0;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        if (r & (1 << J)) continue;
-        if ((r & cmask) != cmask) continue;
-        const int r1 = r | (1 << J);
-        part += rot_grad(AX, x[r], x[r1], y[r], y[r1]);
-        rot_apply(AX, c, s, x[r], x[r1]);
-        rot_apply(AX, c, s, y[r], y[r1]);
+    for (int p = 0; p < 4; ++p) {
+        const int r0 = pair_lo<J>(p), r1 = r0 | (1 << J);
+        if (CTRL && (r0 & cmask) != cmask) continue;
+        part += rot_grad(AX, x[r0], x[r1], y[r0], y[r1]);
+        rot_apply(AX, c, s, x[r0], x[r1]);
+        rot_apply(AX, c, s, y[r0], y[r1]);
     }
     return part;
 }
@@ -302,14 +307,13 @@ __device__ __forceinline__ double blk_rot(T *x, T *y, int cmask, R c, R s) {
 template <typename T, int J>
 __device__ __forceinline__ void blk_u1(T *x, T *y, int cmask, const T *u) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        if (r & (1 << J)) continue;
-        if ((r & cmask) != cmask) continue;
-        const int r1 = r | (1 << J);
-        const T x0 = x[r], x1 = x[r1], y0 = y[r], y1 = y[r1];
-        x[r] = cmadd(cmul(u[0], x0), u[1], x1);
+    for (int p = 0; p < 4; ++p) {
+        const int r0 = pair_lo<J>(p), r1 = r0 | (1 << J);
+        if ((r0 & cmask) != cmask) continue;
+        const T x0 = x[r0], x1 = x[r1], y0 = y[r0], y1 = y[r1];
+        x[r0] = cmadd(cmul(u[0], x0), u[1], x1);
         x[r1] = cmadd(cmul(u[2], x0), u[3], x1);
-        y[r] = cmadd(cmul(u[0], y0), u[1], y1);
+        y[r0] = cmadd(cmul(u[0], y0), u[1], y1);
         y[r1] = cmadd(cmul(u[2], y0), u[3], y1);
     }
 }
@@ -327,9 +331,15 @@ __device__ __forceinline__ void blk_scale(T *x, T *y, uint32_t rows, const T *d,
 
 template <typename T, typename R, int J>
 __device__ __forceinline__ double blk_rot_axis(T *x, T *y, int axis, int cmask, R c, R s) {
-    if (axis == 1) return blk_rot<T, R, J, 1>(x, y, cmask, c, s);
-    if (axis == 2) return blk_rot<T, R, J, 2>(x, y, cmask, c, s);
-    return blk_rot<T, R, J, 3>(x, y, cmask, c, s);
+    // (without in-block controls every pair takes part: no per-pair tests)
+    if (cmask == 0) {
+        if (axis == 1) return blk_rot<T, R, J, 1, false>(x, y, 0, c, s);
+        if (axis == 2) return blk_rot<T, R, J, 2, false>(x, y, 0, c, s);
+        return blk_rot<T, R, J, 3, false>(x, y, 0, c, s);
+    }
+    if (axis == 1) return blk_rot<T, R, J, 1, true>(x, y, cmask, c, s);
+    if (axis == 2) return blk_rot<T, R, J, 2, true>(x, y, cmask, c, s);
+    return blk_rot<T, R, J, 3, true>(x, y, cmask, c, s);
 }
 
 // A block step.  Each thread takes groups tid, tid + kNT, ... one at a time
@@ -381,7 +391,9 @@ __device__ __forceinline__ void lds2_block(unsigned char *tp, unsigned char *tf,
                 else if (j == 1) part = blk_rot_axis<T, R, 1>(x, y, axis, cmask, c, s);
                 else part = blk_rot_axis<T, R, 2>(x, y, axis, cmask, c, s);
                 const double tot = wave_sum(part);
-                if ((tid & 63u) == 0) acc[u.lslot * kAdjWaves + wave] += tot;
+                // (the slot belongs to this wave; an atomic add needs no
+                // read-back wait before the next sub-step)
+                if ((tid & 63u) == 0) atomicAdd(&acc[u.lslot * kAdjWaves + wave], tot);
             } else if (kind == SUB_U1) {
                 const int j = u.j, cmask = u.cmask;
                 const T *m = pool + u.mat;

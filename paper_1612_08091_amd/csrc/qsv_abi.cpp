@@ -1435,9 +1435,18 @@ qsv_status adjoint_reverse_tiled(qsv_sim *s, const std::vector<Gate> &gates,
         QSV_HIP(s, qsv::dev::adjoint_tile_pass(s->opt.dtype, psi, phi, ta, daops + L.first, dsubs,
                                                dmat, L.nrot, partial, grid, s->stream));
         tend(s, tok, QSV_K_TILE, 4.0 * (double)s->dim() * s->elem());
-        if (log_level() >= 2)
-            std::fprintf(stderr, "qsv: adjoint pass tile=%#llx m=%d steps=%zu rotations=%d\n",
-                         (unsigned long long)tile, ta.m, L.count, L.nrot);
+        if (log_level() >= 2) {
+            int nk[4] = {0, 0, 0, 0}, nsub = 0;
+            for (size_t q = L.first; q < L.first + L.count; ++q) {
+                ++nk[aops[q].kind];
+                if (aops[q].kind == qsv::dev::ADJ_BLOCK) nsub += aops[q].nsub;
+            }
+            std::fprintf(stderr,
+                         "qsv: adjoint pass tile=%#llx m=%d steps=%zu (apply %d, chains %d, "
+                         "phases %d, blocks %d with %d sub-steps) rotations=%d\n",
+                         (unsigned long long)tile, ta.m, L.count, nk[0], nk[1], nk[2], nk[3], nsub,
+                         L.nrot);
+        }
     }
     return QSV_OK;
 }
@@ -1500,13 +1509,20 @@ extern "C" qsv_status qsv_adjoint_gradient(qsv_sim *s, const qsv_circuit *circ,
     unsigned char *w = (unsigned char *)s->d_ws;
     std::vector<unsigned char> meta(off_gr, 0);
     std::vector<int32_t> ny(T + 1, 0), porder;
-    for (int t = 0; t < T; ++t) ny[t] = popc(ham->xmask[t] & ham->zmask[t]);
-    if (T) {
-        std::memcpy(meta.data(), ham->xmask, 8 * T);
-        std::memcpy(meta.data() + off_z, ham->zmask, 8 * T);
-        std::memcpy(meta.data() + off_c, ham->coeff, 8 * T);
-        std::memcpy(meta.data() + off_ny, ny.data(), 4 * T);
+    // terms ordered by X mask (stable), so that the kernel gathers once per
+    // distinct mask
+    std::vector<int> tord(T);
+    for (int t = 0; t < T; ++t) tord[t] = t;
+    std::stable_sort(tord.begin(), tord.end(),
+                     [&](int a, int b) { return ham->xmask[a] < ham->xmask[b]; });
+    for (int q = 0; q < T; ++q) {
+        const int t = tord[q];
+        ny[q] = popc(ham->xmask[t] & ham->zmask[t]);
+        std::memcpy(meta.data() + 8 * (size_t)q, &ham->xmask[t], 8);
+        std::memcpy(meta.data() + off_z + 8 * (size_t)q, &ham->zmask[t], 8);
+        std::memcpy(meta.data() + off_c + 8 * (size_t)q, &ham->coeff[t], 8);
     }
+    if (T) std::memcpy(meta.data() + off_ny, ny.data(), 4 * T);
     for (int g = G - 1; g >= 0; --g)
         if (axis[g]) porder.push_back(param[g]);
     if (!porder.empty()) std::memcpy(meta.data() + off_po, porder.data(), 4 * porder.size());
