@@ -15,6 +15,8 @@ only marshals numpy arrays and strings calls together:
 * ``measure``/``sample``/``dealloc``/``prob_bits``/``probs``: the reductions.
 * ``grad_param_shift`` / ``grad_fd``: gradients of <H> by re-running the
   forward circuit; the shift rule is exact for exp(-i theta P / 2) gates.
+* ``apply_math``    an emulated math gate (Sec. 4.3.3): a tabulated classical
+                    bijection applied to a register of a superposition.
 
 Parity status of every function is stated in the module docstring of the
 test that pins it (tests/test_oracle_pins.py).
@@ -70,6 +72,9 @@ def _load():
         lib.oracle_sample.restype = c_i
         lib.oracle_dealloc.argtypes = [P(c_d), c_i, c_i, c_d, P(c_d)]
         lib.oracle_dealloc.restype = c_i
+        lib.oracle_apply_math.argtypes = [P(c_d), c_i, c_i, P(c_i), P(ctypes.c_uint32), c_i,
+                                          P(c_i)]
+        lib.oracle_apply_math.restype = c_i
         _lib = lib
     return _lib
 
@@ -193,6 +198,26 @@ def dealloc(psi: np.ndarray, qubit: int, tau: float):
     if v < 0:
         raise ValueError("qubit %d is not in a classical state" % qubit)
     return v, out
+
+
+def apply_math(psi: np.ndarray, table, qubits: Sequence[int], controls: Sequence[int] = ()):
+    """Emulated math gate in place (Sec. 4.3.3): the register `qubits`
+    (first = least significant) takes the value table[x] wherever the controls
+    are 1.  `table` must be a permutation of range(2**len(qubits))."""
+    n = _nq(psi)
+    w = len(qubits)
+    tab = np.ascontiguousarray(table, dtype=np.uint32)
+    assert tab.shape == (1 << w,)
+    q = np.ascontiguousarray(qubits, dtype=np.intc)
+    c = np.ascontiguousarray(controls if len(controls) else [0], dtype=np.intc)
+    qs = list(qubits) + list(controls)
+    assert len(set(qs)) == len(qs) and all(0 <= x < n for x in qs)
+    rc = _load().oracle_apply_math(_dp(psi.view(np.float64)), n, w, _ip(q),
+                                   tab.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                   len(controls), _ip(c))
+    if rc != 0:
+        raise ValueError("oracle_apply_math: bad arguments or the table is not a permutation")
+    return psi
 
 
 def allocate(psi: np.ndarray, count: int = 1) -> np.ndarray:

@@ -236,3 +236,46 @@ int oracle_dealloc(const double *psi_d, int n, int q, double tau, double *out_d)
     }
     return value;
 }
+
+/* Emulated math gate (Sec. 4.3.3: a gate deriving from BasicMathGate applies
+ * a classical function to a superposition of register values directly,
+ * instead of its decomposition into 1- and 2-qubit gates).  The register is
+ * qubits[0..w-1], qubits[0] the least significant bit; f is tabulated as
+ * table[x] for x = 0..2^w-1 and must be a bijection (else -1: the map would
+ * not be unitary).  For every index i whose control bits are all 1, the
+ * amplitude psi[i] moves to the index that holds the register value
+ * table[x(i)] and the same other bits; every other amplitude stays. */
+int oracle_apply_math(double *psi_d, int n, int w, const int *qubits,
+                      const uint32_t *table, int nc, const int *controls)
+{
+    if (w < 1 || w > 30 || n < w + nc) return -1;
+    cplx *psi = (cplx *)psi_d;
+    const uint64_t dim = (uint64_t)1 << n;
+    const uint64_t size = (uint64_t)1 << w;
+    unsigned char *seen = (unsigned char *)calloc(size, 1);
+    cplx *out = (cplx *)malloc(sizeof(cplx) * dim);
+    if (!seen || !out) { free(seen); free(out); return -1; }
+    for (uint64_t x = 0; x < size; ++x) {
+        if (table[x] >= size || seen[table[x]]) { free(seen); free(out); return -1; }
+        seen[table[x]] = 1;
+    }
+    for (uint64_t i = 0; i < dim; ++i) {
+        int ok = 1;
+        for (int j = 0; j < nc; ++j)
+            if (!bit_of(i, controls[j])) ok = 0;
+        if (!ok) { out[i] = psi[i]; continue; }
+        uint64_t x = 0, rest = i;
+        for (int b = 0; b < w; ++b) {
+            x |= (uint64_t)bit_of(i, qubits[b]) << b;
+            rest &= ~((uint64_t)1 << qubits[b]);
+        }
+        const uint64_t y = table[x];
+        uint64_t j = rest;
+        for (int b = 0; b < w; ++b)
+            if ((y >> b) & 1) j |= (uint64_t)1 << qubits[b];
+        out[j] = psi[i];
+    }
+    memcpy(psi, out, sizeof(cplx) * dim);
+    free(seen); free(out);
+    return 0;
+}

@@ -8,7 +8,10 @@ Pauli purity) and the worked examples the paper prints (the 3-qubit Entangle
 histogram of Sec. 4.3.1, teleportation and Grover of App. A).
 
 Pinned: apply, run, probs, prob_bits, norm2, expectation, measure, sample,
-dealloc, allocate, grad_param_shift, grad_fd.
+dealloc, allocate, grad_param_shift, grad_fd, apply_math (emulated math gates:
+closed forms of AddConstant and modular multiplication on basis states, the
+QFT-phase-QFT^-1 construction of AddConstant through ``apply`` and through the
+gate-level Draper adder, the X gate as the 1-bit table).
 """
 import json
 import math
@@ -187,6 +190,90 @@ def test_simcomparison_fwht_closed_form(rng):
     sign = np.array([[(-1) ** bin(x & y).count("1") for x in xs] for y in xs])
     want = sign @ amp / (1 << n)
     assert np.max(np.abs(psi - want)) <= 1e-13
+
+
+# -------------------------------------------------------- emulated math gates
+def _reg_index(qubits, x, rest=0):
+    i = rest
+    for b, q in enumerate(qubits):
+        if (x >> b) & 1:
+            i |= 1 << q
+    return i
+
+
+def test_math_add_constant_on_basis_states():
+    # AddConstant(c) | quint maps |x> to |x + c mod 2^w>, other qubits untouched
+    n, reg, c = 7, [1, 4, 5, 2], 11
+    tab = W.add_constant_table(len(reg), c)
+    for x in range(16):
+        for rest in (0, 1 << 0, (1 << 3) | (1 << 6)):
+            psi = oracle.basis_state(n, _reg_index(reg, x, rest))
+            oracle.apply_math(psi, tab, reg)
+            want = oracle.basis_state(n, _reg_index(reg, (x + c) % 16, rest))
+            assert np.array_equal(psi, want)
+
+
+def test_math_add_constant_is_qft_phase_inverse_qft(rng):
+    # the decomposition the paper gives for AddConstant: QFT on the register,
+    # addition in the phases, inverse QFT (shift theorem of the DFT), here as
+    # dense controlled gates through oracle.apply, on a random state
+    n, reg, ctrl, c = 7, [0, 3, 5, 6], [2], 5
+    N = 1 << len(reg)
+    k = np.arange(N)
+    F = np.exp(2j * np.pi * np.outer(k, k) / N) / math.sqrt(N)
+    D = np.diag(np.exp(2j * np.pi * c * k / N))
+    psi0 = random_state(rng, n)
+    gates = psi0.copy()
+    oracle.apply(gates, F, reg, ctrl)
+    oracle.apply(gates, D, reg, ctrl)
+    oracle.apply(gates, F.conj().T, reg, ctrl)
+    emu = psi0.copy()
+    oracle.apply_math(emu, W.add_constant_table(len(reg), c), reg, ctrl)
+    assert np.max(np.abs(emu - gates)) <= 1e-13
+
+
+def test_math_add_constant_matches_draper_circuit(rng):
+    n, reg, c = 8, [6, 1, 3, 7, 4], 19
+    psi0 = random_state(rng, n)
+    emu = oracle.apply_math(psi0.copy(), W.add_constant_table(len(reg), c), reg)
+    gate_level = oracle.run(W.draper_add(n, c, reg), psi0.copy())
+    assert np.max(np.abs(emu - gate_level)) <= 1e-12
+
+
+def test_math_modular_multiplication(rng):
+    # x -> a x mod N on x < N (x itself above): a bijection when gcd(a, N) = 1;
+    # multiplying by a and then by a^-1 mod N restores the state exactly
+    w, N, a = 5, 21, 2
+    ainv = pow(a, -1, N)
+    tab, inv = W.mul_mod_table(w, a, N), W.mul_mod_table(w, ainv, N)
+    n, reg, ctrl = 8, [7, 0, 2, 5, 3], [4]
+    for x in range(1 << w):
+        psi = oracle.basis_state(n, _reg_index(reg, x, 1 << 4))
+        oracle.apply_math(psi, tab, reg, ctrl)
+        want = (a * x) % N if x < N else x
+        assert psi[_reg_index(reg, want, 1 << 4)] == 1.0
+        off = oracle.basis_state(n, _reg_index(reg, x))     # control 0: unchanged
+        assert np.array_equal(oracle.apply_math(off.copy(), tab, reg, ctrl), off)
+    psi0 = random_state(rng, n)
+    psi = oracle.apply_math(psi0.copy(), tab, reg, ctrl)
+    oracle.apply_math(psi, inv, reg, ctrl)
+    assert np.array_equal(psi, psi0)
+
+
+def test_math_one_bit_table_is_x_gate(rng):
+    n = 5
+    psi0 = random_state(rng, n)
+    a = oracle.apply_math(psi0.copy(), np.array([1, 0]), [3], [0, 4])
+    b = oracle.apply(psi0.copy(), W.X, [3], [0, 4])
+    assert np.array_equal(a, b)
+
+
+def test_math_rejects_non_bijection():
+    psi = oracle.zero_state(4)
+    with pytest.raises(ValueError):
+        oracle.apply_math(psi, np.array([0, 1, 1, 3]), [0, 2])
+    with pytest.raises(ValueError):
+        oracle.apply_math(psi, np.array([0, 1, 2, 4]), [0, 2])
 
 
 # ------------------------------------------------------------ probabilities

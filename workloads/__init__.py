@@ -206,16 +206,39 @@ def basis_prep(n: int, x: int) -> Circuit:
     return c
 
 
-def draper_add(n: int, const: int) -> Circuit:
-    """Constant adder in Fourier space (Sec. 3): QFT, a phase R(2 pi c 2^j / 2^n)
-    on qubit j, inverse QFT; maps |x> to |x + c mod 2^n>."""
-    c = qft(n)
-    c.label = f"draper-{n}-{const}"
-    for j in range(n):
-        ang = 2 * math.pi * ((const * (1 << j)) % (1 << n)) / (1 << n)
-        c.add(phase(ang), (j,), name="phase")
-    c.gates += qft(n, inverse=True).gates
+def draper_add(n: int, const: int, qubits: Optional[Sequence[int]] = None) -> Circuit:
+    """Constant adder in Fourier space (Sec. 3): QFT, a phase R(2 pi c 2^j / 2^m)
+    on register qubit j, inverse QFT; maps |x> to |x + c mod 2^m> on the
+    register ``qubits`` (default 0..n-1; bit j of x is qubits[j])."""
+    q = list(range(n)) if qubits is None else list(qubits)
+    m = len(q)
+    c = qft(n, q)
+    c.n = max(n, c.n)
+    c.label = f"draper-{m}-{const}"
+    for j in range(m):
+        ang = 2 * math.pi * ((const * (1 << j)) % (1 << m)) / (1 << m)
+        c.add(phase(ang), (q[j],), name="phase")
+    c.gates += qft(n, q, inverse=True).gates
     return c
+
+
+def add_constant_table(w: int, const: int) -> np.ndarray:
+    """The classical function of the AddConstant math gate (Sec. 3,
+    Sec. 4.3.3), tabulated: x -> x + c mod 2^w."""
+    x = np.arange(1 << w, dtype=np.uint64)
+    return ((x + np.uint64(const % (1 << w))) % np.uint64(1 << w)).astype(np.uint32)
+
+
+def mul_mod_table(w: int, a: int, modulus: int) -> np.ndarray:
+    """x -> a x mod N for x < N and x itself for N <= x < 2^w, the modular
+    multiplication of Shor's algorithm (Sec. 5) as a bijection of the w-bit
+    register (gcd(a, N) = 1, N <= 2^w)."""
+    assert math.gcd(a, modulus) == 1 and 0 < modulus <= (1 << w)
+    x = np.arange(1 << w, dtype=np.uint64)
+    out = x.copy()
+    low = x < modulus
+    out[low] = (np.uint64(a % modulus) * x[low]) % np.uint64(modulus)
+    return out.astype(np.uint32)
 
 
 def ghz(n: int) -> Circuit:
