@@ -264,6 +264,74 @@ def form_simcomparison(n: int = 30):
     return out
 
 
+def form_emulation(n: int = 30, w: int = 20):
+    """Emulated math gates (Sec. 4.3.3) at 30 qubits complex128: AddConstant
+    and Shor's controlled modular multiplication on a 20-bit register as one
+    gather pass each, beside the gate-level AddConstant (QFT, phases, inverse
+    QFT: the decomposition the paper gives) run through the fused tile path.
+    The state is a product of seeded Haar 1-qubit states."""
+    import torch
+    import workloads as W
+    from paper_1612_08091_amd import qsv as Q
+    rng = np.random.default_rng(W.SEED_BASE + 6)
+    reg = list(range(6, 6 + w))
+    const, a, N = 123457, 5, 1048573
+    add_tab = W.add_constant_table(w, const)
+    mul_tab = W.mul_mod_table(w, a, N)
+    prep = [W.haar_2x2(rng) for _ in range(n)]
+    idx = rng.integers(0, 1 << n, 1024, dtype=np.uint64)
+    sim = Q.Simulator(n_max=n, dtype="c128", mode="tiled", k_max=2, timing=True)
+    sim.allocate(n)
+
+    def prepare():
+        sim.reset()
+        for q in range(n):
+            sim.apply(prep[q], [q])
+        sim.flush()
+        sim.synchronize()
+
+    def timed(fn, reps=3):
+        best = None
+        for _ in range(reps):
+            prepare()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            sim.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    sim.reset_stats()
+    t_add = timed(lambda: sim.apply_math(reg, add_tab))
+    emu = sim.get_amplitudes(idx)
+    k_add = sim.kernel_times()["mono"]      # the gather kernels (HIP events)
+    sim.reset_stats()
+    t_mul = timed(lambda: sim.apply_math(reg, mul_tab, [0]))
+    k_mul = sim.kernel_times()["mono"]
+    adder = W.draper_add(n, const, reg)
+    prepare()
+    sim.run(adder)
+    _, adder_passes = sim.plan()
+    t_gates = timed(lambda: (sim.run(adder), sim.flush()), reps=2)
+    gates = sim.get_amplitudes(idx)
+    sim.close()
+    log("  emulation: add %.4f s, mulmod %.4f s, gate-level adder %.3f s" % (t_add, t_mul, t_gates))
+    return {"workload": "%d-qubit product state, complex128; %d-bit register" % (n, w),
+            "add_constant_emulated": {
+                "s": t_add, "kernel_ms": k_add[0] / max(k_add[1], 1),
+                "kernel_GBps": k_add[2] / max(k_add[1], 1) / (k_add[0] / max(k_add[1], 1) * 1e-3) / 1e9,
+                "kernel_pct_hbm_peak": k_add[2] / (k_add[0] * 1e-3) / HBM_PEAK},
+            "mul_mod_N_controlled_emulated": {
+                "s": t_mul, "kernel_ms": k_mul[0] / max(k_mul[1], 1),
+                "kernel_GBps": k_mul[2] / max(k_mul[1], 1) / (k_mul[0] / max(k_mul[1], 1) * 1e-3) / 1e9,
+                "kernel_pct_hbm_peak": k_mul[2] / (k_mul[0] * 1e-3) / HBM_PEAK},
+            "add_constant_gate_level": {"s": t_gates, "gates": len(adder.gates),
+                                        "passes": adder_passes},
+            "emulation_speedup": t_gates / t_add,
+            "max_abs_diff_emulated_vs_gates": float(np.max(np.abs(emu - gates)))}
+
+
 def form_batched():
     """Config 3: 4096 HEA circuits (8..20 qubits, depth 6) with 64-term Pauli
     sums, complex64, one persistent graph-captured launch per evaluation."""
@@ -350,7 +418,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the 32-qubit precision, batched and adjoint forms")
     ap.add_argument("--only-form", default="",
-                    choices=["", "adjoint", "batched", "precision", "fusion", "simcomparison"],
+                    choices=["", "adjoint", "batched", "precision", "fusion", "simcomparison",
+                             "emulation"],
                     help="run just this form, print its JSON object and exit (for profiling)")
     args = ap.parse_args()
 
@@ -374,7 +443,8 @@ def main():
     if args.only_form:
         forms = {"adjoint": form_adjoint, "batched": form_batched, "precision": form_precision,
                  "fusion": lambda: form_fusion_qft(args.qubits),
-                 "simcomparison": lambda: form_simcomparison(args.qubits)}
+                 "simcomparison": lambda: form_simcomparison(args.qubits),
+                 "emulation": lambda: form_emulation(args.qubits)}
         print(json.dumps({args.only_form: forms[args.only_form]()}))
         return
 
@@ -456,6 +526,8 @@ def main():
         log("precision form done")
         extra["batched"] = form_batched()
         log("batched form done")
+        extra["emulation_30q"] = form_emulation(n)
+        log("emulation form done")
         extra["adjoint_24q"] = form_adjoint()
         log("adjoint form done")
 

@@ -137,6 +137,22 @@ qsv_status qsv_qubits(const qsv_sim *sim, int32_t *n, int32_t *ids);
 qsv_status qsv_apply(qsv_sim *sim, const double *U, int32_t k, const int32_t *targets,
                      int32_t c, const int32_t *controls);
 
+/* Emulated math gate (Sec. 4.3.3: a BasicMathGate such as AddConstant applied
+ * as the classical function it computes instead of its gate decomposition).
+ * The register is qubits[0..w-1] (qubit ids, qubits[0] the least significant
+ * bit of the register value x); table[x] (2^w entries, host memory, copied)
+ * is the new value, and must be a permutation of 0..2^w-1 so that the map is
+ * unitary.  For every basis state whose controls[0..c-1] are all |1>, its
+ * amplitude moves to the basis state holding table[x] in the register and
+ * the same values elsewhere; the other amplitudes stay.  Flushes the queue,
+ * then runs at once (a gather into a second state-sized device buffer that
+ * the handle keeps, then a pointer swap, or a copy back into a borrowed
+ * state).  EINVAL: w outside 1..26, unknown or repeated qubits, w + c above
+ * the live qubits, NULL table, or a table that is not a permutation (checked
+ * before anything runs); ENOMEM if the second buffer cannot be allocated. */
+qsv_status qsv_apply_math(qsv_sim *sim, int32_t w, const int32_t *qubits, const uint32_t *table,
+                          int32_t c, const int32_t *controls);
+
 /* Execute every queued gate (Sec. 4.1.3 eng.flush()): plan fusion and passes,
  * enqueue the kernels on the stream.  Asynchronous. */
 qsv_status qsv_flush(qsv_sim *sim);

@@ -21,6 +21,7 @@
 #include "../../include/qsv.h"
 #include "adjoint_tile.hpp"
 #include "device.hpp"
+#include "math_gate.hpp"
 #include "qsv_internal.hpp"
 #include "tileprog.hpp"
 
@@ -68,6 +69,9 @@ struct qsv_sim {
     double k_ms[QSV_K_COUNT] = {0, 0, 0, 0};
     uint64_t k_launch[QSV_K_COUNT] = {0, 0, 0, 0};
     double k_bytes[QSV_K_COUNT] = {0, 0, 0, 0};
+    // second state buffer of the math gates (same capacity as the state)
+    void *d_alt = nullptr;
+    uint64_t alt_amps = 0;
     // adjoint / scratch vectors
     void *d_vec[3] = {nullptr, nullptr, nullptr};
     uint64_t vec_amps = 0;
@@ -590,6 +594,7 @@ qsv_status qsv_destroy(qsv_sim *s) {
     if (s->materialized || s->d_ws || s->slot[0].h || s->slot[1].h) (void)hipStreamSynchronize(s->stream);
     if (s->owns_state && s->d_state) (void)hipFree(s->d_state);
     if (s->d_ws) (void)hipFree(s->d_ws);
+    if (s->d_alt) (void)hipFree(s->d_alt);
     if (s->d_small) (void)hipFree(s->d_small);
     for (auto &sl : s->slot) {
         if (sl.h) (void)hipHostFree(sl.h);
@@ -724,6 +729,70 @@ qsv_status qsv_apply(qsv_sim *s, const double *U, int32_t k, const int32_t *targ
 qsv_status qsv_flush(qsv_sim *s) {
     QSV_CHECK(s);
     return do_flush(s);
+}
+
+qsv_status qsv_apply_math(qsv_sim *s, int32_t w, const int32_t *qubits, const uint32_t *table,
+                          int32_t c, const int32_t *controls) {
+    QSV_CHECK(s);
+    if (!qubits || !table || (c > 0 && !controls)) return fail(s, QSV_EINVAL, "NULL argument");
+    if (w < 1 || w > qsv::dev::kMaxMathBits)
+        return fail(s, QSV_EINVAL, "register width must be in 1..26");
+    if (c < 0 || w + c > s->n) return fail(s, QSV_EINVAL, "too many qubits for the register");
+    uint64_t regmask = 0, ctrl = 0;
+    QSV_TRY(check_ids(s, w, qubits, &regmask));
+    QSV_TRY(check_ids(s, c, controls, &ctrl));
+    if (regmask & ctrl) return fail(s, QSV_EINVAL, "a control is also a register qubit");
+    // the table must be a bijection; the kernel gathers through its inverse
+    const uint32_t size = 1u << w;
+    std::vector<uint32_t> inv(size, 0xffffffffu);
+    for (uint32_t x = 0; x < size; ++x) {
+        const uint32_t y = table[x];
+        if (y >= size || inv[y] != 0xffffffffu)
+            return fail(s, QSV_EINVAL, "math table is not a permutation of 0..2^w-1");
+        inv[y] = x;
+    }
+    qsv::dev::MathArgs a{};
+    a.regmask = regmask;
+    a.ctrl = ctrl;
+    a.w = w;
+    a.shift = s->pos_of[qubits[0]];
+    for (int b = 0; b < w; ++b) {
+        a.pos[b] = (uint32_t)s->pos_of[qubits[b]];
+        if ((int)a.pos[b] != a.shift + b) a.shift = -1;
+    }
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    if (s->alt_amps < s->cap_amps) {
+        if (s->d_alt) {
+            QSV_HIP(s, hipStreamSynchronize(s->stream));
+            QSV_HIP(s, hipFree(s->d_alt));
+            s->d_alt = nullptr;
+            s->alt_amps = 0;
+        }
+        hipError_t e = hipMalloc(&s->d_alt, s->cap_amps * s->elem());
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            s->d_alt = nullptr;
+            return fail(s, QSV_ENOMEM, "hipMalloc of the math gate's second state buffer failed");
+        }
+        s->alt_amps = s->cap_amps;
+    }
+    void *dinv = nullptr;
+    QSV_TRY(stage(s, inv.data(), (size_t)size * sizeof(uint32_t), &dinv));
+    const int tok = tbegin(s);
+    QSV_HIP(s, qsv::dev::math_gather(s->opt.dtype, s->d_state, s->d_alt, s->dim(), a,
+                                     (const uint32_t *)dinv, s->stream));
+    tend(s, tok, QSV_K_MONO, 2.0 * (double)s->dim() * s->elem());
+    if (s->owns_state) {
+        std::swap(s->d_state, s->d_alt);
+        std::swap(s->cap_amps, s->alt_amps);
+    } else {
+        QSV_HIP(s, hipMemcpyAsync(s->d_state, s->d_alt, s->dim() * s->elem(),
+                                  hipMemcpyDeviceToDevice, s->stream));
+    }
+    s->stats.gates += 1;
+    s->stats.amp_gate_updates += (double)s->dim();
+    return QSV_OK;
 }
 
 qsv_status qsv_synchronize(qsv_sim *s) {

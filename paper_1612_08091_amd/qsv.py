@@ -88,6 +88,7 @@ _SIGS = {
     "qsv_deallocate": (ctypes.c_int, [_P, ctypes.c_int32]),
     "qsv_qubits": (ctypes.c_int, [_P, _P, _P]),
     "qsv_apply": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
+    "qsv_apply_math": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P]),
     "qsv_flush": (ctypes.c_int, [_P]),
     "qsv_synchronize": (ctypes.c_int, [_P]),
     "qsv_get_probability": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
@@ -236,6 +237,18 @@ class Simulator:
         c = np.ascontiguousarray(list(controls) or [0], dtype=np.int32)
         _check(lib.qsv_apply(self._h, _ptr(u), len(targets), _ptr(t), len(controls), _ptr(c)),
                self._h)
+
+    def apply_math(self, qubits: Sequence[int], table, controls: Sequence[int] = ()):
+        """Emulated math gate (Sec. 4.3.3): the register ``qubits`` (first =
+        least significant bit) takes the value table[x]; ``table`` is a
+        permutation of range(2**len(qubits)).  Flushes and runs at once."""
+        tab = np.ascontiguousarray(table, dtype=np.uint32)
+        if tab.shape != (1 << len(qubits),):
+            raise ValueError("table must have 2**len(qubits) entries")
+        q = np.ascontiguousarray(list(qubits) or [0], dtype=np.int32)
+        c = np.ascontiguousarray(list(controls) or [0], dtype=np.int32)
+        _check(lib.qsv_apply_math(self._h, len(qubits), _ptr(q), _ptr(tab), len(controls),
+                                  _ptr(c)), self._h)
 
     def run(self, circuit, qubit_ids: Optional[Sequence[int]] = None):
         """Queue every gate of a circuit; circuit qubit j -> qubit_ids[j]."""
@@ -446,6 +459,28 @@ def adjoint_gradient(sim: Simulator, circuit, ham, theta=None):
     _check(lib.qsv_adjoint_gradient(sim._h, ctypes.byref(fc.struct), ctypes.byref(fp.struct),
                                     ctypes.byref(val), _ptr(grad)), sim._h)
     return val.value, grad[: fc.n_params]
+
+
+def math_table(func, widths: Sequence[int]) -> np.ndarray:
+    """Tabulate a BasicMathGate-style function (Sec. 4.3.3) of several
+    registers: ``func(*values) -> tuple of new values``, register r holding
+    widths[r] bits, packed least significant register first.  ``func`` is
+    called once on numpy arrays of all register values (so x + c, a * x % N
+    and the like vectorise); the result must be a permutation."""
+    total = int(sum(widths))
+    x = np.arange(1 << total, dtype=np.uint64)
+    vals, off = [], 0
+    for w in widths:
+        vals.append((x >> np.uint64(off)) & np.uint64((1 << w) - 1))
+        off += w
+    out = func(*vals)
+    if not isinstance(out, (tuple, list)):
+        out = (out,)
+    packed, off = np.zeros_like(x), 0
+    for w, v in zip(widths, out):
+        packed |= (np.asarray(v, dtype=np.uint64) & np.uint64((1 << w) - 1)) << np.uint64(off)
+        off += w
+    return packed.astype(np.uint32)
 
 
 class Batch:

@@ -72,6 +72,35 @@ def test_apply_validation_keeps_handle_usable():
     assert len(ops) >= 1
 
 
+def test_apply_math_validation_before_any_device_work():
+    s, ids = new_sim(6)
+    add3 = W.add_constant_table(3, 3)
+    expect_status(1, s.apply_math, [0, 1, 9], add3)                 # unknown id
+    expect_status(1, s.apply_math, [0, 1, 1], add3)                 # repeated qubit
+    expect_status(1, s.apply_math, [0, 1, 2], add3, [2])            # control in the register
+    expect_status(1, s.apply_math, [0, 1, 2], np.array([0, 1, 2, 3, 4, 5, 6, 6]))  # not a bijection
+    expect_status(1, s.apply_math, [0, 1, 2], np.array([0, 1, 2, 3, 4, 5, 6, 8]))  # value >= 2^w
+    expect_status(1, s.apply_math, [0, 1, 2, 3, 4], W.add_constant_table(5, 1), [5, 0])  # w + c > n
+    for w in (0, 27):                                               # width outside 1..26
+        tab = np.zeros(4, dtype=np.uint32)
+        q = np.arange(6, dtype=np.int32)
+        assert Q.lib.qsv_apply_math(s._h, w, Q._ptr(q), Q._ptr(tab), 0, Q._ptr(q)) == 1
+    # the pending queue is untouched by the rejected calls
+    s.apply(W.H, [0])
+    ops, npass = s.plan()
+    assert len(ops) == 1
+
+
+def test_math_table_packs_registers():
+    # two registers (3 and 2 bits): (a, b) -> (a + b mod 8, b)
+    tab = Q.math_table(lambda a, b: ((a + b) % 8, b), [3, 2])
+    assert tab.shape == (32,)
+    for a in range(8):
+        for b in range(4):
+            assert tab[a | (b << 3)] == ((a + b) % 8) | (b << 3)
+    assert np.array_equal(np.sort(tab), np.arange(32))
+
+
 def test_allocation_limits_and_ids():
     s = Q.Simulator(n_max=5, use_torch_stream=False)
     assert s.allocate(3) == [0, 1, 2]
