@@ -157,34 +157,28 @@ __device__ __forceinline__ void reg_g2(T *amp, const T *__restrict__ U, uint64_t
     }
 }
 
+// Diagonal op: amplitude i of the thread takes the factor val[r], where the
+// row index r = r_thr ^ op.wr[i] splits into the bits of the targets that
+// are not register bits (read once per thread from its global base gb;
+// op.pad0 marks them) and the bits from the register index (op.wr[i],
+// precomputed on the host for the current layout).  Controls that are not
+// register bits are in op.ctrl; those that are, as register-index bits, in
+// op.b.
 template <typename T, int NR, int RB>
 __device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const T *__restrict__ pool,
                                          uint64_t gb, const uint64_t *gbit) {
+    (void)gbit;
+    if ((gb & op.ctrl) != op.ctrl) return;
     const int k = op.a;
-    const uint64_t ctrl = op.ctrl;
+    const uint32_t thr_targets = op.pad0;
+    uint32_t rt = 0;
+    for (int q = 0; q < k; ++q)
+        if ((thr_targets >> q) & 1u) rt |= (uint32_t)((gb >> op.gt[q]) & 1u) << q;
     const T *val = pool + op.mat;
-    if (k <= 2) {
-        const T v0 = val[0], v1 = val[1];
-        const T v2 = k == 2 ? val[2] : v0, v3 = k == 2 ? val[3] : v1;
-        const int t0 = op.gt[0], t1 = k == 2 ? op.gt[1] : op.gt[0];
+    const int creg = op.b;
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            const uint64_t g = gb | greg<T, NR, RB>(i, gbit);
-            const bool on = (g & ctrl) == ctrl;
-            const bool b0 = (g >> t0) & 1, b1 = (k == 2) && ((g >> t1) & 1);
-            const T v = b1 ? (b0 ? v3 : v2) : (b0 ? v1 : v0);
-            amp[i] = csel(on, cmul(v, amp[i]), amp[i]);
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            const uint64_t g = gb | greg<T, NR, RB>(i, gbit);
-            if ((g & ctrl) != ctrl) continue;
-            uint32_t r = 0;
-            for (int q = 0; q < k; ++q) r |= (uint32_t)((g >> op.gt[q]) & 1u) << q;
-            amp[i] = cmul(val[r], amp[i]);
-        }
-    }
+    for (int i = 0; i < NR; ++i)
+        if ((i & creg) == creg) amp[i] = cmul(val[rt ^ op.wr[i]], amp[i]);
 }
 
 // Layout change through an LDS buffer of half a tile.  Slot J holds the same

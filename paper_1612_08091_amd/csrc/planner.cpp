@@ -159,6 +159,7 @@ namespace {
 
 struct Block {
     uint64_t all = 0, mix = 0;
+    bool diag = true;            // every member is diagonal
     std::vector<int> members;
 };
 
@@ -199,13 +200,19 @@ Op build_block(const std::vector<Op> &ops, const Block &b) {
     return out;
 }
 
-std::vector<Op> fuse_impl(const std::vector<Op> &ops, int k_max, uint64_t allowed) {
+// kd_max: a diagonal op fuses with a diagonal block it shares a qubit with up
+// to kd_max qubits (a run of phases stays one diagonal op, cheap to apply);
+// every other block stays within k_max.
+std::vector<Op> fuse_impl(const std::vector<Op> &ops, int k_max, uint64_t allowed, int kd_max) {
     std::vector<Block> blocks;
     std::vector<bool> frozen;   // blocks that may not absorb anything
+    kd_max = std::max(kd_max, k_max);
     for (int i = 0; i < (int)ops.size(); ++i) {
         const Op &op = ops[i];
         const uint64_t all = op.qubits(), mix = op.mixing();
-        const bool fusable = k_max >= 1 && (all & ~allowed) == 0 && popc(all) <= k_max;
+        const bool dg = op.kind == Op::MONO && op.diag;
+        const bool fusable =
+            k_max >= 1 && (all & ~allowed) == 0 && popc(all) <= (dg ? kd_max : k_max);
         // latest block that does not commute with op
         int j = -1;
         for (int b = (int)blocks.size() - 1; b >= 0; --b)
@@ -214,19 +221,25 @@ std::vector<Op> fuse_impl(const std::vector<Op> &ops, int k_max, uint64_t allowe
         if (fusable) {
             for (int b = std::max(j, 0); b < (int)blocks.size(); ++b) {
                 if (frozen[b]) continue;
-                if (popc(blocks[b].all | all) > k_max) continue;
-                int ov = popc(blocks[b].all & all);
+                const int ov = popc(blocks[b].all & all);
+                // a diagonal block grows past k_max only along shared qubits
+                // (a chain of phases on one qubit), so unrelated phases stay
+                // free to fuse with the dense gates next to them
+                const int lim = (dg && blocks[b].diag && ov > 0) ? kd_max : k_max;
+                if (popc(blocks[b].all | all) > lim) continue;
                 if (ov >= best_ov) { best = b; best_ov = ov; }
             }
         }
         if (best >= 0) {
             blocks[best].all |= all;
             blocks[best].mix |= mix;
+            blocks[best].diag = blocks[best].diag && dg;
             blocks[best].members.push_back(i);
         } else {
             Block nb;
             nb.all = all;
             nb.mix = mix;
+            nb.diag = dg;
             nb.members.push_back(i);
             blocks.push_back(nb);
             frozen.push_back(!fusable);
@@ -241,7 +254,7 @@ std::vector<Op> fuse_impl(const std::vector<Op> &ops, int k_max, uint64_t allowe
 }  // namespace
 
 std::vector<Op> fuse(const std::vector<Op> &ops, int k_max) {
-    return fuse_impl(ops, k_max, ~0ull);
+    return fuse_impl(ops, k_max, ~0ull, k_max);
 }
 
 // ---------------------------------------------------------- pass planning
@@ -289,7 +302,7 @@ std::vector<PlanGroup> plan_groups(const std::vector<PlanItem> &items, int n, in
 }
 
 std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_bits,
-                              int k_max) {
+                              int k_max, int kd_max) {
     std::vector<PlanItem> items(ops.size());
     for (size_t i = 0; i < ops.size(); ++i) {
         items[i].need = items[i].mix = ops[i].mixing();
@@ -302,7 +315,7 @@ std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_
         for (int i : g.idx) in_pass.push_back(ops[i]);
         Pass ps;
         ps.tile = g.tile;
-        ps.ops = fuse_impl(in_pass, k_max, g.tile);
+        ps.ops = fuse_impl(in_pass, k_max, g.tile, kd_max);
         passes.push_back(std::move(ps));
     }
     return passes;
@@ -312,6 +325,6 @@ std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_
 
 namespace qsv {
 std::vector<Pass> plan_tiled(const std::vector<Op> &ops, int n, int m, int k_max) {
-    return plan_passes(fuse(ops, k_max), n, m, 3, k_max);
+    return plan_passes(fuse_impl(ops, k_max, ~0ull, kMaxK), n, m, 3, k_max, kMaxK);
 }
 }  // namespace qsv

@@ -98,13 +98,14 @@ std::vector<PlanGroup> plan_groups(const std::vector<PlanItem> &items, int n, in
 // Group ops into passes whose mixing qubits fit in m tile bits, the lowest
 // `low_bits` positions always included (contiguous HBM runs).  Ops are moved
 // across each other only when they commute.  Then each pass is fused to
-// k_max (only ops with all their qubits inside the tile are fused).
+// k_max (only ops with all their qubits inside the tile are fused); runs of
+// diagonal ops fuse into diagonal ops of up to kd_max qubits (at least k_max).
 std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_bits,
-                              int k_max);
+                              int k_max, int kd_max = 0);
 
-// Whole-queue fusion to k_max first, then pass planning of the fused ops
-// (blocks are not cut at pass boundaries); three low bits stay in every
-// tile for contiguous HBM runs.
+// Whole-queue fusion to k_max first (diagonal runs to kMaxK qubits), then
+// pass planning of the fused ops (blocks are not cut at pass boundaries);
+// three low bits stay in every tile for contiguous HBM runs.
 std::vector<Pass> plan_tiled(const std::vector<Op> &ops, int n, int m, int k_max);
 
 // Dense 2^k x 2^k matrix of an op on its own target list (controls excluded).

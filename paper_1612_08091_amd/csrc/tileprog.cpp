@@ -42,7 +42,9 @@ dev::TileOp lds_form(const Op &op, const int *li, std::vector<double> &mats, int
     bool inside = true;
     for (int j = 0; j < op.k; ++j)
         if (li[op.t[j]] < 0) inside = false;
-    if (op.kind == Op::MONO && op.diag && !inside) {
+    // diagonal ops of more than three targets, or with targets outside the
+    // tile, take their phase index from the global index of each amplitude
+    if (op.kind == Op::MONO && op.diag && (!inside || op.k > 3)) {
         t.kind = dev::TOP_DIAG_GLOBAL;
         for (int j = 0; j < op.k; ++j) t.gt[j] = (uint32_t)op.t[j];
         t.gctrl = op.ctrl;
@@ -291,9 +293,30 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         dev::RegOp r{};
         r.kind = it.kind;
         if (it.kind == dev::ROP_DIAG) {
+            // split the row index and the controls into register bits (wr[i]
+            // per register index i, b) and the rest (pad0, ctrl)
+            auto reg_of = [&](int pos) {
+                for (int j = 0; j < rb; ++j)
+                    if (li[pos] >= 0 && cur_reg[j] == li[pos]) return j;
+                return -1;
+            };
             r.a = op.k;
-            r.ctrl = op.ctrl;
-            for (int j = 0; j < op.k; ++j) r.gt[j] = (uint32_t)op.t[j];
+            r.pad0 = 0;
+            for (int j = 0; j < op.k; ++j) {
+                r.gt[j] = (uint32_t)op.t[j];
+                const int rj = reg_of(op.t[j]);
+                if (rj < 0) r.pad0 |= 1u << j;
+                for (int i = 0; i < (1 << rb); ++i)
+                    if (rj >= 0 && ((i >> rj) & 1)) r.wr[i] |= 1u << j;
+            }
+            r.ctrl = 0;
+            r.b = 0;
+            for (int p = 0; p < 64; ++p)
+                if ((op.ctrl >> p) & 1) {
+                    const int rj = reg_of(p);
+                    if (rj >= 0) r.b |= 1 << rj;
+                    else r.ctrl |= 1ull << p;
+                }
             r.mat = (int64_t)(mats.size() / 2);
             for (int e = 0; e < (1 << op.k); ++e) push(mats, op.U[e]);
             prog.flops_per_amp += 6.0 * __builtin_popcount(op.touch) / (double)(1 << op.k) /
