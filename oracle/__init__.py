@@ -17,6 +17,9 @@ only marshals numpy arrays and strings calls together:
   forward circuit; the shift rule is exact for exp(-i theta P / 2) gates.
 * ``apply_math``    an emulated math gate (Sec. 4.3.3): a tabulated classical
                     bijection applied to a register of a superposition.
+* ``dm_*``          density matrices (the noise simulator Sec. 4.3.3 names as
+                    future work): gates as G rho G^dagger, channels as
+                    sum_j K_j rho K_j^dagger, Tr(rho P) per Pauli string.
 
 Parity status of every function is stated in the module docstring of the
 test that pins it (tests/test_oracle_pins.py).
@@ -75,6 +78,13 @@ def _load():
         lib.oracle_apply_math.argtypes = [P(c_d), c_i, c_i, P(c_i), P(ctypes.c_uint32), c_i,
                                           P(c_i)]
         lib.oracle_apply_math.restype = c_i
+        lib.oracle_dm_apply.argtypes = [P(c_d), c_i, P(c_d), c_i, P(c_i), c_i, P(c_i)]
+        lib.oracle_dm_apply.restype = c_i
+        lib.oracle_dm_kraus.argtypes = [P(c_d), c_i, c_i, P(c_d), c_i, P(c_i)]
+        lib.oracle_dm_kraus.restype = c_i
+        lib.oracle_dm_expectation.argtypes = [P(c_d), c_i, c_i, P(c_u64), P(c_u64), P(c_d),
+                                              P(c_d), P(c_d)]
+        lib.oracle_dm_expectation.restype = c_d
         _lib = lib
     return _lib
 
@@ -218,6 +228,70 @@ def apply_math(psi: np.ndarray, table, qubits: Sequence[int], controls: Sequence
     if rc != 0:
         raise ValueError("oracle_apply_math: bad arguments or the table is not a permutation")
     return psi
+
+
+# ------------------------------------------------------------ density matrices
+def _dn(rho: np.ndarray) -> int:
+    n = int(rho.shape[0]).bit_length() - 1
+    assert rho.shape == (1 << n, 1 << n) and rho.dtype == np.complex128 and rho.flags.c_contiguous
+    return n
+
+
+def dm_zero(n: int) -> np.ndarray:
+    rho = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+    rho[0, 0] = 1.0
+    return rho
+
+
+def dm_apply(rho: np.ndarray, matrix, targets: Sequence[int], controls: Sequence[int] = ()):
+    """rho <- G rho G^dagger in place, G the (controlled) gate."""
+    n = _dn(rho)
+    u = np.ascontiguousarray(matrix, dtype=np.complex128)
+    t = np.ascontiguousarray(targets, dtype=np.intc)
+    c = np.ascontiguousarray(controls if len(controls) else [0], dtype=np.intc)
+    if _load().oracle_dm_apply(_dp(rho.view(np.float64)), n, _dp(u.view(np.float64)),
+                               len(targets), _ip(t), len(controls), _ip(c)) != 0:
+        raise ValueError("oracle_dm_apply rejected its arguments")
+    return rho
+
+
+def dm_kraus(rho: np.ndarray, kraus, targets: Sequence[int]):
+    """rho <- sum_j K_j rho K_j^dagger in place (a quantum channel)."""
+    n = _dn(rho)
+    ks = np.ascontiguousarray(np.stack([np.asarray(k, dtype=np.complex128) for k in kraus]))
+    t = np.ascontiguousarray(targets, dtype=np.intc)
+    if _load().oracle_dm_kraus(_dp(rho.view(np.float64)), n, len(ks), _dp(ks.view(np.float64)),
+                               len(targets), _ip(t)) != 0:
+        raise ValueError("oracle_dm_kraus rejected its arguments")
+    return rho
+
+
+def dm_expectation(rho: np.ndarray, ham, return_terms: bool = False):
+    """(sum_t c_t Re Tr(rho P_t), sum_t c_t Im Tr(rho P_t)) [, per-term]."""
+    n = _dn(rho)
+    x = np.ascontiguousarray(ham.xmask, dtype=np.uint64)
+    z = np.ascontiguousarray(ham.zmask, dtype=np.uint64)
+    c = np.ascontiguousarray(ham.coeff, dtype=np.float64)
+    nt = len(c)
+    terms = np.zeros(max(nt, 1), dtype=np.complex128)
+    im = ctypes.c_double(0.0)
+    re = _load().oracle_dm_expectation(_dp(rho.view(np.float64)), n, nt, _up(x), _up(z), _dp(c),
+                                       _dp(terms.view(np.float64)), ctypes.byref(im))
+    if return_terms:
+        return re, im.value, terms[:nt]
+    return re, im.value
+
+
+def dm_run(events, n: int) -> np.ndarray:
+    """Apply a noisy circuit (workloads.NoisyCircuit events: ("gate", U,
+    targets, controls) or ("kraus", [K_j], targets)) to |0..0><0..0|."""
+    rho = dm_zero(n)
+    for ev in events:
+        if ev[0] == "gate":
+            dm_apply(rho, ev[1], ev[2], ev[3])
+        else:
+            dm_kraus(rho, ev[1], ev[2])
+    return rho
 
 
 def allocate(psi: np.ndarray, count: int = 1) -> np.ndarray:

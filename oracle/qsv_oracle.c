@@ -279,3 +279,102 @@ int oracle_apply_math(double *psi_d, int n, int w, const int *qubits,
     free(seen); free(out);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Density matrices (Sec. 4.3.3 names a density-matrix simulator for noise as
+ * future work).  rho is 2^n x 2^n, row-major, rho[r * 2^n + c].
+ * ---------------------------------------------------------------------- */
+
+/* rho <- G rho G^dagger for the (controlled) gate G = (U, targets, controls)
+ * on n qubits, or rho <- sum_j K_j rho K_j^dagger over nk Kraus matrices
+ * (kraus_d: nk matrices of 2^k x 2^k, controls ignored when nk > 1).  Both
+ * are written out from the definition: G (or K_j) is applied to every column
+ * of rho, then to every column of the conjugate transpose of the result.
+ * Returns 0, or -1 on bad arguments. */
+static int dm_conjugate(cplx *rho, int n, const double *u_d, int k, const int *targets,
+                        int nc, const int *controls, cplx *out)
+{
+    const uint64_t dim = (uint64_t)1 << n;
+    cplx *col = (cplx *)malloc(sizeof(cplx) * dim);
+    cplx *a = (cplx *)malloc(sizeof(cplx) * dim * dim);
+    if (!col || !a) { free(col); free(a); return -1; }
+    /* a = G rho */
+    for (uint64_t c = 0; c < dim; ++c) {
+        for (uint64_t r = 0; r < dim; ++r) col[r] = rho[r * dim + c];
+        if (oracle_apply((double *)col, n, u_d, k, targets, nc, controls) != 0) {
+            free(col); free(a); return -1;
+        }
+        for (uint64_t r = 0; r < dim; ++r) a[r * dim + c] = col[r];
+    }
+    /* out += (G a^dagger)^dagger = a G^dagger */
+    for (uint64_t r = 0; r < dim; ++r) {
+        for (uint64_t c = 0; c < dim; ++c) col[c] = conj(a[r * dim + c]);
+        if (oracle_apply((double *)col, n, u_d, k, targets, nc, controls) != 0) {
+            free(col); free(a); return -1;
+        }
+        for (uint64_t c = 0; c < dim; ++c) out[r * dim + c] += conj(col[c]);
+    }
+    free(col); free(a);
+    return 0;
+}
+
+int oracle_dm_apply(double *rho_d, int n, const double *u_d, int k, const int *targets,
+                    int nc, const int *controls)
+{
+    if (n < 1 || n > 12) return -1;
+    const uint64_t dim = (uint64_t)1 << n;
+    cplx *out = (cplx *)calloc(dim * dim, sizeof(cplx));
+    if (!out) return -1;
+    int rc = dm_conjugate((cplx *)rho_d, n, u_d, k, targets, nc, controls, out);
+    if (rc == 0) memcpy(rho_d, out, sizeof(cplx) * dim * dim);
+    free(out);
+    return rc;
+}
+
+int oracle_dm_kraus(double *rho_d, int n, int nk, const double *kraus_d, int k,
+                    const int *targets)
+{
+    if (n < 1 || n > 12 || nk < 1) return -1;
+    const uint64_t dim = (uint64_t)1 << n;
+    const size_t msz = (size_t)2 << (2 * k);   /* doubles per 2^k x 2^k complex matrix */
+    cplx *out = (cplx *)calloc(dim * dim, sizeof(cplx));
+    if (!out) return -1;
+    int dummy = 0;
+    for (int j = 0; j < nk; ++j)
+        if (dm_conjugate((cplx *)rho_d, n, kraus_d + j * msz, k, targets, 0, &dummy, out) != 0) {
+            free(out); return -1;
+        }
+    memcpy(rho_d, out, sizeof(cplx) * dim * dim);
+    free(out);
+    return 0;
+}
+
+/* Tr(rho P_t) for each Pauli string (X on xmask only, Z on zmask only, Y on
+ * both): the sum over r, c of rho[r][c] P[c][r], P[c][r] the product of the
+ * one-qubit entries.  Returns sum_t coeff_t Re Tr(rho P_t); imag_out gets the
+ * imaginary part, term_out (if not NULL) each Tr(rho P_t). */
+double oracle_dm_expectation(const double *rho_d, int n, int nterms, const uint64_t *xmask,
+                             const uint64_t *zmask, const double *coeff, double *term_out,
+                             double *imag_out)
+{
+    const cplx *rho = (const cplx *)rho_d;
+    const uint64_t dim = (uint64_t)1 << n;
+    double tot_re = 0.0, tot_im = 0.0;
+    for (int t = 0; t < nterms; ++t) {
+        cplx acc = 0;
+        for (uint64_t r = 0; r < dim; ++r)
+            for (uint64_t c = 0; c < dim; ++c) {
+                cplx p = 1.0;
+                for (int q = 0; q < n && p != 0; ++q) {
+                    int code = (int)((xmask[t] >> q) & 1u) + 2 * (int)((zmask[t] >> q) & 1u);
+                    p *= pauli_entry(code, bit_of(c, q), bit_of(r, q));
+                }
+                if (p != 0) acc += rho[r * dim + c] * p;
+            }
+        if (term_out) { term_out[2 * t] = creal(acc); term_out[2 * t + 1] = cimag(acc); }
+        tot_re += coeff[t] * creal(acc);
+        tot_im += coeff[t] * cimag(acc);
+    }
+    if (imag_out) *imag_out = tot_im;
+    return tot_re;
+}

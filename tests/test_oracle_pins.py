@@ -11,7 +11,10 @@ Pinned: apply, run, probs, prob_bits, norm2, expectation, measure, sample,
 dealloc, allocate, grad_param_shift, grad_fd, apply_math (emulated math gates:
 closed forms of AddConstant and modular multiplication on basis states, the
 QFT-phase-QFT^-1 construction of AddConstant through ``apply`` and through the
-gate-level Draper adder, the X gate as the 1-bit table).
+gate-level Draper adder, the X gate as the 1-bit table), dm_apply / dm_kraus /
+dm_expectation (pure states against the state-vector oracle, closed forms of
+the depolarizing, amplitude-damping and dephasing channels, trace
+preservation, Kronecker-product operators from tests/brute.py).
 """
 import json
 import math
@@ -274,6 +277,85 @@ def test_math_rejects_non_bijection():
         oracle.apply_math(psi, np.array([0, 1, 1, 3]), [0, 2])
     with pytest.raises(ValueError):
         oracle.apply_math(psi, np.array([0, 1, 2, 4]), [0, 2])
+
+
+# ------------------------------------------------------------ density matrices
+def test_dm_pure_state_follows_state_vector(rng):
+    # rho = |psi><psi| stays the projector of the state-vector oracle's state
+    n = 5
+    rho = oracle.dm_zero(n)
+    psi = oracle.zero_state(n)
+    for _ in range(25):
+        u, t, c = random_gate(rng, n)
+        oracle.dm_apply(rho, u, t, c)
+        oracle.apply(psi, u, t, c)
+    assert np.max(np.abs(rho - np.outer(psi, psi.conj()))) <= 1e-13
+    ham = W.random_pauli_dense(n, 12, rng)
+    re, im, terms = oracle.dm_expectation(rho, ham, return_terms=True)
+    re2, im2, terms2 = oracle.expectation(psi, ham, return_terms=True)
+    assert abs(re - re2) <= 1e-13 and np.max(np.abs(terms - terms2)) <= 1e-13
+
+
+def test_dm_gate_matches_dense_operator(rng):
+    n = 4
+    a = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+    rho = np.ascontiguousarray(a @ a.conj().T / np.trace(a @ a.conj().T))
+    u, t, c = W.haar_unitary(4, rng), [3, 1], [0]
+    G = brute.gate_operator(u, t, c, n)
+    want = G @ rho @ G.conj().T
+    got = oracle.dm_apply(rho.copy(), u, t, c)
+    assert np.max(np.abs(got - want)) <= 1e-13
+
+
+def test_dm_channel_closed_forms():
+    # one qubit: depolarizing keeps (1-p) of rho and adds p I/2; amplitude
+    # damping moves gamma of |1><1| to |0><0| and scales coherences by
+    # sqrt(1-gamma); dephasing scales coherences by 1-p
+    rho = np.array([[0.3, 0.2 - 0.1j], [0.2 + 0.1j, 0.7]], dtype=np.complex128)
+    p, g = 0.3, 0.4
+    dep = oracle.dm_kraus(rho.copy(), W.depolarizing(p), [0])
+    assert np.max(np.abs(dep - ((1 - p) * rho + p * np.eye(2) / 2))) <= 1e-15
+    ad = oracle.dm_kraus(rho.copy(), W.amplitude_damping(g), [0])
+    want = np.array([[0.3 + g * 0.7, math.sqrt(1 - g) * rho[0, 1]],
+                     [math.sqrt(1 - g) * rho[1, 0], (1 - g) * 0.7]])
+    assert np.max(np.abs(ad - want)) <= 1e-15
+    dp = oracle.dm_kraus(rho.copy(), W.dephasing(p), [0])
+    want = rho.copy()
+    want[0, 1] *= 1 - p
+    want[1, 0] *= 1 - p
+    assert np.max(np.abs(dp - want)) <= 1e-15
+
+
+def test_dm_channel_on_a_register_and_trace(rng):
+    # a channel on qubit 2 of a 4-qubit state equals I (x) K (x) I operators;
+    # a random Kraus set (sum K^dag K = I) keeps the trace
+    n = 4
+    a = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+    rho = np.ascontiguousarray(a @ a.conj().T / np.trace(a @ a.conj().T))
+    ks = W.amplitude_damping(0.25)
+    want = sum(brute.gate_operator(k, [2], [], n) @ rho @ brute.gate_operator(k, [2], [], n).conj().T
+               for k in ks)
+    got = oracle.dm_kraus(rho.copy(), ks, [2])
+    assert np.max(np.abs(got - want)) <= 1e-13
+    q, _ = np.linalg.qr(rng.standard_normal((8, 4)) + 1j * rng.standard_normal((8, 4)))
+    kr = [q[2 * j:2 * j + 2, :2] for j in range(4)]          # stacked isometry: sum K^dag K = I
+    kr = [np.ascontiguousarray(k) for k in kr]
+    assert np.allclose(sum(k.conj().T @ k for k in kr), np.eye(2))
+    out = oracle.dm_kraus(rho.copy(), kr, [1])
+    assert abs(np.trace(out) - 1.0) <= 1e-14
+    assert np.max(np.abs(out - out.conj().T)) <= 1e-15
+
+
+def test_dm_fully_depolarized_expectations_vanish(rng):
+    n = 3
+    rho = oracle.dm_run(W.noisy_brick(n, 2, 0.05, rng), n)
+    for q in range(n):
+        oracle.dm_kraus(rho, W.depolarizing(1.0), [q])
+    assert np.max(np.abs(rho - np.eye(8) / 8)) <= 1e-15
+    ham = W.random_pauli_dense(n, 10, rng)
+    re, im, terms = oracle.dm_expectation(rho, ham, return_terms=True)
+    ident = (np.asarray(ham.xmask) == 0) & (np.asarray(ham.zmask) == 0)
+    assert np.max(np.abs(terms[~ident])) <= 1e-15
 
 
 # ------------------------------------------------------------ probabilities

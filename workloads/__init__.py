@@ -222,6 +222,47 @@ def draper_add(n: int, const: int, qubits: Optional[Sequence[int]] = None) -> Ci
     return c
 
 
+# --------------------------------------------------------------------------
+# noise channels (Kraus operators) and noisy circuits
+# --------------------------------------------------------------------------
+def depolarizing(p: float):
+    """rho -> (1 - p) rho + p I/2 on one qubit."""
+    a, b = math.sqrt(1 - 3 * p / 4), math.sqrt(p / 4)
+    return [a * I2, b * X, b * Y, b * Z]
+
+
+def amplitude_damping(gamma: float):
+    """|1> decays to |0> with probability gamma."""
+    return [np.array([[1, 0], [0, math.sqrt(1 - gamma)]], dtype=np.complex128),
+            np.array([[0, math.sqrt(gamma)], [0, 0]], dtype=np.complex128)]
+
+
+def dephasing(p: float):
+    """Off-diagonal elements scaled by 1 - p."""
+    return [math.sqrt(1 - p / 2) * I2, math.sqrt(p / 2) * Z]
+
+
+def noisy_brick(n: int, layers: int, p: float, rng: np.random.Generator, gamma: float = 0.0):
+    """Events of a noisy brick circuit: per layer a Haar 1-qubit gate on every
+    qubit followed by depolarizing noise p on it, then CNOTs on alternating
+    neighbour pairs, each followed by depolarizing noise on both qubits and,
+    if gamma > 0, amplitude damping on the target.  Events are ("gate", U,
+    targets, controls) and ("kraus", [K_j], targets)."""
+    ev = []
+    dep = depolarizing(p)
+    for layer in range(layers):
+        for q in range(n):
+            ev.append(("gate", haar_2x2(rng), (q,), ()))
+            ev.append(("kraus", dep, (q,)))
+        for (a, b) in brick_pairs(n, layer):
+            ev.append(("gate", X, (b,), (a,)))
+            ev.append(("kraus", dep, (a,)))
+            ev.append(("kraus", dep, (b,)))
+            if gamma > 0:
+                ev.append(("kraus", amplitude_damping(gamma), (b,)))
+    return ev
+
+
 def add_constant_table(w: int, const: int) -> np.ndarray:
     """The classical function of the AddConstant math gate (Sec. 3,
     Sec. 4.3.3), tabulated: x -> x + c mod 2^w."""
