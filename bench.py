@@ -332,6 +332,41 @@ def form_emulation(n: int = 30, w: int = 20):
             "max_abs_diff_emulated_vs_gates": float(np.max(np.abs(emu - gates)))}
 
 
+def form_noise(n: int = 15, layers: int = 10):
+    """Density matrix of a noisy 15-qubit brick circuit (Haar 1-qubit gates
+    and CNOTs, each followed by depolarizing noise p = 1e-3 on its qubits and
+    amplitude damping 1e-3 on CNOT targets): vec(rho) is a 30-qubit complex128
+    vector; gates and channel superoperators run through the fused tile
+    passes.  Reports the time per circuit, the passes, and the trace."""
+    import torch
+    import workloads as W
+    from paper_1612_08091_amd import qsv as Q
+    ev = W.noisy_brick(n, layers, 1e-3, np.random.default_rng(W.SEED_BASE + 7), gamma=1e-3)
+    d = Q.DensityMatrix(n, dtype="c128", mode="tiled", k_max=2, timing=True)
+    d.run(ev)
+    _, npass = d.sim.plan()
+    times = []
+    for _ in range(2):
+        d.sim.reset()
+        d.run(ev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d.flush()
+        d.sim.synchronize()
+        times.append(time.perf_counter() - t0)
+    p = d.probabilities()
+    kt = d.sim.kernel_times()
+    d.close()
+    t = min(times)
+    gates = sum(1 for e in ev if e[0] == "gate")
+    return {"workload": "%d-qubit noisy brick, %d layers: %d gates, %d channels; vec(rho) on %d "
+                        "qubits, complex128" % (n, layers, gates, len(ev) - gates, 2 * n),
+            "s_per_circuit": t, "passes": npass,
+            "events_per_s": len(ev) / t,
+            "tile_kernel_ms_avg": kt["tile"][0] / max(kt["tile"][1], 1),
+            "trace_minus_one": float(p.sum() - 1.0)}
+
+
 def form_batched():
     """Config 3: 4096 HEA circuits (8..20 qubits, depth 6) with 64-term Pauli
     sums, complex64, one persistent graph-captured launch per evaluation."""
@@ -419,7 +454,7 @@ def main():
                     help="skip the 32-qubit precision, batched and adjoint forms")
     ap.add_argument("--only-form", default="",
                     choices=["", "adjoint", "batched", "precision", "fusion", "simcomparison",
-                             "emulation"],
+                             "emulation", "noise"],
                     help="run just this form, print its JSON object and exit (for profiling)")
     args = ap.parse_args()
 
@@ -444,7 +479,8 @@ def main():
         forms = {"adjoint": form_adjoint, "batched": form_batched, "precision": form_precision,
                  "fusion": lambda: form_fusion_qft(args.qubits),
                  "simcomparison": lambda: form_simcomparison(args.qubits),
-                 "emulation": lambda: form_emulation(args.qubits)}
+                 "emulation": lambda: form_emulation(args.qubits),
+                 "noise": form_noise}
         print(json.dumps({args.only_form: forms[args.only_form]()}))
         return
 
@@ -528,6 +564,8 @@ def main():
         log("batched form done")
         extra["emulation_30q"] = form_emulation(n)
         log("emulation form done")
+        extra["noise_density_matrix_15q"] = form_noise()
+        log("noise form done")
         extra["adjoint_24q"] = form_adjoint()
         log("adjoint form done")
 

@@ -153,6 +153,44 @@ qsv_status qsv_apply(qsv_sim *sim, const double *U, int32_t k, const int32_t *ta
 qsv_status qsv_apply_math(qsv_sim *sim, int32_t w, const int32_t *qubits, const uint32_t *table,
                           int32_t c, const int32_t *controls);
 
+/* ---------------------------------------------------------------------- */
+/* Density matrices (noise: Sec. 4.3.2 names stochastic noise models and a  */
+/* density-matrix simulator as future work).  A handle with 2n live qubits  */
+/* holds vec(rho) of an n-qubit density matrix: rho[r][c] at index          */
+/* r + 2^n c, so bit positions 0..n-1 index the row and n..2n-1 the column; */
+/* a fresh handle's |0..0> is rho = |0..0><0..0|.  System qubit j is bit    */
+/* position j (row) and j + n (column); the calls below take system qubit   */
+/* indices 0..n-1, not ids.  Gates and channels queue like qsv_apply and    */
+/* run through the same fusion and tile passes (on 2n qubits).              */
+/* ---------------------------------------------------------------------- */
+
+/* Queue rho <- G rho G^dagger for G = U on targets[k] (k <= 2) controlled by
+ * controls[c]: U on the row bits, conj(U) on the column bits.  EINVAL for an
+ * odd number of live qubits, indices outside 0..n-1 or repeated, k outside
+ * 1..2, c + k > n, or non-finite entries. */
+qsv_status qsv_dm_apply(qsv_sim *sim, const double *U, int32_t k, const int32_t *targets,
+                        int32_t c, const int32_t *controls);
+
+/* Queue the channel rho <- sum_j K_j rho K_j^dagger on targets[k] (k <= 2):
+ * kraus holds nk matrices of 2^k x 2^k (row-major, interleaved complex128).
+ * The superoperator M[r' + 2^k c'][r + 2^k c] = sum_j K_j[r'][r]
+ * conj(K_j[c'][c]) is formed on the host in complex128 and queued as one op
+ * on the k row bits and the k column bits.  The
+ * channel is taken as given (trace preservation is the caller's).  EINVAL as
+ * qsv_dm_apply, or nk < 1, or non-finite entries. */
+qsv_status qsv_dm_apply_kraus(qsv_sim *sim, int32_t nk, const double *kraus, int32_t k,
+                              const int32_t *targets);
+
+/* out[i] = Re rho[i][i] for i < 2^n (host memory): the probabilities of a
+ * measurement of all qubits.  Flushes; synchronises. */
+qsv_status qsv_dm_probabilities(qsv_sim *sim, double *out);
+
+/* *out = sum_t coeff[t] Re Tr(rho P_t); masks over system qubits 0..n-1 as in
+ * qsv_get_expectation_value (X only in xmask, Z only in zmask, Y in both).
+ * Flushes; synchronises. */
+qsv_status qsv_dm_expectation(qsv_sim *sim, int32_t nterms, const uint64_t *xmask,
+                              const uint64_t *zmask, const double *coeff, double *out);
+
 /* Execute every queued gate (Sec. 4.1.3 eng.flush()): plan fusion and passes,
  * enqueue the kernels on the stream.  Asynchronous. */
 qsv_status qsv_flush(qsv_sim *sim);

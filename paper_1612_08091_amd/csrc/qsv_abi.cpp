@@ -21,6 +21,7 @@
 #include "../../include/qsv.h"
 #include "adjoint_tile.hpp"
 #include "device.hpp"
+#include "dm.hpp"
 #include "math_gate.hpp"
 #include "qsv_internal.hpp"
 #include "tileprog.hpp"
@@ -523,6 +524,36 @@ qsv_status prob_split_host(qsv_sim *s, int pos, double *p0, double *p1) {
 void qsv::set_last_error(const std::string &msg) { g_err = msg; }
 
 // =================================================================== ABI
+// ----------------------------------------------------------- density matrices
+namespace {
+
+// Validate system qubit indices of a density-matrix call; n = live / 2.
+qsv_status dm_check(qsv_sim *s, int k, const int32_t *targets, int c, const int32_t *controls,
+                    int kmax, uint64_t *tmask, uint64_t *cmask) {
+    if ((s->n & 1) || s->n == 0)
+        return fail(s, QSV_EINVAL, "a density matrix needs an even, nonzero number of qubits");
+    const int n = s->n / 2;
+    if (!targets || (c > 0 && !controls)) return fail(s, QSV_EINVAL, "NULL argument");
+    if (k < 1 || k > kmax) return fail(s, QSV_EINVAL, "unsupported number of targets");
+    if (c < 0 || k + c > n) return fail(s, QSV_EINVAL, "too many qubits");
+    uint64_t seen = 0;
+    *tmask = *cmask = 0;
+    for (int j = 0; j < k + c; ++j) {
+        const int q = j < k ? targets[j] : controls[j - k];
+        if (q < 0 || q >= n || ((seen >> q) & 1))
+            return fail(s, QSV_EINVAL, "system qubit index out of range or repeated");
+        seen |= 1ull << q;
+        (j < k ? *tmask : *cmask) |= 1ull << q;
+    }
+    return QSV_OK;
+}
+
+void dm_queue(qsv_sim *s, Gate &&g) {
+    s->queue.push_back(std::move(g));
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *qsv_version(void) { return "qsv 0.1 (gfx950)"; }
@@ -729,6 +760,129 @@ qsv_status qsv_apply(qsv_sim *s, const double *U, int32_t k, const int32_t *targ
 qsv_status qsv_flush(qsv_sim *s) {
     QSV_CHECK(s);
     return do_flush(s);
+}
+
+
+qsv_status qsv_dm_apply(qsv_sim *s, const double *U, int32_t k, const int32_t *targets,
+                        int32_t c, const int32_t *controls) {
+    QSV_CHECK(s);
+    if (!U) return fail(s, QSV_EINVAL, "NULL argument");
+    uint64_t tm, cm;
+    QSV_TRY(dm_check(s, k, targets, c, controls, 2, &tm, &cm));
+    const int n = s->n / 2;
+    const int D = 1 << k;
+    Gate row, col;
+    row.k = col.k = k;
+    row.U.resize((size_t)D * D);
+    col.U.resize((size_t)D * D);
+    for (int i = 0; i < D * D; ++i) {
+        const double re = U[2 * i], im = U[2 * i + 1];
+        if (!std::isfinite(re) || !std::isfinite(im))
+            return fail(s, QSV_EINVAL, "non-finite matrix entry");
+        row.U[i] = cd(re, im);
+        col.U[i] = cd(re, -im);
+    }
+    for (int j = 0; j < k; ++j) {
+        row.t[j] = targets[j];
+        col.t[j] = targets[j] + n;
+    }
+    row.ctrl = cm;
+    col.ctrl = cm << n;
+    dm_queue(s, std::move(row));
+    dm_queue(s, std::move(col));
+    const int lim = s->opt.queue_limit > 0 ? s->opt.queue_limit : 4096;
+    if ((int)s->queue.size() >= lim) return do_flush(s);
+    return QSV_OK;
+}
+
+qsv_status qsv_dm_apply_kraus(qsv_sim *s, int32_t nk, const double *kraus, int32_t k,
+                              const int32_t *targets) {
+    QSV_CHECK(s);
+    if (!kraus || nk < 1) return fail(s, QSV_EINVAL, "no Kraus matrices");
+    uint64_t tm, cm;
+    QSV_TRY(dm_check(s, k, targets, 0, nullptr, 2, &tm, &cm));
+    const int n = s->n / 2;
+    const int D = 1 << k, DD = D * D;
+    for (size_t i = 0; i < (size_t)2 * nk * D * D; ++i)
+        if (!std::isfinite(kraus[i])) return fail(s, QSV_EINVAL, "non-finite Kraus entry");
+    // local index of the 2k-qubit op: row bits r (targets) low, column bits c high
+    Gate g;
+    g.k = 2 * k;
+    for (int j = 0; j < k; ++j) {
+        g.t[j] = targets[j];
+        g.t[k + j] = targets[j] + n;
+    }
+    g.U.assign((size_t)DD * DD, cd(0, 0));
+    for (int j = 0; j < nk; ++j) {
+        const double *K = kraus + (size_t)2 * j * D * D;
+        auto kv = [&](int a, int b) { return cd(K[2 * (a * D + b)], K[2 * (a * D + b) + 1]); };
+        for (int r2 = 0; r2 < D; ++r2)
+            for (int c2 = 0; c2 < D; ++c2)
+                for (int r = 0; r < D; ++r)
+                    for (int c = 0; c < D; ++c)
+                        g.U[(size_t)(r2 + D * c2) * DD + (r + D * c)] +=
+                            kv(r2, r) * std::conj(kv(c2, c));
+    }
+    dm_queue(s, std::move(g));
+    const int lim = s->opt.queue_limit > 0 ? s->opt.queue_limit : 4096;
+    if ((int)s->queue.size() >= lim) return do_flush(s);
+    return QSV_OK;
+}
+
+qsv_status qsv_dm_probabilities(qsv_sim *s, double *out) {
+    QSV_CHECK(s);
+    if (!out) return fail(s, QSV_EINVAL, "NULL argument");
+    if ((s->n & 1) || s->n == 0)
+        return fail(s, QSV_EINVAL, "a density matrix needs an even, nonzero number of qubits");
+    const int n = s->n / 2;
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    QSV_TRY(ensure_ws(s, 8ull << n));
+    QSV_HIP(s, qsv::dev::dm_diagonal(s->opt.dtype, s->d_state, n, (double *)s->d_ws, s->stream));
+    QSV_HIP(s, hipMemcpyAsync(out, s->d_ws, 8ull << n, hipMemcpyDeviceToHost, s->stream));
+    return sync(s);
+}
+
+qsv_status qsv_dm_expectation(qsv_sim *s, int32_t nterms, const uint64_t *xmask,
+                              const uint64_t *zmask, const double *coeff, double *out) {
+    QSV_CHECK(s);
+    if (!out || nterms < 0 || (nterms > 0 && (!xmask || !zmask || !coeff)))
+        return fail(s, QSV_EINVAL, "NULL argument");
+    if ((s->n & 1) || s->n == 0)
+        return fail(s, QSV_EINVAL, "a density matrix needs an even, nonzero number of qubits");
+    const int n = s->n / 2;
+    const uint64_t full = (1ull << n) - 1;
+    for (int t = 0; t < nterms; ++t)
+        if (((xmask[t] | zmask[t]) & ~full) || !std::isfinite(coeff[t]))
+            return fail(s, QSV_EINVAL, "Pauli term outside the system qubits");
+    *out = 0.0;
+    if (nterms == 0) return QSV_OK;
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    const size_t off_z = 8 * (size_t)nterms, off_p = 16 * (size_t)nterms;
+    QSV_TRY(ensure_ws(s, off_p + 16 * (size_t)nterms));
+    unsigned char *w = (unsigned char *)s->d_ws;
+    std::vector<unsigned char> meta(off_p);
+    std::memcpy(meta.data(), xmask, 8 * (size_t)nterms);
+    std::memcpy(meta.data() + off_z, zmask, 8 * (size_t)nterms);
+    QSV_HIP(s, hipMemcpyAsync(w, meta.data(), off_p, hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(s, qsv::dev::dm_pauli_sums(s->opt.dtype, s->d_state, n, nterms, (const uint64_t *)w,
+                                       (const uint64_t *)(w + off_z), (double *)(w + off_p),
+                                       s->stream));
+    std::vector<double> part(2 * (size_t)nterms);
+    QSV_HIP(s, hipMemcpyAsync(part.data(), w + off_p, 16 * (size_t)nterms, hipMemcpyDeviceToHost,
+                              s->stream));
+    QSV_TRY(sync(s));
+    // Tr(rho P) = i^ny * sum_r (-1)^popcount(r & z) rho[r][r ^ x]
+    double acc = 0.0;
+    for (int t = 0; t < nterms; ++t) {
+        const int ny = popc(xmask[t] & zmask[t]) & 3;
+        const double re = part[2 * t], im = part[2 * t + 1];
+        const double tr = ny == 0 ? re : ny == 1 ? -im : ny == 2 ? -re : im;
+        acc += coeff[t] * tr;
+    }
+    *out = acc;
+    return QSV_OK;
 }
 
 qsv_status qsv_apply_math(qsv_sim *s, int32_t w, const int32_t *qubits, const uint32_t *table,

@@ -89,6 +89,10 @@ _SIGS = {
     "qsv_qubits": (ctypes.c_int, [_P, _P, _P]),
     "qsv_apply": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
     "qsv_apply_math": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P]),
+    "qsv_dm_apply": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
+    "qsv_dm_apply_kraus": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
+    "qsv_dm_probabilities": (ctypes.c_int, [_P, _P]),
+    "qsv_dm_expectation": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "qsv_flush": (ctypes.c_int, [_P]),
     "qsv_synchronize": (ctypes.c_int, [_P]),
     "qsv_get_probability": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
@@ -459,6 +463,63 @@ def adjoint_gradient(sim: Simulator, circuit, ham, theta=None):
     _check(lib.qsv_adjoint_gradient(sim._h, ctypes.byref(fc.struct), ctypes.byref(fp.struct),
                                     ctypes.byref(val), _ptr(grad)), sim._h)
     return val.value, grad[: fc.n_params]
+
+
+class DensityMatrix:
+    """An n-qubit density matrix on a handle of 2n qubits (vec(rho), row bits
+    low, column bits high; see qsv_dm_apply).  Gates and Kraus channels queue
+    and run through the fused tile passes like ordinary gates."""
+
+    def __init__(self, n: int, dtype="c128", mode="tiled", k_max: int = 2, **kw):
+        self.n = n
+        self.sim = Simulator(n_max=2 * n, dtype=dtype, mode=mode, k_max=k_max, **kw)
+        self.sim.allocate(2 * n)
+
+    def close(self):
+        self.sim.close()
+
+    def apply(self, matrix, targets: Sequence[int], controls: Sequence[int] = ()):
+        u = np.ascontiguousarray(matrix, dtype=np.complex128)
+        t = np.ascontiguousarray(list(targets) or [0], dtype=np.int32)
+        c = np.ascontiguousarray(list(controls) or [0], dtype=np.int32)
+        _check(lib.qsv_dm_apply(self.sim._h, _ptr(u), len(targets), _ptr(t), len(controls),
+                                _ptr(c)), self.sim._h)
+
+    def channel(self, kraus, targets: Sequence[int]):
+        ks = np.ascontiguousarray(np.stack([np.asarray(k, dtype=np.complex128) for k in kraus]))
+        t = np.ascontiguousarray(list(targets), dtype=np.int32)
+        _check(lib.qsv_dm_apply_kraus(self.sim._h, len(ks), _ptr(ks), len(targets), _ptr(t)),
+               self.sim._h)
+
+    def run(self, events):
+        """Queue ("gate", U, targets, controls) / ("kraus", [K_j], targets) events."""
+        for ev in events:
+            if ev[0] == "gate":
+                self.apply(ev[1], ev[2], ev[3])
+            else:
+                self.channel(ev[1], ev[2])
+
+    def flush(self):
+        self.sim.flush()
+
+    def probabilities(self) -> np.ndarray:
+        out = np.zeros(1 << self.n, dtype=np.float64)
+        _check(lib.qsv_dm_probabilities(self.sim._h, _ptr(out)), self.sim._h)
+        return out
+
+    def expectation(self, ham) -> float:
+        x = np.ascontiguousarray(ham.xmask, dtype=np.uint64)
+        z = np.ascontiguousarray(ham.zmask, dtype=np.uint64)
+        c = np.ascontiguousarray(ham.coeff, dtype=np.float64)
+        out = ctypes.c_double()
+        _check(lib.qsv_dm_expectation(self.sim._h, len(c), _ptr(x), _ptr(z), _ptr(c),
+                                      ctypes.byref(out)), self.sim._h)
+        return out.value
+
+    def matrix(self) -> np.ndarray:
+        """rho as a 2^n x 2^n array (host copy)."""
+        v = self.sim.get_state()
+        return v.reshape(1 << self.n, 1 << self.n).T.copy()
 
 
 def math_table(func, widths: Sequence[int]) -> np.ndarray:
