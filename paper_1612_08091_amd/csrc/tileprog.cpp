@@ -358,6 +358,39 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         }
         prog.rops.push_back(r);
     }
+    // Stores leave from the final layout.  With some of the three lowest tile
+    // bits in registers and the first two thread bits far up the index, each
+    // store instruction writes 16-byte pieces of many separate 128-byte
+    // lines, and the memory system writes them out more than once (measured:
+    // 2.5 x the state for one pass of the 30-qubit brick circuit).  A final
+    // remap to a layout without those bits in registers costs less.
+    if (S & 0x7u) {
+        int gpos[32], c = 0;
+        for (int p = 0; p < 64; ++p)
+            if ((ps.tile >> p) & 1) gpos[c++] = p;
+        int thr[2] = {m, m}, t = 0;
+        for (int b = 0; b < m && t < 2; ++b)
+            if (!((S >> b) & 1)) thr[t++] = b;
+        if (t == 2 && (gpos[thr[0]] > 5 || gpos[thr[1]] > 6)) {
+            uint32_t Sn = S & ~0x7u;
+            for (int b = m - 1; b >= 3 && __builtin_popcount(Sn) < rb; --b) Sn |= 1u << b;
+            int split = -1;
+            for (int j = 0; j < rb && split < 0; ++j)
+                if ((Sn >> cur_reg[j]) & 1) split = j;
+            if (split >= 0 && __builtin_popcount(Sn) == rb) {
+                dev::RegOp r{};
+                r.kind = dev::ROP_REMAP;
+                r.a = split;
+                set_layout(Sn, m, rb, r.reg_lbit, r.thr_lbit);
+                for (int j = 0; j < rb; ++j)
+                    if (r.reg_lbit[j] == cur_reg[split]) std::swap(r.reg_lbit[j], r.reg_lbit[split]);
+                std::memcpy(cur_reg, r.reg_lbit, 8);
+                prog.rops.push_back(r);
+                prog.remaps += 1;
+                S = Sn;
+            }
+        }
+    }
     fill_layouts(prog, rb, elem_bytes);
     // the kernel runs ops in pairs: pad with an identity 1-qubit op
     if (prog.rops.size() & 1) {
