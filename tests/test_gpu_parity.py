@@ -387,6 +387,27 @@ def test_qft_32q_c64_sampled_closed_form():
     s.close()
 
 
+def test_qft_33q_c128_sampled_closed_form():
+    """The largest size of the workloads at full precision: 2^33 complex128
+    amplitudes (128 GiB).  QFT of a basis state against its closed form on
+    sampled amplitudes, then the norm."""
+    n = 33
+    x = int(np.random.default_rng(33).integers(0, 1 << n))
+    log("case qft33 c128 x=%d" % x)
+    s = make(n, mode="tiled", k_max=2, dtype="c128")
+    s.run(W.basis_prep(n, x))
+    s.run(W.qft(n))
+    rng = np.random.default_rng(24)
+    idx = rng.integers(0, 1 << n, size=4096, dtype=np.uint64)
+    idx[:4] = [0, 1, (1 << n) - 1, 1 << (n - 1)]
+    got = s.get_amplitudes(idx)
+    ph = np.array([float((x * int(v)) % (1 << n)) for v in idx.astype(object)]) / (1 << n)
+    want = np.exp(2j * math.pi * ph) / (2 ** (n / 2))
+    check_c128(got, want)
+    assert abs(s.norm2() - 1.0) <= 1e-12
+    s.close()
+
+
 def test_config2_32q_c64_then_inverse_and_measure():
     """The 32-qubit brick circuit and its inverse return |0...0> (within FP32
     rounding of 3800 gates); then a GHZ state is measured and collapsed."""
