@@ -147,6 +147,13 @@ void fill_layouts(TileProgram &prog, int rb, int elem_bytes) {
     std::memcpy(cur_reg, prog.reg_lbit, 8);
     std::memcpy(cur_thr, prog.thr_lbit, 16);
     for (dev::RegOp &r : prog.rops) {
+        if (r.kind == dev::ROP_SWAP) {
+            for (int t = 0; t < tb; ++t) r.g_thr[t] = 1ull << tpos[r.thr_lbit[t]];
+            for (int j = 0; j < rb; ++j) r.g_reg[j] = 1ull << tpos[r.reg_lbit[j]];
+            std::memcpy(cur_reg, r.reg_lbit, 8);
+            std::memcpy(cur_thr, r.thr_lbit, 16);
+            continue;
+        }
         if (r.kind != dev::ROP_REMAP) continue;
         const int kept = cur_reg[r.a];
         for (int i = 0; i < nr; ++i) {
@@ -236,14 +243,47 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
     }
     for (int b = m - 1; b >= 0 && __builtin_popcount(S) < rb; --b) S |= 1u << b;
     set_layout(S, m, rb, prog.reg_lbit, prog.thr_lbit);
-    uint8_t cur_reg[8];
+    uint8_t cur_reg[8], cur_thr[16];
     std::memcpy(cur_reg, prog.reg_lbit, 8);
+    std::memcpy(cur_thr, prog.thr_lbit, 16);
 
     for (int i = 0; i < n_items; ++i) {
         const Item &it = items[i];
         const Op &op = *it.op;
         if ((it.need & ~S) != 0) {
             // Belady: keep the bits needed soonest
+            int next_use[32];
+            for (int b = 0; b < m; ++b) next_use[b] = 1 << 30;
+            for (int j = n_items - 1; j >= i; --j)
+                for (int b = 0; b < m; ++b)
+                    if ((items[j].need >> b) & 1) next_use[b] = j;
+            // One missing bit that sits on lane bit 4 or 5: trade it with the
+            // register bit used last, by cross-lane swaps inside the wave (no
+            // LDS round trip)
+            const uint32_t miss = it.need & ~S;
+            int lane_t = -1;
+            if (__builtin_popcount(miss) == 1)
+                for (int t = 4; t <= 5 && t < tb; ++t)
+                    if (cur_thr[t] == __builtin_ctz(miss)) lane_t = t;
+            if (lane_t >= 0) {
+                int v = -1;
+                for (int j = 0; j < rb; ++j)
+                    if (!((it.need >> cur_reg[j]) & 1) &&
+                        (v < 0 || next_use[cur_reg[j]] > next_use[cur_reg[v]]))
+                        v = j;
+                dev::RegOp r{};
+                r.kind = dev::ROP_SWAP;
+                r.a = v;
+                r.b = lane_t == 4 ? 16 : 32;
+                S = (S & ~(1u << cur_reg[v])) | miss;
+                std::swap(cur_reg[v], cur_thr[lane_t]);
+                std::memcpy(r.reg_lbit, cur_reg, 8);
+                std::memcpy(r.thr_lbit, cur_thr, 16);
+                prog.rops.push_back(r);
+                prog.swaps += 1;
+            }
+        }
+        if ((it.need & ~S) != 0) {
             int next_use[32];
             for (int b = 0; b < m; ++b) next_use[b] = 1 << 30;
             for (int j = n_items - 1; j >= i; --j)
@@ -286,6 +326,7 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
             for (int j = 0; j < rb; ++j)
                 if (r.reg_lbit[j] == cur_reg[split]) std::swap(r.reg_lbit[j], r.reg_lbit[split]);
             std::memcpy(cur_reg, r.reg_lbit, 8);
+            std::memcpy(cur_thr, r.thr_lbit, 16);
             prog.rops.push_back(r);
             prog.remaps += 1;
             S = Sn;
@@ -368,10 +409,7 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         int gpos[32], c = 0;
         for (int p = 0; p < 64; ++p)
             if ((ps.tile >> p) & 1) gpos[c++] = p;
-        int thr[2] = {m, m}, t = 0;
-        for (int b = 0; b < m && t < 2; ++b)
-            if (!((S >> b) & 1)) thr[t++] = b;
-        if (t == 2 && (gpos[thr[0]] > 5 || gpos[thr[1]] > 6)) {
+        if (tb >= 2 && (gpos[cur_thr[0]] > 5 || gpos[cur_thr[1]] > 6)) {
             uint32_t Sn = S & ~0x7u;
             for (int b = m - 1; b >= 3 && __builtin_popcount(Sn) < rb; --b) Sn |= 1u << b;
             int split = -1;
@@ -385,6 +423,7 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
                 for (int j = 0; j < rb; ++j)
                     if (r.reg_lbit[j] == cur_reg[split]) std::swap(r.reg_lbit[j], r.reg_lbit[split]);
                 std::memcpy(cur_reg, r.reg_lbit, 8);
+                std::memcpy(cur_thr, r.thr_lbit, 16);
                 prog.rops.push_back(r);
                 prog.remaps += 1;
                 S = Sn;

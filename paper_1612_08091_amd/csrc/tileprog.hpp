@@ -19,7 +19,8 @@ struct TileProgram {
     uint8_t thr_lbit[16] = {};
     uint64_t g_reg[8] = {};             // initial layout as global index bits
     uint64_t g_thr[16] = {};
-    int remaps = 0;
+    int remaps = 0;                     // layout changes through LDS
+    int swaps = 0;                      // layout changes by cross-lane swaps
     int mfma_k = 0;                     // widest matrix-core op (LDS kernel)
     double flops_per_amp = 0.0;
 };
