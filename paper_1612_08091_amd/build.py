@@ -25,8 +25,13 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 # -simplifycfg-sink-common=false: without it LLVM merges the per-register-bit
 # cases of the tile kernel into one dynamically indexed access, which moves
 # the register-resident amplitudes to scratch memory.
+# -amdgpu-atomic-optimizer-strategy=None: every atomic here is one lane's
+# claim of a work item; the optimizer turns it into a wave-wide scan whose
+# result is needed at once, which puts a full vmcnt(0) wait (on the tile loads
+# issued just before) right after the claim.
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics", "-mllvm", "--simplifycfg-sink-common=false"]
+          "-munsafe-fp-atomics", "-mllvm", "--simplifycfg-sink-common=false",
+          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 
 
 def sources():
