@@ -33,35 +33,65 @@ __device__ __forceinline__ double block_sum_b(double v, double *sh) {
 }
 
 // sum_t c_t Re(i^{ny_t} sum_j conj(psi_{j^x}) psi_j (-1)^{popcount(j & z)}),
-// this thread's share, state `st` of 2^n amplitudes (LDS or global).
+// this thread's share, state `st` of 2^n amplitudes (LDS or global).  The
+// sweeps issue the loads of U indices (U pairs) per thread before using any,
+// so enough reads are in flight for a state in global memory; a tail loop
+// takes the indices left over.
 template <typename R, bool SWZ>
 __device__ __forceinline__ double pauli_partial(const typename VT<R>::T *st, int n,
                                                 const BatchTerm *__restrict__ terms, int nt) {
+    using T = typename VT<R>::T;
+    constexpr int U = sizeof(R) == 4 ? 8 : 4;
     double acc = 0.0;
     const uint64_t dim = 1ull << n;
+    const uint64_t bd = blockDim.x;
+    auto at = [&](uint64_t j) -> T { return st[SWZ ? swz<R>((uint32_t)j) : j]; };
     for (int t = 0; t < nt; ++t) {
         const BatchTerm tm = terms[t];
         double sr = 0.0, si = 0.0;
         if (tm.x == 0) {
-            for (uint64_t j = threadIdx.x; j < dim; j += blockDim.x) {
-                const auto a = st[SWZ ? swz<R>((uint32_t)j) : j];
+            auto add = [&](uint64_t j, const T &a) {
                 const double p = (double)a.x * a.x + (double)a.y * a.y;
                 sr += (__popcll(j & tm.z) & 1) ? -p : p;
+            };
+            uint64_t j = threadIdx.x;
+            for (; j + (U - 1) * bd < dim; j += U * bd) {
+                T a[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) a[u] = at(j + u * bd);
+#pragma unroll
+                for (int u = 0; u < U; ++u) add(j + u * bd, a[u]);
             }
+            for (; j < dim; j += bd) add(j, at(j));
         } else {
             const int h = 63 - __builtin_clzll(tm.x);
             const uint64_t lowm = (1ull << h) - 1;
-            for (uint64_t g = threadIdx.x; g < (dim >> 1); g += blockDim.x) {
-                const uint64_t j = ((g & ~lowm) << 1) | (g & lowm);
+            auto idx = [&](uint64_t g) { return ((g & ~lowm) << 1) | (g & lowm); };
+            auto add = [&](uint64_t j, const T &a, const T &b) {
                 const uint64_t j2 = j ^ tm.x;
-                const auto a = st[SWZ ? swz<R>((uint32_t)j) : j];
-                const auto b = st[SWZ ? swz<R>((uint32_t)j2) : j2];
                 const double u = (double)b.x * a.x + (double)b.y * a.y;
                 const double v = (double)b.x * a.y - (double)b.y * a.x;
                 const double s1 = (__popcll(j & tm.z) & 1) ? -1.0 : 1.0;
                 const double s2 = (__popcll(j2 & tm.z) & 1) ? -1.0 : 1.0;
                 sr += (s1 + s2) * u;
                 si += (s1 - s2) * v;
+            };
+            const uint64_t half = dim >> 1;
+            uint64_t g = threadIdx.x;
+            for (; g + (U - 1) * bd < half; g += U * bd) {
+                T a[U], b[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint64_t j = idx(g + u * bd);
+                    a[u] = at(j);
+                    b[u] = at(j ^ tm.x);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) add(idx(g + u * bd), a[u], b[u]);
+            }
+            for (; g < half; g += bd) {
+                const uint64_t j = idx(g);
+                add(j, at(j), at(j ^ tm.x));
             }
         }
         // Re(i^{ny} (sr + i si))
@@ -129,7 +159,9 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                 const uint32_t *tpos = bp.tpos;
                 const uint32_t tsize = 1u << m;
                 const uint64_t ntiles = 1ull << (n - m);
-                // thread part of local index j0 + tid (used when tsize >= 4 kNT)
+                // loads in flight per thread while a tile comes in or goes out
+                constexpr int LD = sizeof(R) == 4 ? 8 : 4;
+                // thread part of local index j0 + tid (used when tsize >= LD kNT)
                 const uint64_t dep_tid = deposit_bits(tid, tpos, m < 8 ? m : 8);
                 const uint32_t swz_tid = swz<R>(tid);
                 for (uint64_t t = 0; t < ntiles; ++t) {
@@ -138,9 +170,9 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                         const uint64_t lowm = (1ull << tpos[i]) - 1;
                         base = ((base & ~lowm) << 1) | (base & lowm);
                     }
-                    // loads go out 4 at a time, before their LDS writes (tiles of
-                    // at least 4 * kNT amplitudes; smaller ones one at a time)
-                    if (tsize < 4 * kNT) {
+                    // loads go out LD at a time, before their LDS writes (tiles of
+                    // at least LD * kNT amplitudes; smaller ones one at a time)
+                    if (tsize < LD * kNT) {
                         for (uint32_t l = tid; l < tsize; l += kNT) {
                             const uint64_t gi = base | deposit_bits(l, tpos, m);
                             T v;
@@ -152,10 +184,10 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                             }
                             tile[swz<R>(l)] = v;
                         }
-                    } else for (uint32_t j0 = 0; j0 < tsize; j0 += 4 * kNT) {
-                        T v[4];
+                    } else for (uint32_t j0 = 0; j0 < tsize; j0 += LD * kNT) {
+                        T v[LD];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
+                        for (int u = 0; u < LD; ++u) {
                             const uint64_t gi = base | dep_tid | deposit_bits(j0 + u * kNT, tpos, m);
                             if (p == 0) {   // the first pass starts from |0...0>
                                 v[u].x = (gi == 0) ? R(1) : R(0);
@@ -165,22 +197,22 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                             }
                         }
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) tile[swz_tid ^ swz<R>(j0 + u * kNT)] = v[u];
+                        for (int u = 0; u < LD; ++u) tile[swz_tid ^ swz<R>(j0 + u * kNT)] = v[u];
                     }
                     __syncthreads();
                     for (int o = 0; o < bp.op_count; ++o) {
                         lds_op<R, KM>(tile, m, base, tpos, ops[bp.op_begin + o], pool);
                         __syncthreads();
                     }
-                    if (tsize < 4 * kNT) {
+                    if (tsize < LD * kNT) {
                         for (uint32_t l = tid; l < tsize; l += kNT)
                             slot[base | deposit_bits(l, tpos, m)] = tile[swz<R>(l)];
-                    } else for (uint32_t j0 = 0; j0 < tsize; j0 += 4 * kNT) {
-                        T v[4];
+                    } else for (uint32_t j0 = 0; j0 < tsize; j0 += LD * kNT) {
+                        T v[LD];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) v[u] = tile[swz_tid ^ swz<R>(j0 + u * kNT)];
+                        for (int u = 0; u < LD; ++u) v[u] = tile[swz_tid ^ swz<R>(j0 + u * kNT)];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u)
+                        for (int u = 0; u < LD; ++u)
                             slot[base | dep_tid | deposit_bits(j0 + u * kNT, tpos, m)] = v[u];
                     }
                     __syncthreads();
