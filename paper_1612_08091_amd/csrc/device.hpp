@@ -66,6 +66,8 @@ struct TileArgs {
     uint8_t thr_lbit[16]; //                  tile bit of thread-id bit i
     int32_t rb;           // register bits per thread (threads = 2^(m - rb))
     int32_t mfma_k;       // LDS kernel: widest matrix-core op of the pass (0 = none)
+    int32_t no_diag;      // register kernel: 1 if the program has no ROP_DIAG op (a
+                          // leaner kernel instance without that case runs it)
     uint64_t g_reg[8];    // register kernel, initial layout: global index bit of register
                           // bit j, and of thread-id bit i
     uint64_t g_thr[16];

@@ -163,22 +163,36 @@ __device__ __forceinline__ void reg_g2(T *amp, const T *__restrict__ U, uint64_t
 // op.pad0 marks them) and the bits from the register index (op.wr[i],
 // precomputed on the host for the current layout).  Controls that are not
 // register bits are in op.ctrl; those that are, as register-index bits, in
-// op.b.
+// op.b.  The wave first copies the op's 2^k factors into its own LDS table
+// `tab` (every lane takes part, before any lane leaves on its controls), so
+// the 16 gathers per thread are LDS reads instead of vector-memory reads
+// that compete with the tile loads.  LDS operations of one wave are
+// performed in order, so the reads see the copy and the next op's copy
+// comes after these reads.
 template <typename T, int NR, int RB>
 __device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const T *__restrict__ pool,
-                                         uint64_t gb, const uint64_t *gbit) {
-    (void)gbit;
-    if ((gb & op.ctrl) != op.ctrl) return;
+                                         uint64_t gb, T *tab) {
     const int k = op.a;
+    const uint32_t lane = threadIdx.x & 63u;
+    const T *val = pool + op.mat;
+    if (lane < (1u << k)) tab[lane] = val[lane];
+    __builtin_amdgcn_wave_barrier();
+    if ((gb & op.ctrl) != op.ctrl) return;
     const uint32_t thr_targets = op.pad0;
     uint32_t rt = 0;
     for (int q = 0; q < k; ++q)
         if ((thr_targets >> q) & 1u) rt |= (uint32_t)((gb >> op.gt[q]) & 1u) << q;
-    const T *val = pool + op.mat;
     const int creg = op.b;
+    // rows outside the register controls take the factor 1
 #pragma unroll
-    for (int i = 0; i < NR; ++i)
-        if ((i & creg) == creg) amp[i] = cmul(val[rt ^ op.wr[i]], amp[i]);
+    for (int i = 0; i < NR; ++i) {
+        const T v = tab[rt ^ op.wr[i]];
+        const bool on = (i & creg) == creg;
+        T f;
+        f.x = on ? v.x : decltype(v.x)(1);
+        f.y = on ? v.y : decltype(v.y)(0);
+        amp[i] = cmul(f, amp[i]);
+    }
 }
 
 // Layout change through an LDS buffer of half a tile.  Slot J holds the same
@@ -314,9 +328,9 @@ __device__ __forceinline__ void dispatch_swap(T *amp, int j) {
     }
 }
 
-template <typename T, int NR, int RB, int TB>
+template <typename T, int NR, int RB, int TB, bool DG>
 __device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restrict__ pool,
-                                       unsigned char *lds, uint64_t base, uint64_t &gthr,
+                                       unsigned char *lds, T *dtab, uint64_t base, uint64_t &gthr,
                                        uint64_t *gbit, uint32_t tid) {
     const int kind = op.kind;
     const uint64_t gb = base | gthr;
@@ -329,7 +343,8 @@ __device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restr
         if (op.ctrl) dispatch_g2<T, NR, RB, true>(amp, op.a, op.b, U, gb, gbit, op.ctrl);
         else dispatch_g2<T, NR, RB, false>(amp, op.a, op.b, U, gb, gbit, 0);
     } else if (kind == ROP_DIAG) {
-        reg_diag<T, NR, RB>(amp, op, pool, gb, gbit);
+        if constexpr (DG) reg_diag<T, NR, RB>(amp, op, pool, gb, dtab);
+        else __builtin_unreachable();
     } else if (kind == ROP_SWAP) {
         if (op.b == 16) dispatch_swap<T, NR, RB, true>(amp, op.a);
         else dispatch_swap<T, NR, RB, false>(amp, op.a);
@@ -383,7 +398,10 @@ __device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restr
 // that runs slower simply processes fewer tiles and no dispatch gaps open up
 // between tiles.  Every workgroup leaves once the counter has passed the tile
 // count.
-template <typename R, int RB, int TB>
+// DG: the instance with the diagonal-op case; programs without one run on
+// the instance without it, whose register allocation the case does not
+// burden.
+template <typename R, int RB, int TB, bool DG>
 __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restrict__ psi,
                                                   TileArgs ta, const RegOp *__restrict__ ops,
                                                   const typename VT<R>::T *__restrict__ pool,
@@ -394,8 +412,11 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
     // half a tile for the two-phase remaps (static, so addresses need no base)
     __shared__ T half_tile[1 << (m - 1)];
     __shared__ unsigned int s_tile;
+    // one table of diagonal factors (at most 32) per wave
+    __shared__ T diag_tab[DG ? (1 << TB) / 2 : 1];
     unsigned char *lds = reinterpret_cast<unsigned char *>(half_tile);
     const uint32_t tid = threadIdx.x;
+    T *dtab = diag_tab + (DG ? (tid >> 6) * 32 : 0);
     // layout at load time (the same for every tile): global index bit of each
     // register bit (uniform) and the global bits of this thread
     uint64_t gbit0[RB];
@@ -435,8 +456,8 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
         // are read through references into the uniform op array so they stay
         // scalar.
         for (int oi = 0; oi < ta.n_ops; oi += 2) {
-            reg_op<T, NR, RB, TB>(amp, ops[oi], pool, lds, base, gthr, gbit, tid);
-            reg_op<T, NR, RB, TB>(amp, ops[oi + 1], pool, lds, base, gthr, gbit, tid);
+            reg_op<T, NR, RB, TB, DG>(amp, ops[oi], pool, lds, dtab, base, gthr, gbit, tid);
+            reg_op<T, NR, RB, TB, DG>(amp, ops[oi + 1], pool, lds, dtab, base, gthr, gbit, tid);
         }
 #pragma unroll
         for (int i = 0; i < NR; ++i) psi[base | gthr | greg<T, NR, RB>(i, gbit)] = amp[i];
@@ -509,7 +530,7 @@ static hipError_t launch_lds_k(void *psi, const TileArgs &ta, const TileOp *ops,
     return hipErrorInvalidValue;
 }
 
-template <typename R, int RB, int TB>
+template <typename R, int RB, int TB, bool DG>
 static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
                                const void *pool, unsigned int *counter, hipStream_t s) {
     using T = typename VT<R>::T;
@@ -523,12 +544,12 @@ static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void *>(k_tile_reg<R, RB, TB>), 1 << TB, 0);
+                &per_cu, reinterpret_cast<const void *>(k_tile_reg<R, RB, TB, DG>), 1 << TB, 0);
         if (e != hipSuccess) return e;
         resident = (unsigned)std::max(1, cus * std::max(1, per_cu));
     }
     const unsigned grid = (unsigned)std::min<uint64_t>(ta.n_tiles, resident);
-    hipLaunchKernelGGL((k_tile_reg<R, RB, TB>), dim3(grid), dim3(1 << TB), 0, s, (T *)psi, ta,
+    hipLaunchKernelGGL((k_tile_reg<R, RB, TB, DG>), dim3(grid), dim3(1 << TB), 0, s, (T *)psi, ta,
                        rops, (const T *)pool, counter);
     return hipGetLastError();
 }
@@ -543,14 +564,17 @@ hipError_t launch_tile_pass(int dtype, void *psi, const TileArgs &ta, const Tile
 hipError_t launch_tile_reg(int dtype, void *psi, const TileArgs &ta, const RegOp *rops,
                            const void *pool, unsigned int *counter, hipStream_t s) {
     const int rb = ta.rb, tb = ta.m - ta.rb;
+#define QSV_REG_T(R, RB, TB)                                                         \
+    return ta.no_diag ? launch_reg_t<R, RB, TB, false>(psi, ta, rops, pool, counter, s)   \
+                      : launch_reg_t<R, RB, TB, true>(psi, ta, rops, pool, counter, s);
 #define QSV_REG(R)                                                                   \
     if (tb == 8) {                                                                   \
-        if (rb == 3) return launch_reg_t<R, 3, 8>(psi, ta, rops, pool, counter, s);           \
-        if (rb == 4) return launch_reg_t<R, 4, 8>(psi, ta, rops, pool, counter, s);           \
-        if (rb == 5) return launch_reg_t<R, 5, 8>(psi, ta, rops, pool, counter, s);           \
+        if (rb == 3) { QSV_REG_T(R, 3, 8) }                                          \
+        if (rb == 4) { QSV_REG_T(R, 4, 8) }                                          \
+        if (rb == 5) { QSV_REG_T(R, 5, 8) }                                          \
     } else if (tb == 9) {                                                            \
-        if (rb == 3) return launch_reg_t<R, 3, 9>(psi, ta, rops, pool, counter, s);           \
-        if (rb == 4) return launch_reg_t<R, 4, 9>(psi, ta, rops, pool, counter, s);           \
+        if (rb == 3) { QSV_REG_T(R, 3, 9) }                                          \
+        if (rb == 4) { QSV_REG_T(R, 4, 9) }                                          \
     }
     if (dtype == 0) {
         QSV_REG(double)
@@ -558,6 +582,7 @@ hipError_t launch_tile_reg(int dtype, void *psi, const TileArgs &ta, const RegOp
         QSV_REG(float)
     }
 #undef QSV_REG
+#undef QSV_REG_T
     return hipErrorInvalidValue;
 }
 

@@ -422,6 +422,9 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         const int tok = tbegin(s);
         if (pg.reg) {
             ta.n_ops = (int)nr;
+            ta.no_diag = 1;
+            for (const qsv::dev::RegOp &r : pg.rops)
+                if (r.kind == qsv::dev::ROP_DIAG) ta.no_diag = 0;
             QSV_HIP(s, qsv::dev::launch_tile_reg(s->opt.dtype, s->d_state, ta, drops + ro, dmat,
                                                  dcount + pi, s->stream));
         } else {
