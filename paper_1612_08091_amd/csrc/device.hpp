@@ -81,6 +81,10 @@ struct TileArgs {
 enum RegOpKind : int32_t {
     ROP_G1 = 0, ROP_G2 = 1, ROP_DIAG = 2, ROP_REMAP = 3, ROP_LDS = 4, ROP_SWAP = 5
 };
+// Widest diagonal op of the register kernel (targets; its table of 2^k
+// factors is staged per wave in LDS).
+constexpr int kRegDiagMax = 8;
+
 struct RegOp {
     int32_t kind;
     int32_t a;            // G1: register bit; G2: lower register bit (matrix bit 0);

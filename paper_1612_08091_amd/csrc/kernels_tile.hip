@@ -175,7 +175,7 @@ __device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const T *__res
     const int k = op.a;
     const uint32_t lane = threadIdx.x & 63u;
     const T *val = pool + op.mat;
-    if (lane < (1u << k)) tab[lane] = val[lane];
+    for (uint32_t e = lane; e < (1u << k); e += 64) tab[e] = val[e];
     __builtin_amdgcn_wave_barrier();
     if ((gb & op.ctrl) != op.ctrl) return;
     const uint32_t thr_targets = op.pad0;
@@ -412,11 +412,12 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
     // half a tile for the two-phase remaps (static, so addresses need no base)
     __shared__ T half_tile[1 << (m - 1)];
     __shared__ unsigned int s_tile;
-    // one table of diagonal factors (at most 32) per wave
-    __shared__ T diag_tab[DG ? (1 << TB) / 2 : 1];
+    // one table of diagonal factors (at most 2^kRegDiagMax) per wave
+    constexpr int kTab = 1 << kRegDiagMax;
+    __shared__ T diag_tab[DG ? ((1 << TB) >> 6) * kTab : 1];
     unsigned char *lds = reinterpret_cast<unsigned char *>(half_tile);
     const uint32_t tid = threadIdx.x;
-    T *dtab = diag_tab + (DG ? (tid >> 6) * 32 : 0);
+    T *dtab = diag_tab + (DG ? (tid >> 6) * kTab : 0);
     // layout at load time (the same for every tile): global index bit of each
     // register bit (uniform) and the global bits of this thread
     uint64_t gbit0[RB];

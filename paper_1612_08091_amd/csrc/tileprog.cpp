@@ -216,12 +216,71 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         int kind;          // ROP_G1/G2/DIAG/LDS
         uint32_t need;     // local bits that must be register bits
         const Op *op;
+        int run;           // DIAG: index into `runs`
     };
+    // A run of consecutive diagonal ops becomes one diagonal op: the controls
+    // that all of them share stay controls, every other qubit of the run
+    // (targets and the remaining controls) indexes the table, while there are
+    // at most kRegDiagMax such qubits.  The kernel's cost of a diagonal op is
+    // one table gather and one complex product per amplitude, whatever its
+    // width.  A run of one op keeps its own targets and controls.
+    struct DiagRun {
+        int k = 0;
+        int t[dev::kRegDiagMax] = {};
+        uint64_t ctrl = 0;
+        std::vector<cd> val;   // val[r], bit j of r <-> qubit t[j]
+    };
+    std::vector<DiagRun> runs;
     std::vector<Item> items;
-    for (const Op &op : ps.ops) {
-        if (op.kind == Op::MONO && op.touch == 0) continue;
-        if (op.kind == Op::MONO && op.diag) {
-            items.push_back({dev::ROP_DIAG, 0u, &op});
+    const int n_ops = (int)ps.ops.size();
+    auto is_diag = [](const Op &o) { return o.kind == Op::MONO && o.diag && o.touch != 0; };
+    auto is_noop = [](const Op &o) { return o.kind == Op::MONO && o.touch == 0; };
+    for (int oi = 0; oi < n_ops; ++oi) {
+        const Op &op = ps.ops[oi];
+        if (is_noop(op)) continue;
+        if (is_diag(op)) {
+            uint64_t common = op.ctrl, qs = op.targets();
+            std::vector<const Op *> mem{&op};
+            int oj = oi + 1;
+            for (; oj < n_ops; ++oj) {
+                const Op &o2 = ps.ops[oj];
+                if (is_noop(o2)) continue;
+                if (!is_diag(o2)) break;
+                const uint64_t c2 = common & o2.ctrl;
+                const uint64_t q2 = qs | (common & ~c2) | (o2.qubits() & ~c2);
+                if (popc(q2) > dev::kRegDiagMax) break;
+                common = c2;
+                qs = q2;
+                mem.push_back(&o2);
+            }
+            DiagRun run;
+            if (mem.size() == 1) {
+                run.k = op.k;
+                for (int j = 0; j < op.k; ++j) run.t[j] = op.t[j];
+                run.ctrl = op.ctrl;
+                run.val.assign(op.U.begin(), op.U.begin() + (1 << op.k));
+            } else {
+                run.ctrl = common;
+                for (int p = 0; p < 64; ++p)
+                    if ((qs >> p) & 1) run.t[run.k++] = p;
+                run.val.assign(size_t(1) << run.k, cd(1, 0));
+                for (uint32_t r = 0; r < (1u << run.k); ++r) {
+                    uint64_t bits = common;   // the qubits' values in row r
+                    for (int j = 0; j < run.k; ++j)
+                        if ((r >> j) & 1) bits |= 1ull << run.t[j];
+                    for (const Op *o : mem) {
+                        if ((bits & o->ctrl) != o->ctrl) continue;
+                        uint32_t row = 0;
+                        for (int j = 0; j < o->k; ++j)
+                            if ((bits >> o->t[j]) & 1) row |= 1u << j;
+                        run.val[r] *= o->U[row];
+                    }
+                }
+                prog.diag_merged += (int)mem.size() - 1;
+            }
+            runs.push_back(std::move(run));
+            items.push_back({dev::ROP_DIAG, 0u, nullptr, (int)runs.size() - 1});
+            oi = oj - 1;
             continue;
         }
         bool inside = true;
@@ -230,8 +289,8 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
             if (li[op.t[j]] < 0) inside = false;
             else need |= 1u << li[op.t[j]];
         }
-        if (inside && op.k <= 2) items.push_back({op.k == 1 ? dev::ROP_G1 : dev::ROP_G2, need, &op});
-        else items.push_back({dev::ROP_LDS, 0u, &op});
+        if (inside && op.k <= 2) items.push_back({op.k == 1 ? dev::ROP_G1 : dev::ROP_G2, need, &op, -1});
+        else items.push_back({dev::ROP_LDS, 0u, &op, -1});
     }
     const int n_items = (int)items.size();
     // initial register set: the first needed bits, then the highest free bits
@@ -249,7 +308,6 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
 
     for (int i = 0; i < n_items; ++i) {
         const Item &it = items[i];
-        const Op &op = *it.op;
         if ((it.need & ~S) != 0) {
             // Belady: keep the bits needed soonest
             int next_use[32];
@@ -341,11 +399,12 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
                     if (li[pos] >= 0 && cur_reg[j] == li[pos]) return j;
                 return -1;
             };
-            r.a = op.k;
+            const DiagRun &run = runs[it.run];
+            r.a = run.k;
             r.pad0 = 0;
-            for (int j = 0; j < op.k; ++j) {
-                r.gt[j] = (uint32_t)op.t[j];
-                const int rj = reg_of(op.t[j]);
+            for (int j = 0; j < run.k; ++j) {
+                r.gt[j] = (uint32_t)run.t[j];
+                const int rj = reg_of(run.t[j]);
                 if (rj < 0) r.pad0 |= 1u << j;
                 for (int i = 0; i < (1 << rb); ++i)
                     if (rj >= 0 && ((i >> rj) & 1)) r.wr[i] |= 1u << j;
@@ -353,22 +412,28 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
             r.ctrl = 0;
             r.b = 0;
             for (int p = 0; p < 64; ++p)
-                if ((op.ctrl >> p) & 1) {
+                if ((run.ctrl >> p) & 1) {
                     const int rj = reg_of(p);
                     if (rj >= 0) r.b |= 1 << rj;
                     else r.ctrl |= 1ull << p;
                 }
             r.mat = (int64_t)(mats.size() / 2);
-            for (int e = 0; e < (1 << op.k); ++e) push(mats, op.U[e]);
-            prog.flops_per_amp += 6.0 * __builtin_popcount(op.touch) / (double)(1 << op.k) /
-                                  (double)(1ull << popc(op.ctrl));
+            int changed = 0;
+            for (int e = 0; e < (1 << run.k); ++e) {
+                push(mats, run.val[e]);
+                if (run.val[e] != cd(1, 0)) ++changed;
+            }
+            prog.flops_per_amp += 6.0 * changed / (double)(1 << run.k) /
+                                  (double)(1ull << popc(run.ctrl));
         } else if (it.kind == dev::ROP_LDS) {
+            const Op &op = *it.op;
             double fl = 0.0;
             dev::TileOp t = lds_form(op, li, mats, elem_bytes, &fl);
             prog.flops_per_amp += fl;
             r.a = (int32_t)prog.lops.size();
             prog.lops.push_back(t);
         } else {
+            const Op &op = *it.op;
             auto reg_index = [&](int local_bit) {
                 for (int j = 0; j < rb; ++j)
                     if (cur_reg[j] == local_bit) return j;
