@@ -122,6 +122,44 @@ def test_random_circuits_c64(mode, k_max):
     s.close()
 
 
+def diag_circuit(rng, n, count):
+    """A Hadamard layer, then mostly diagonal gates: phases with 0-3 random
+    controls and Rz, with an occasional dense 1-qubit gate.  Long runs of
+    diagonal ops with differing controls reach the register-tile lowering,
+    which merges them into diagonal ops of up to 8 table qubits."""
+    c = W.Circuit(n)
+    for q in range(n):
+        c.add(W.H, (q,))
+    for _ in range(count):
+        kind = rng.integers(0, 10)
+        if kind == 0:
+            c.add(W.haar_2x2(rng), (int(rng.integers(0, n)),))
+        elif kind <= 2:
+            c.add(W.rz(float(rng.uniform(0, 6))), (int(rng.integers(0, n)),))
+        else:
+            nc = int(rng.integers(0, 4))
+            qs = rng.permutation(n)[:nc + 1].tolist()
+            c.add(W.phase(float(rng.uniform(0, 6))), qs[:1], qs[1:])
+    return c
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [13, 16])
+def test_diagonal_runs_tiled(dtype, n):
+    rng = np.random.default_rng(4242 + n)
+    circ = diag_circuit(rng, n, 300)
+    log("case diagonal runs", dtype, n)
+    s = make(n, mode="tiled", k_max=2, dtype=dtype)
+    s.run(circ)
+    got = s.get_state()
+    want = oracle.run(circ)
+    if dtype == "c128":
+        check_c128(got, want)
+    else:
+        check_c64(got, want)
+    s.close()
+
+
 def test_config0_state_probs_samples():
     circ, u = W.config0()
     log("case config0")
