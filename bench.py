@@ -359,12 +359,34 @@ def form_noise(n: int = 15, layers: int = 10):
     d.close()
     t = min(times)
     gates = sum(1 for e in ev if e[0] == "gate")
+    # the same circuit as stochastic trajectories on the 15-qubit state: every
+    # channel is one reduction (its branch probabilities), a host draw and
+    # the chosen branch queued as a gate
+    s = Q.Simulator(n_max=n, dtype="c128", mode="tiled", k_max=2)
+    s.allocate(n)
+    urng = np.random.default_rng(W.SEED_BASE + 8)
+    ttimes = []
+    for _ in range(4):
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e in ev:
+            if e[0] == "gate":
+                s.apply(e[1], list(e[2]), list(e[3]))
+            else:
+                s.apply_kraus_sampled(e[1], list(e[2]), float(urng.uniform()))
+        s.flush()
+        s.synchronize()
+        ttimes.append(time.perf_counter() - t0)
+    s.close()
+    tt = min(ttimes[1:])
     return {"workload": "%d-qubit noisy brick, %d layers: %d gates, %d channels; vec(rho) on %d "
                         "qubits, complex128" % (n, layers, gates, len(ev) - gates, 2 * n),
             "s_per_circuit": t, "passes": npass,
             "events_per_s": len(ev) / t,
             "tile_kernel_ms_avg": kt["tile"][0] / max(kt["tile"][1], 1),
-            "trace_minus_one": float(p.sum() - 1.0)}
+            "trace_minus_one": float(p.sum() - 1.0),
+            "trajectory": {"s_per_trajectory": tt, "channels_per_s": (len(ev) - gates) / tt}}
 
 
 def form_batched():

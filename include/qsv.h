@@ -221,6 +221,23 @@ qsv_status qsv_get_expectation(qsv_sim *sim, int32_t nterms, const uint64_t *xma
 qsv_status qsv_measure(qsv_sim *sim, int32_t m, const int32_t *qubits, const double *u,
                        int8_t *bits_out);
 
+/* One step of a stochastic noise trajectory (Sec. 4.3.2 names stochastic
+ * noise models as future work): the channel with Kraus operators K_j
+ * (kraus: nk matrices of 2^k x 2^k, row-major, interleaved complex128) on
+ * targets[k], k <= 2, is replaced by one of its branches.  Branch j has
+ * probability p_j = ||K_j psi||^2 = Tr(K_j rho_T K_j^dagger), rho_T the
+ * reduced density matrix of the targets (one reduction over the state,
+ * accumulated in double); the branch taken is the smallest j whose running
+ * sum of p exceeds u * sum_j p_j (u in [0,1), the caller's uniform), and
+ * K_j / sqrt(p_j) is queued as a gate, so the state keeps unit norm.
+ * *chosen = j; probs[nk] (may be NULL) receives the p_j.  Averaged over u,
+ * |psi><psi| follows the channel sum_j K_j rho K_j^dagger.  EINVAL for k
+ * outside 1..2, unknown or repeated ids, u outside [0,1), non-finite
+ * entries, or a channel that leaves no probability.  Flushes; synchronises. */
+qsv_status qsv_apply_kraus_sampled(qsv_sim *sim, int32_t nk, const double *kraus, int32_t k,
+                                   const int32_t *targets, double u, int32_t *chosen,
+                                   double *probs);
+
 /* Draw `shots` samples without collapse.  Shot s returns the smallest index i
  * with C_i > u[s] * T, C the running sum of |psi|^2 in double and T its total,
  * or the largest i with |psi_i|^2 > 0 if none.  out[s] has bit p = value of the

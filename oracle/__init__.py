@@ -17,9 +17,12 @@ only marshals numpy arrays and strings calls together:
   forward circuit; the shift rule is exact for exp(-i theta P / 2) gates.
 * ``apply_math``    an emulated math gate (Sec. 4.3.3): a tabulated classical
                     bijection applied to a register of a superposition.
-* ``dm_*``          density matrices (the noise simulator Sec. 4.3.3 names as
+* ``dm_*``          density matrices (the noise simulator Sec. 4.3.2 names as
                     future work): gates as G rho G^dagger, channels as
                     sum_j K_j rho K_j^dagger, Tr(rho P) per Pauli string.
+* ``kraus_sample``  one step of a stochastic noise trajectory (the stochastic
+                    noise models named beside it): branch j of a channel with
+                    probability ||K_j psi||^2, the state renormalised.
 
 Parity status of every function is stated in the module docstring of the
 test that pins it (tests/test_oracle_pins.py).
@@ -292,6 +295,34 @@ def dm_run(events, n: int) -> np.ndarray:
         else:
             dm_kraus(rho, ev[1], ev[2])
     return rho
+
+
+def kraus_sample(psi: np.ndarray, kraus, targets: Sequence[int], u: float):
+    """Replace the channel {K_j} on ``targets`` by one branch, in place.
+    Branch j has probability p_j = ||K_j psi||^2; the branch taken is the
+    smallest j whose running sum of p exceeds u * sum_j p_j, and psi becomes
+    K_j psi / sqrt(p_j).  Returns (j, p)."""
+    branches = []
+    for K in kraus:
+        phi = psi.copy()
+        apply(phi, np.asarray(K, dtype=np.complex128), targets)
+        branches.append(phi)
+    p = np.array([norm2(b) for b in branches])
+    total = float(p.sum())
+    if not total > 0.0:
+        raise ValueError("the channel leaves no probability")
+    r = u * total
+    run = 0.0
+    pick = -1
+    for j, pj in enumerate(p):
+        run += pj
+        if run > r:
+            pick = j
+            break
+    if pick < 0:
+        pick = int(np.nonzero(p > 0)[0][-1])
+    psi[:] = branches[pick] / math.sqrt(p[pick])
+    return pick, p
 
 
 def allocate(psi: np.ndarray, count: int = 1) -> np.ndarray:

@@ -147,6 +147,13 @@ hipError_t prob_masked(int dtype, const void *psi, uint64_t ngroups, const Index
 hipError_t prob_split(int dtype, const void *psi, int nq, int q, double *ws, double *out_dev,
                       hipStream_t s);
 hipError_t probs(int dtype, const void *psi, uint64_t dim, double *out_dev, hipStream_t s);
+// Reduced density matrix of the k <= 2 qubits at bit positions pos[0..k-1]:
+// out_dev[2 * (a * 2^k + b) + {0, 1}] = re / im of sum over the other bits of
+// psi[i_a] conj(psi[i_b]), where bit j of a is the bit at pos[j] of i_a.
+// Accumulated in double; ws holds reduced_dm_workspace_bytes().
+hipError_t reduced_dm(int dtype, const void *psi, int nq, int k, const int *pos, double *ws,
+                      double *out_dev, hipStream_t s);
+size_t reduced_dm_workspace_bytes();
 
 // Pauli sum.  Terms are grouped by x mask on the host; `grp_*` describe the
 // groups.  out_dev[0..1] = sum_t coeff_t <P_t> (re, im).

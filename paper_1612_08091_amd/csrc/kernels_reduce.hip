@@ -131,6 +131,86 @@ hipError_t prob_split(int dtype, const void *psi, int nq, int q, double *ws, dou
     return hipGetLastError();
 }
 
+// ------------------------------------------------ reduced density matrix
+// rho_T[a][b] = sum over the other bits of psi[i_a] conj(psi[i_b]), where i_a
+// is the index whose target bits (positions ia.pos, ascending, and tp[j] the
+// position of target j) take the bits of a.  Each block writes its partial
+// 2^K x 2^K complex matrix (2 * 4^K doubles, row-major, re/im) to
+// partial[block * 2 * 4^K ...].
+template <typename R, int K>
+__global__ __launch_bounds__(kRedThreads) void k_reduced_dm(const typename V2r<R>::T *psi,
+                                                            uint64_t ngroups, IndexArgs ia,
+                                                            int tp0, int tp1, double *partial) {
+    constexpr int D = 1 << K;
+    __shared__ double sh[16];
+    double re[D][D], im[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) re[a][b] = im[a][b] = 0.0;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t base = expand_idx(g, ia);
+        double xr[D], xi[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            uint64_t i = base;
+            if (a & 1) i |= 1ull << tp0;
+            if (K > 1 && (a & 2)) i |= 1ull << tp1;
+            const auto v = psi[i];
+            xr[a] = v.x;
+            xi[a] = v.y;
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                re[a][b] += xr[a] * xr[b] + xi[a] * xi[b];
+                im[a][b] += xi[a] * xr[b] - xr[a] * xi[b];
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            const double sr = block_sum(re[a][b], sh);
+            const double si = block_sum(im[a][b], sh);
+            if (threadIdx.x == 0) {
+                partial[(size_t)blockIdx.x * 2 * D * D + 2 * (a * D + b)] = sr;
+                partial[(size_t)blockIdx.x * 2 * D * D + 2 * (a * D + b) + 1] = si;
+            }
+        }
+}
+
+size_t reduced_dm_workspace_bytes() { return sizeof(double) * 2 * 16 * kRedBlocks; }
+
+hipError_t reduced_dm(int dtype, const void *psi, int nq, int k, const int *pos, double *ws,
+                      double *out_dev, hipStream_t s) {
+    if (k < 1 || k > 2 || nq < k) return hipErrorInvalidValue;
+    IndexArgs ia;
+    int sorted[2] = {pos[0], k > 1 ? pos[1] : 0};
+    if (k > 1 && sorted[1] < sorted[0]) std::swap(sorted[0], sorted[1]);
+    ia.npos = k;
+    for (int j = 0; j < k; ++j) ia.pos[j] = (uint8_t)sorted[j];
+    const uint64_t ngroups = 1ull << (nq - k);
+    const unsigned g = red_grid(ngroups);
+    const int w = 2 << (2 * k);
+    const int tp1 = k > 1 ? pos[1] : 0;
+#define QSV_RDM(R, K)                                                                        \
+    hipLaunchKernelGGL((k_reduced_dm<R, K>), dim3(g), dim3(kRedThreads), 0, s,               \
+                       (const typename V2r<R>::T *)psi, ngroups, ia, pos[0], tp1, ws)
+    if (dtype == 0) {
+        if (k == 1) QSV_RDM(double, 1);
+        else QSV_RDM(double, 2);
+    } else {
+        if (k == 1) QSV_RDM(float, 1);
+        else QSV_RDM(float, 2);
+    }
+#undef QSV_RDM
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedThreads), 0, s, ws, (int)g, w, w, out_dev);
+    return hipGetLastError();
+}
+
 template <typename R>
 __global__ void k_probs(const typename V2r<R>::T *psi, uint64_t dim, double *out) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;

@@ -1100,6 +1100,76 @@ qsv_status qsv_measure(qsv_sim *s, int32_t m, const int32_t *qubits, const doubl
     return sync(s);
 }
 
+qsv_status qsv_apply_kraus_sampled(qsv_sim *s, int32_t nk, const double *kraus, int32_t k,
+                                   const int32_t *targets, double u, int32_t *chosen,
+                                   double *probs) {
+    QSV_CHECK(s);
+    if (nk < 1 || !kraus || !targets || !chosen) return fail(s, QSV_EINVAL, "bad argument");
+    if (k < 1 || k > 2) return fail(s, QSV_EINVAL, "k must be 1 or 2");
+    if (!(u >= 0.0 && u < 1.0)) return fail(s, QSV_EINVAL, "uniform outside [0,1)");
+    QSV_TRY(check_ids(s, k, targets, nullptr));
+    const int D = 1 << k;
+    for (int i = 0; i < nk * D * D * 2; ++i)
+        if (!std::isfinite(kraus[i])) return fail(s, QSV_EINVAL, "non-finite Kraus entry");
+    QSV_TRY(do_flush(s));
+    QSV_TRY(materialize(s));
+    // reduced density matrix of the targets (bit j of its index = target j)
+    int pos[2] = {s->pos_of[targets[0]], k > 1 ? s->pos_of[targets[1]] : 0};
+    QSV_TRY(ensure_ws(s, qsv::dev::reduced_dm_workspace_bytes()));
+    const int tok = tbegin(s);
+    QSV_HIP(s, qsv::dev::reduced_dm(s->opt.dtype, s->d_state, s->n, k, pos, (double *)s->d_ws,
+                                    s->d_small, s->stream));
+    tend(s, tok, QSV_K_REDUCE, (double)s->dim() * s->elem());
+    double h[32];
+    QSV_HIP(s, hipMemcpyAsync(h, s->d_small, sizeof(double) * 2 * D * D, hipMemcpyDeviceToHost,
+                              s->stream));
+    s->stats.kernels += 2;
+    s->stats.alg_bytes += (double)s->dim() * s->elem();
+    QSV_TRY(sync(s));
+    std::vector<cd> rho((size_t)D * D);
+    for (int e = 0; e < D * D; ++e) rho[e] = cd(h[2 * e], h[2 * e + 1]);
+    // p_j = ||K_j psi||^2 = Tr(K_j rho K_j^dagger)
+    std::vector<double> p(nk);
+    double total = 0.0;
+    for (int j = 0; j < nk; ++j) {
+        const double *K = kraus + (size_t)j * D * D * 2;
+        double pj = 0.0;
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b)
+                for (int c = 0; c < D; ++c) {
+                    const cd kab(K[2 * (a * D + b)], K[2 * (a * D + b) + 1]);
+                    const cd kac(K[2 * (a * D + c)], K[2 * (a * D + c) + 1]);
+                    pj += (kab * rho[b * D + c] * std::conj(kac)).real();
+                }
+        p[j] = std::max(pj, 0.0);
+        total += p[j];
+    }
+    if (probs)
+        for (int j = 0; j < nk; ++j) probs[j] = p[j];
+    if (!(total > 0.0) || !std::isfinite(total))
+        return fail(s, QSV_EINVAL, "the channel leaves no probability");
+    // the first branch whose running sum exceeds u * total
+    const double r = u * total;
+    int pick = -1;
+    double run = 0.0;
+    for (int j = 0; j < nk; ++j) {
+        run += p[j];
+        if (run > r) {
+            pick = j;
+            break;
+        }
+    }
+    if (pick < 0)
+        for (int j = nk - 1; j >= 0 && pick < 0; --j)
+            if (p[j] > 0.0) pick = j;
+    *chosen = pick;
+    // queue K_pick / sqrt(p_pick): the state keeps unit norm
+    const double sc = 1.0 / std::sqrt(p[pick]);
+    std::vector<double> G((size_t)D * D * 2);
+    for (int i = 0; i < D * D * 2; ++i) G[i] = kraus[(size_t)pick * D * D * 2 + i] * sc;
+    return qsv_apply(s, G.data(), k, targets, 0, nullptr);
+}
+
 qsv_status qsv_sample(qsv_sim *s, int32_t shots, const double *u, uint64_t *out) {
     QSV_CHECK(s);
     if (shots < 0 || (shots > 0 && (!u || !out))) return fail(s, QSV_EINVAL, "bad argument");

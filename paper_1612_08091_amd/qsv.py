@@ -100,6 +100,8 @@ _SIGS = {
     "qsv_get_expectation": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "qsv_measure": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "qsv_sample": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "qsv_apply_kraus_sampled": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P,
+                                               ctypes.c_double, _P, _P]),
     "qsv_get_state": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "qsv_set_state": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "qsv_get_amplitudes": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
@@ -321,6 +323,19 @@ class Simulator:
         out = np.zeros(max(len(qubits), 1), dtype=np.int8)
         _check(lib.qsv_measure(self._h, len(qubits), _ptr(q), _ptr(uu), _ptr(out)), self._h)
         return out[: len(qubits)].tolist()
+
+    def apply_kraus_sampled(self, kraus, targets: Sequence[int], u: float):
+        """One stochastic-trajectory step: replace the channel {K_j} on
+        ``targets`` (k <= 2) by branch j, chosen with the uniform ``u`` from
+        p_j = ||K_j psi||^2; the state becomes K_j psi / sqrt(p_j).  Returns
+        (j, p) with p the array of branch probabilities."""
+        ks = np.ascontiguousarray(np.stack([np.asarray(k, dtype=np.complex128) for k in kraus]))
+        t = np.ascontiguousarray(list(targets), dtype=np.int32)
+        chosen = ctypes.c_int32(-1)
+        probs = np.zeros(len(ks), dtype=np.float64)
+        _check(lib.qsv_apply_kraus_sampled(self._h, len(ks), _ptr(ks), len(t), _ptr(t), float(u),
+                                           ctypes.byref(chosen), _ptr(probs)), self._h)
+        return int(chosen.value), probs
 
     def sample(self, u) -> np.ndarray:
         uu = np.ascontiguousarray(u, dtype=np.float64)

@@ -133,6 +133,21 @@ def test_reductions_validate_before_device():
     expect_status(1, s.get_amplitudes, [8])               # index >= 2^n
 
 
+def test_sampled_channel_validates_before_device():
+    s, ids = new_sim(3)
+    ad = W.amplitude_damping(0.2)
+    expect_status(1, s.apply_kraus_sampled, ad, [0], 1.0)          # u outside [0,1)
+    expect_status(1, s.apply_kraus_sampled, ad, [0], -0.5)
+    expect_status(1, s.apply_kraus_sampled, ad, [7], 0.5)          # unknown id
+    two = [np.kron(a, b) for a in ad for b in ad]
+    expect_status(1, s.apply_kraus_sampled, two, [1, 1], 0.5)      # repeated id
+    three = [np.eye(8)]
+    expect_status(1, s.apply_kraus_sampled, three, [0, 1, 2], 0.5)  # k > 2
+    bad = [ad[0].copy(), ad[1].copy()]
+    bad[1][0, 1] = np.nan
+    expect_status(1, s.apply_kraus_sampled, bad, [0], 0.5)         # non-finite entry
+
+
 # ----------------------------------------------------------- planner exactness
 def planned_product(sim, n):
     ops, npass = sim.plan()

@@ -14,7 +14,10 @@ QFT-phase-QFT^-1 construction of AddConstant through ``apply`` and through the
 gate-level Draper adder, the X gate as the 1-bit table), dm_apply / dm_kraus /
 dm_expectation (pure states against the state-vector oracle, closed forms of
 the depolarizing, amplitude-damping and dephasing channels, trace
-preservation, Kronecker-product operators from tests/brute.py).
+preservation, Kronecker-product operators from tests/brute.py), kraus_sample
+(closed forms of the bit-flip and amplitude-damping branches, the branch
+probabilities against dense operators, the probability-weighted branches
+against the density-matrix channel, the tie rule at a running-sum boundary).
 """
 import json
 import math
@@ -356,6 +359,74 @@ def test_dm_fully_depolarized_expectations_vanish(rng):
     re, im, terms = oracle.dm_expectation(rho, ham, return_terms=True)
     ident = (np.asarray(ham.xmask) == 0) & (np.asarray(ham.zmask) == 0)
     assert np.max(np.abs(terms[~ident])) <= 1e-15
+
+
+# ------------------------------------------------- stochastic trajectories
+def test_kraus_sample_bit_flip_closed_form(rng):
+    # K0 = sqrt(1-p) I, K1 = sqrt(p) X: p_0 = 1 - p and p_1 = p for any unit
+    # state; branch 0 leaves the state alone, branch 1 applies X
+    n, q, p = 4, 2, 0.3
+    ks = [math.sqrt(1 - p) * np.eye(2), math.sqrt(p) * np.array([[0, 1], [1, 0]])]
+    psi = random_state(rng, n)
+    a = psi.copy()
+    j, pr = oracle.kraus_sample(a, ks, [q], 0.69)
+    assert j == 0 and abs(pr[0] - (1 - p)) <= 1e-15 and abs(pr[1] - p) <= 1e-15
+    assert np.max(np.abs(a - psi)) <= 1e-15
+    b = psi.copy()
+    j, _ = oracle.kraus_sample(b, ks, [q], 0.71)
+    assert j == 1
+    assert np.max(np.abs(b - brute.gate_operator(np.array([[0, 1], [1, 0]]), [q], [], n) @ psi)) <= 1e-15
+
+
+def test_kraus_sample_boundary_takes_next_branch():
+    # the branch is the first whose running sum EXCEEDS u * total: at u = 1/2
+    # with p = (1/2, 1/2) that is branch 1
+    ks = [math.sqrt(0.5) * np.eye(2), math.sqrt(0.5) * np.array([[0, 1], [1, 0]])]
+    psi = np.array([1.0, 0.0], dtype=np.complex128)
+    j, _ = oracle.kraus_sample(psi, ks, [0], 0.5)
+    assert j == 1 and abs(psi[1] - 1.0) <= 1e-15
+
+
+def test_kraus_sample_amplitude_damping_closed_form():
+    # |1> on qubit 1 of |0 1 0>: p(decay) = gamma exactly, and the decayed
+    # branch is |000>; the other branch stays |010>
+    g = 0.35
+    ks = W.amplitude_damping(g)
+    psi = oracle.basis_state(3, 0b010)
+    j, pr = oracle.kraus_sample(psi, ks, [1], 0.99)
+    assert j == 1 and abs(pr[1] - g) <= 1e-15 and abs(pr[0] - (1 - g)) <= 1e-15
+    assert abs(psi[0] - 1.0) <= 1e-15 and np.sum(np.abs(psi) ** 2) - 1 <= 1e-15
+    psi = oracle.basis_state(3, 0b010)
+    j, _ = oracle.kraus_sample(psi, ks, [1], 0.2)
+    assert j == 0 and abs(abs(psi[0b010]) - 1.0) <= 1e-15
+
+
+@pytest.mark.parametrize("targets", [[1], [3, 0]])
+def test_kraus_sample_branches_average_to_channel(rng, targets):
+    # sum_j p_j |psi_j><psi_j| over the branches equals the channel applied to
+    # |psi><psi| (dm_kraus), and p_j = ||K_j psi||^2 with dense operators
+    n = 4
+    if len(targets) == 1:
+        ks = W.amplitude_damping(0.3) + [0.0 * np.eye(2)]
+    else:
+        ks = [np.kron(a, b) for a in W.depolarizing(0.4) for b in W.dephasing(0.5)]
+    psi = random_state(rng, n)
+    want = oracle.dm_kraus(np.ascontiguousarray(np.outer(psi, psi.conj())), ks, targets)
+    pd = [np.linalg.norm(brute.gate_operator(k, targets, [], n) @ psi) ** 2 for k in ks]
+    _, pr = oracle.kraus_sample(psi.copy(), ks, targets, 0.0)
+    assert np.max(np.abs(pr - pd)) <= 1e-14
+    total = float(np.sum(pr))
+    acc = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+    run = 0.0
+    for j, pj in enumerate(pr):
+        if pj > 0:
+            u = (run + pj / 2) / total
+            a = psi.copy()
+            jj, _ = oracle.kraus_sample(a, ks, targets, u)
+            assert jj == j
+            acc += pj * np.outer(a, a.conj())
+        run += pj
+    assert np.max(np.abs(acc - want)) <= 1e-14
 
 
 # ------------------------------------------------------------ probabilities
