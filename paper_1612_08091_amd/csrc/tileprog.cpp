@@ -231,6 +231,7 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         std::vector<cd> val;   // val[r], bit j of r <-> qubit t[j]
     };
     std::vector<DiagRun> runs;
+    std::vector<uint64_t> run_all;   // qubits of each run (for commutation)
     std::vector<Item> items;
     const int n_ops = (int)ps.ops.size();
     auto is_diag = [](const Op &o) { return o.kind == Op::MONO && o.diag && o.touch != 0; };
@@ -278,6 +279,9 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
                 }
                 prog.diag_merged += (int)mem.size() - 1;
             }
+            uint64_t all = 0;
+            for (const Op *o : mem) all |= o->qubits();
+            run_all.push_back(all);
             runs.push_back(std::move(run));
             items.push_back({dev::ROP_DIAG, 0u, nullptr, (int)runs.size() - 1});
             oi = oj - 1;
@@ -291,6 +295,73 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         }
         if (inside && op.k <= 2) items.push_back({op.k == 1 ? dev::ROP_G1 : dev::ROP_G2, need, &op, -1});
         else items.push_back({dev::ROP_LDS, 0u, &op, -1});
+    }
+    // Ops of a pass that commute may run in any order.  List scheduling over
+    // the order that non-commuting ops impose: among the ops whose
+    // predecessors have run, take the first (in queue order) whose bits are
+    // already register bits; if none is, the first one, and model the new
+    // register set as its bits plus the old register bits that the most
+    // waiting ops need.  The lowering below then places the layout changes.
+    {
+        const int N = (int)items.size();
+        std::vector<uint64_t> q_all(N), q_mix(N);
+        for (int i = 0; i < N; ++i) {
+            if (items[i].run >= 0) {
+                q_all[i] = run_all[items[i].run];
+                q_mix[i] = 0;
+            } else {
+                q_all[i] = items[i].op->qubits();
+                q_mix[i] = items[i].op->mixing();
+            }
+        }
+        std::vector<int> npred(N, 0);
+        std::vector<std::vector<int>> succ(N);
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < i; ++j)
+                if (!commute_masks(q_mix[j], q_all[j], q_mix[i], q_all[i])) {
+                    succ[j].push_back(i);
+                    npred[i] += 1;
+                }
+        uint32_t Sm = 0;
+        for (const Item &it : items) {
+            if (__builtin_popcount(Sm | it.need) > rb) break;
+            Sm |= it.need;
+        }
+        std::vector<char> ready(N, 0), done(N, 0);
+        for (int i = 0; i < N; ++i) ready[i] = npred[i] == 0;
+        std::vector<Item> order;
+        order.reserve(N);
+        for (int step = 0; step < N; ++step) {
+            int pick = -1;
+            for (int i = 0; i < N && pick < 0; ++i)
+                if (ready[i] && !done[i] && (items[i].need & ~Sm) == 0) pick = i;
+            if (pick < 0) {
+                for (int i = 0; i < N && pick < 0; ++i)
+                    if (ready[i] && !done[i]) pick = i;
+                // new register set: the op's bits, then the old register bits
+                // wanted by the most ops that wait (ready ones count more)
+                uint32_t Sn = items[pick].need;
+                int cnt[32] = {0};
+                for (int i = 0; i < N; ++i)
+                    if (!done[i] && i != pick)
+                        for (int b = 0; b < m; ++b)
+                            if ((items[i].need >> b) & 1) cnt[b] += ready[i] ? 4 : 1;
+                while (__builtin_popcount(Sn) < rb) {
+                    int best = -1;
+                    for (int b = 0; b < m; ++b)
+                        if (!((Sn >> b) & 1) && ((Sm >> b) & 1) && (best < 0 || cnt[b] > cnt[best]))
+                            best = b;
+                    if (best < 0) break;
+                    Sn |= 1u << best;
+                }
+                Sm = Sn;
+            }
+            done[pick] = 1;
+            order.push_back(items[pick]);
+            for (int j : succ[pick])
+                if (--npred[j] == 0) ready[j] = 1;
+        }
+        items.swap(order);
     }
     const int n_items = (int)items.size();
     // initial register set: the first needed bits, then the highest free bits
