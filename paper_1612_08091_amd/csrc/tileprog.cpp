@@ -299,9 +299,11 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
     // Ops of a pass that commute may run in any order.  List scheduling over
     // the order that non-commuting ops impose: among the ops whose
     // predecessors have run, take the first (in queue order) whose bits are
-    // already register bits; if none is, the first one, and model the new
-    // register set as its bits plus the old register bits that the most
-    // waiting ops need.  The lowering below then places the layout changes.
+    // already register bits; if none is, the one with the fewest bits missing
+    // (a one-bit change is often a cross-lane swap, and a layout change costs
+    // a workgroup-wide LDS round trip), and model the new register set as its
+    // bits plus the old register bits that the most waiting ops need.  The
+    // lowering below then places the layout changes.
     {
         const int N = (int)items.size();
         std::vector<uint64_t> q_all(N), q_mix(N);
@@ -336,8 +338,15 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
             for (int i = 0; i < N && pick < 0; ++i)
                 if (ready[i] && !done[i] && (items[i].need & ~Sm) == 0) pick = i;
             if (pick < 0) {
-                for (int i = 0; i < N && pick < 0; ++i)
-                    if (ready[i] && !done[i]) pick = i;
+                int fewest = 1 << 30;
+                for (int i = 0; i < N; ++i)
+                    if (ready[i] && !done[i]) {
+                        const int miss = __builtin_popcount(items[i].need & ~Sm);
+                        if (miss < fewest) {
+                            fewest = miss;
+                            pick = i;
+                        }
+                    }
                 // new register set: the op's bits, then the old register bits
                 // wanted by the most ops that wait (ready ones count more)
                 uint32_t Sn = items[pick].need;
