@@ -75,12 +75,7 @@ struct TileArgs {
 };
 
 // One operation of the register-resident tile kernel.
-// ROP_SWAP: register bit a and lane bit 4 (b = 16) or 5 (b = 32) trade places
-// inside the wave (cross-lane swaps, no LDS); reg_lbit / thr_lbit and
-// g_reg / g_thr give the new layout.
-enum RegOpKind : int32_t {
-    ROP_G1 = 0, ROP_G2 = 1, ROP_DIAG = 2, ROP_REMAP = 3, ROP_LDS = 4, ROP_SWAP = 5
-};
+enum RegOpKind : int32_t { ROP_G1 = 0, ROP_G2 = 1, ROP_DIAG = 2, ROP_REMAP = 3, ROP_LDS = 4 };
 // Widest diagonal op of the register kernel (targets; its table of 2^k
 // factors is staged per wave in LDS).
 constexpr int kRegDiagMax = 8;

@@ -268,66 +268,6 @@ __device__ __forceinline__ void dispatch_g2(T *amp, int a, int b, const T *U, ui
 }
 
 // One operation of a register program on the thread's amplitudes.
-// Exchange register bit J with lane bit 4 (S16) or 5: for every register
-// pair (i, i + 2^J) the lanes with that lane bit set in register i trade
-// values with the lanes with it clear in register i + 2^J.
-template <bool S16>
-__device__ __forceinline__ void lane_swap32(uint32_t &a, uint32_t &b) {
-    if constexpr (S16) {
-        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
-        a = r[0];
-        b = r[1];
-    } else {
-        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
-        a = r[0];
-        b = r[1];
-    }
-}
-
-template <bool S16, typename R>
-__device__ __forceinline__ void lane_swap_r(R &a, R &b) {
-    if constexpr (sizeof(R) == 8) {
-        uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-        uint32_t al = (uint32_t)ua, ah = (uint32_t)(ua >> 32);
-        uint32_t bl = (uint32_t)ub, bh = (uint32_t)(ub >> 32);
-        lane_swap32<S16>(al, bl);
-        lane_swap32<S16>(ah, bh);
-        a = __builtin_bit_cast(R, ((uint64_t)ah << 32) | al);
-        b = __builtin_bit_cast(R, ((uint64_t)bh << 32) | bl);
-    } else {
-        uint32_t ua = __builtin_bit_cast(uint32_t, a), ub = __builtin_bit_cast(uint32_t, b);
-        lane_swap32<S16>(ua, ub);
-        a = __builtin_bit_cast(R, ua);
-        b = __builtin_bit_cast(R, ub);
-    }
-}
-
-template <typename T, int NR, int J, bool S16>
-__device__ __forceinline__ void swap_bit(T *amp) {
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        if (i & (1 << J)) continue;
-        lane_swap_r<S16>(amp[i].x, amp[i | (1 << J)].x);
-        lane_swap_r<S16>(amp[i].y, amp[i | (1 << J)].y);
-    }
-}
-
-template <typename T, int NR, int RB, bool S16>
-__device__ __forceinline__ void dispatch_swap(T *amp, int j) {
-    switch (j) {
-    case 0: swap_bit<T, NR, 0, S16>(amp); break;
-    case 1: swap_bit<T, NR, 1, S16>(amp); break;
-    case 2: swap_bit<T, NR, 2, S16>(amp); break;
-    case 3:
-        if constexpr (RB > 3) swap_bit<T, NR, 3, S16>(amp);
-        break;
-    case 4:
-        if constexpr (RB > 4) swap_bit<T, NR, 4, S16>(amp);
-        break;
-    default: break;
-    }
-}
-
 template <typename T, int NR, int RB, int TB, bool DG>
 __device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restrict__ pool,
                                        unsigned char *lds, T *dtab, uint64_t base, uint64_t &gthr,
@@ -345,20 +285,6 @@ __device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restr
     } else if (kind == ROP_DIAG) {
         if constexpr (DG) reg_diag<T, NR, RB>(amp, op, pool, gb, dtab);
         else __builtin_unreachable();
-    } else if (kind == ROP_SWAP) {
-        if (op.b == 16) dispatch_swap<T, NR, RB, true>(amp, op.a);
-        else dispatch_swap<T, NR, RB, false>(amp, op.a);
-        uint32_t tr = tid;
-        asm volatile("" : "+v"(tr));
-        uint64_t gthr_n = 0;
-#pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            const uint32_t msk = 0u - ((tr >> t) & 1u);
-            gthr_n |= (((uint64_t)msk << 32) | msk) & op.g_thr[t];
-        }
-#pragma unroll
-        for (int j = 0; j < RB; ++j) gbit[j] = op.g_reg[j];
-        gthr = gthr_n;
     } else {
         // thread parts from the thread-id bits; the empty asm makes the id
         // opaque so the per-bit masks are not kept live across the op loop

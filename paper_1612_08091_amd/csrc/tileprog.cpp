@@ -147,13 +147,6 @@ void fill_layouts(TileProgram &prog, int rb, int elem_bytes) {
     std::memcpy(cur_reg, prog.reg_lbit, 8);
     std::memcpy(cur_thr, prog.thr_lbit, 16);
     for (dev::RegOp &r : prog.rops) {
-        if (r.kind == dev::ROP_SWAP) {
-            for (int t = 0; t < tb; ++t) r.g_thr[t] = 1ull << tpos[r.thr_lbit[t]];
-            for (int j = 0; j < rb; ++j) r.g_reg[j] = 1ull << tpos[r.reg_lbit[j]];
-            std::memcpy(cur_reg, r.reg_lbit, 8);
-            std::memcpy(cur_thr, r.thr_lbit, 16);
-            continue;
-        }
         if (r.kind != dev::ROP_REMAP) continue;
         const int kept = cur_reg[r.a];
         for (int i = 0; i < nr; ++i) {
@@ -300,10 +293,11 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
     // the order that non-commuting ops impose: among the ops whose
     // predecessors have run, take the first (in queue order) whose bits are
     // already register bits; if none is, the one with the fewest bits missing
-    // (a one-bit change is often a cross-lane swap, and a layout change costs
-    // a workgroup-wide LDS round trip), and model the new register set as its
-    // bits plus the old register bits that the most waiting ops need.  The
-    // lowering below then places the layout changes.
+    // (its layout change keeps more of the register set that the waiting ops
+    // may want, and every change is a workgroup-wide LDS round trip), and
+    // model the new register set as its bits plus the old register bits that
+    // the most waiting ops need.  The lowering below then places the layout
+    // changes.
     {
         const int N = (int)items.size();
         std::vector<uint64_t> q_all(N), q_mix(N);
@@ -388,39 +382,6 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
 
     for (int i = 0; i < n_items; ++i) {
         const Item &it = items[i];
-        if ((it.need & ~S) != 0) {
-            // Belady: keep the bits needed soonest
-            int next_use[32];
-            for (int b = 0; b < m; ++b) next_use[b] = 1 << 30;
-            for (int j = n_items - 1; j >= i; --j)
-                for (int b = 0; b < m; ++b)
-                    if ((items[j].need >> b) & 1) next_use[b] = j;
-            // One missing bit that sits on lane bit 4 or 5: trade it with the
-            // register bit used last, by cross-lane swaps inside the wave (no
-            // LDS round trip)
-            const uint32_t miss = it.need & ~S;
-            int lane_t = -1;
-            if (__builtin_popcount(miss) == 1)
-                for (int t = 4; t <= 5 && t < tb; ++t)
-                    if (cur_thr[t] == __builtin_ctz(miss)) lane_t = t;
-            if (lane_t >= 0) {
-                int v = -1;
-                for (int j = 0; j < rb; ++j)
-                    if (!((it.need >> cur_reg[j]) & 1) &&
-                        (v < 0 || next_use[cur_reg[j]] > next_use[cur_reg[v]]))
-                        v = j;
-                dev::RegOp r{};
-                r.kind = dev::ROP_SWAP;
-                r.a = v;
-                r.b = lane_t == 4 ? 16 : 32;
-                S = (S & ~(1u << cur_reg[v])) | miss;
-                std::swap(cur_reg[v], cur_thr[lane_t]);
-                std::memcpy(r.reg_lbit, cur_reg, 8);
-                std::memcpy(r.thr_lbit, cur_thr, 16);
-                prog.rops.push_back(r);
-                prog.swaps += 1;
-            }
-        }
         if ((it.need & ~S) != 0) {
             int next_use[32];
             for (int b = 0; b < m; ++b) next_use[b] = 1 << 30;

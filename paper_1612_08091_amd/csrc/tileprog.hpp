@@ -20,7 +20,6 @@ struct TileProgram {
     uint64_t g_reg[8] = {};             // initial layout as global index bits
     uint64_t g_thr[16] = {};
     int remaps = 0;                     // layout changes through LDS
-    int swaps = 0;                      // layout changes by cross-lane swaps
     int diag_merged = 0;                // diagonal ops folded into a preceding one
     int mfma_k = 0;                     // widest matrix-core op (LDS kernel)
     double flops_per_amp = 0.0;
