@@ -73,11 +73,15 @@ __global__ __launch_bounds__(kNT) void k_tile_lds(typename VT<R>::T *__restrict_
         }
         unsigned int next = 0;
         if (tid == 0) next = atomicAdd(counter, 1u);
+        // normal priority for the ops; raised again for the stores and the
+        // next tile's loads (see k_tile_reg)
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         for (int oi = 0; oi < ta.n_ops; ++oi) {
             lds_op<R, KM>(tile, m, base, ta.tpos, ops[oi], pool, ta.dep_hi);
             __syncthreads();
         }
+        __builtin_amdgcn_s_setprio(2);
         if (tsize >= 8 * kNT) {
             for (uint32_t j0 = 0; j0 < tsize; j0 += 8 * kNT) {
                 T v[8];
@@ -299,6 +303,10 @@ __device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restr
             rt ^= msk & op.rthr[t];
             gthr_n |= (((uint64_t)msk << 32) | msk) & op.g_thr[t];
         }
+        // raised priority through the remap (LDS round trips and barriers
+        // that the whole workgroup waits on), as for the tile's stores and
+        // loads
+        __builtin_amdgcn_s_setprio(2);
         switch (op.a) {
         case 0: remap_half<T, NR, 0>(amp, lds, wt, rt, op); break;
         case 1: remap_half<T, NR, 1>(amp, lds, wt, rt, op); break;
@@ -313,6 +321,7 @@ __device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restr
             break;
         default: __builtin_unreachable();
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int j = 0; j < RB; ++j) gbit[j] = op.g_reg[j];
         gthr = gthr_n;
@@ -374,6 +383,11 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
         // claim the next tile now; the atomic's latency hides behind the ops
         unsigned int next = 0;
         if (tid == 0) next = atomicAdd(counter, 1u);
+        // back to normal priority for the arithmetic (raised before the
+        // stores below: a wave that stores one tile and issues the next
+        // tile's loads goes ahead of the other waves' FMAs, so the memory
+        // requests of the compute units go out sooner)
+        __builtin_amdgcn_s_setprio(0);
         uint64_t gbit[RB];
 #pragma unroll
         for (int j = 0; j < RB; ++j) gbit[j] = gbit0[j];
@@ -386,6 +400,7 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
             reg_op<T, NR, RB, TB, DG>(amp, ops[oi], pool, lds, dtab, base, gthr, gbit, tid);
             reg_op<T, NR, RB, TB, DG>(amp, ops[oi + 1], pool, lds, dtab, base, gthr, gbit, tid);
         }
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int i = 0; i < NR; ++i) psi[base | gthr | greg<T, NR, RB>(i, gbit)] = amp[i];
         __syncthreads();   // every thread has read s_tile and left the LDS buffer
