@@ -550,6 +550,9 @@ __global__ __launch_bounds__(kNT) void k_adj_tile(typename VT<R>::T *__restrict_
                     tf[li] = phi[gi];
                 }
         }
+        // normal priority for the steps; raised for the stores and the next
+        // tiles' loads, which then go out ahead of other waves' arithmetic
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         T pend;
         pend.x = R(1);
@@ -557,6 +560,7 @@ __global__ __launch_bounds__(kNT) void k_adj_tile(typename VT<R>::T *__restrict_
         for (int oi = 0; oi < ta.n_ops; ++oi)
             if (adj_step<R, KM>(tp, tf, m, base, ta, ops[oi], subs, pool, acc, pend))
                 __syncthreads();
+        __builtin_amdgcn_s_setprio(2);
         const bool ph = pend.x != R(1) || pend.y != R(0);
         if (tsize >= 4 * kNT) {
             for (uint32_t j0 = 0; j0 < tsize; j0 += 4 * kNT) {
