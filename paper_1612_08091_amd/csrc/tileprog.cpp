@@ -297,8 +297,12 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
     // may want, and every change is a workgroup-wide LDS round trip), and
     // model the new register set as its bits plus the old register bits that
     // the most waiting ops need.  The lowering below then places the layout
-    // changes.
+    // changes.  The choice is among the next kWin unscheduled ops (queue
+    // order), which bounds the cost on long passes: the first unscheduled op
+    // is always ready, and an op further than kWin behind an unscheduled
+    // one cannot be picked, so only dependences within kWin need recording.
     {
+        constexpr int kWin = 256;
         const int N = (int)items.size();
         std::vector<uint64_t> q_all(N), q_mix(N);
         for (int i = 0; i < N; ++i) {
@@ -313,7 +317,7 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         std::vector<int> npred(N, 0);
         std::vector<std::vector<int>> succ(N);
         for (int i = 0; i < N; ++i)
-            for (int j = 0; j < i; ++j)
+            for (int j = std::max(0, i - kWin); j < i; ++j)
                 if (!commute_masks(q_mix[j], q_all[j], q_mix[i], q_all[i])) {
                     succ[j].push_back(i);
                     npred[i] += 1;
@@ -327,13 +331,16 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         for (int i = 0; i < N; ++i) ready[i] = npred[i] == 0;
         std::vector<Item> order;
         order.reserve(N);
+        int first = 0;   // first unscheduled op
         for (int step = 0; step < N; ++step) {
+            while (done[first]) ++first;
+            const int end = std::min(N, first + kWin);
             int pick = -1;
-            for (int i = 0; i < N && pick < 0; ++i)
+            for (int i = first; i < end && pick < 0; ++i)
                 if (ready[i] && !done[i] && (items[i].need & ~Sm) == 0) pick = i;
             if (pick < 0) {
                 int fewest = 1 << 30;
-                for (int i = 0; i < N; ++i)
+                for (int i = first; i < end; ++i)
                     if (ready[i] && !done[i]) {
                         const int miss = __builtin_popcount(items[i].need & ~Sm);
                         if (miss < fewest) {
@@ -345,7 +352,7 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
                 // wanted by the most ops that wait (ready ones count more)
                 uint32_t Sn = items[pick].need;
                 int cnt[32] = {0};
-                for (int i = 0; i < N; ++i)
+                for (int i = first; i < end; ++i)
                     if (!done[i] && i != pick)
                         for (int b = 0; b < m; ++b)
                             if ((items[i].need >> b) & 1) cnt[b] += ready[i] ? 4 : 1;
@@ -367,6 +374,13 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         items.swap(order);
     }
     const int n_items = (int)items.size();
+    // next_at[i * m + b]: the first op at or after position i that needs
+    // tile bit b (1 << 30: none), for the Belady choices of the remaps
+    std::vector<int> next_at((size_t)(n_items + 1) * m, 1 << 30);
+    for (int i = n_items - 1; i >= 0; --i)
+        for (int b = 0; b < m; ++b)
+            next_at[(size_t)i * m + b] =
+                ((items[i].need >> b) & 1) ? i : next_at[(size_t)(i + 1) * m + b];
     // initial register set: the first needed bits, then the highest free bits
     uint32_t S = 0;
     for (const Item &it : items) {
@@ -384,10 +398,7 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         const Item &it = items[i];
         if ((it.need & ~S) != 0) {
             int next_use[32];
-            for (int b = 0; b < m; ++b) next_use[b] = 1 << 30;
-            for (int j = n_items - 1; j >= i; --j)
-                for (int b = 0; b < m; ++b)
-                    if ((items[j].need >> b) & 1) next_use[b] = j;
+            for (int b = 0; b < m; ++b) next_use[b] = next_at[(size_t)i * m + b];
             uint32_t Sn = it.need;
             std::vector<int> cand;
             for (int b = 0; b < m; ++b)
