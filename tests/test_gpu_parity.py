@@ -160,6 +160,25 @@ def test_diagonal_runs_tiled(dtype, n):
     s.close()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_long_single_pass_scheduling(dtype):
+    # 12 qubits fit one tile: 1200 gates become one pass of several hundred
+    # ops, longer than the lowering's scheduling window
+    n = 12
+    rng = np.random.default_rng(8080)
+    circ = random_circuit(rng, n, 1200, kmax=2)   # register-kernel ops only
+    log("case long pass", dtype)
+    s = make(n, mode="tiled", k_max=2, dtype=dtype)
+    s.run(circ)
+    got = s.get_state()
+    want = oracle.run(circ)
+    if dtype == "c128":
+        check_c128(got, want, tol=1e-11)
+    else:
+        check_c64(got, want)
+    s.close()
+
+
 def test_config0_state_probs_samples():
     circ, u = W.config0()
     log("case config0")
