@@ -535,7 +535,9 @@ def main():
     elif args.k_max <= 2:
         # the benchmark circuit has no diagonal op: its passes run the kernel
         # instance without that case
-        kname = "k_tile_reg<%s,%d,8,false>" % (rname, args.reg_bits or 4)
+        rb = args.reg_bits or 4
+        tb = (args.tile_bits or 12) - rb
+        kname = "k_tile_reg<%s,%d,%d,false>" % (rname, rb, tb)
     else:
         kname = "k_tile_lds<%s,k<=%d> (MFMA for k>=3)" % (rname, args.k_max)
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
