@@ -241,3 +241,34 @@ def test_canonical_forms_drop_identities_and_extract_controls():
     (m0, t0, c0), (m1, t1, c1) = ops
     assert len(t0) == 1 and bin(c0).count("1") == 1
     assert len(t1) == 1 and c1 == 1 and t1 == [1]
+
+
+# ----------------------------------------------------------------- bench.py
+def test_bench_refuses_more_than_one_gpu():
+    # the measured path runs on one GPU; the check comes before any GPU work
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_traffic_is_tied_to_the_kernel_sources():
+    # bench.py reports measured HBM traffic only while the digest of the
+    # kernel's sources is the one the counters were taken with
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    t = dict(b.TRAFFIC)
+    got = b.measured_traffic()
+    if t["digest"] == b.kernel_source_digest():
+        assert got == 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+    else:
+        assert got is None
+    b.TRAFFIC["digest"] = "0" * 16
+    try:
+        assert b.measured_traffic() is None
+    finally:
+        b.TRAFFIC.update(t)
