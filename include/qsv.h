@@ -214,6 +214,14 @@ qsv_status qsv_get_probabilities(qsv_sim *sim, double *out, int32_t out_is_devic
 qsv_status qsv_get_expectation(qsv_sim *sim, int32_t nterms, const uint64_t *xmask,
                                const uint64_t *zmask, const double *coeff, double *out);
 
+/* As qsv_get_expectation, with the imaginary part of sum_t coeff[t] <P_t> in
+ * *im_out.  A Pauli sum with real coefficients is Hermitian, so the
+ * imaginary part is zero up to rounding; it is returned so that callers (and
+ * the parity tests) can check that.  Flushes; synchronises. */
+qsv_status qsv_get_expectation_complex(qsv_sim *sim, int32_t nterms, const uint64_t *xmask,
+                                       const uint64_t *zmask, const double *coeff, double *re_out,
+                                       double *im_out);
+
 /* Measure qubits[m] one after the other in list order (App. A.1), qubit j with
  * the caller's uniform u[j] in [0,1): outcome 0 iff u*(p0+p1) < p0; the other
  * branch is zeroed and the kept one scaled by 1/sqrt(p_outcome).  Outcomes go

@@ -1050,10 +1050,11 @@ static qsv_status expectation_positions(qsv_sim *s, const void *psi, int nq, int
     return QSV_OK;
 }
 
-qsv_status qsv_get_expectation(qsv_sim *s, int32_t nterms, const uint64_t *xmask,
-                               const uint64_t *zmask, const double *coeff, double *out) {
+qsv_status qsv_get_expectation_complex(qsv_sim *s, int32_t nterms, const uint64_t *xmask,
+                                       const uint64_t *zmask, const double *coeff, double *re_out,
+                                       double *im_out) {
     QSV_CHECK(s);
-    if (!out || nterms < 0 || (nterms > 0 && (!xmask || !zmask || !coeff)))
+    if (!re_out || !im_out || nterms < 0 || (nterms > 0 && (!xmask || !zmask || !coeff)))
         return fail(s, QSV_EINVAL, "bad argument");
     std::vector<uint64_t> x(nterms), z(nterms);
     for (int t = 0; t < nterms; ++t) {
@@ -1071,8 +1072,16 @@ qsv_status qsv_get_expectation(qsv_sim *s, int32_t nterms, const uint64_t *xmask
     }
     QSV_TRY(do_flush(s));
     QSV_TRY(materialize(s));
+    return expectation_positions(s, s->d_state, s->n, nterms, x.data(), z.data(), coeff, re_out,
+                                 im_out);
+}
+
+qsv_status qsv_get_expectation(qsv_sim *s, int32_t nterms, const uint64_t *xmask,
+                               const uint64_t *zmask, const double *coeff, double *out) {
+    QSV_CHECK(s);
+    if (!out) return fail(s, QSV_EINVAL, "bad argument");
     double im = 0.0;
-    return expectation_positions(s, s->d_state, s->n, nterms, x.data(), z.data(), coeff, out, &im);
+    return qsv_get_expectation_complex(s, nterms, xmask, zmask, coeff, out, &im);
 }
 
 qsv_status qsv_measure(qsv_sim *s, int32_t m, const int32_t *qubits, const double *u,

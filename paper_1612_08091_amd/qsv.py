@@ -98,6 +98,7 @@ _SIGS = {
     "qsv_get_probability": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "qsv_get_probabilities": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "qsv_get_expectation": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
+    "qsv_get_expectation_complex": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "qsv_measure": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "qsv_sample": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     "qsv_apply_kraus_sampled": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P,
@@ -299,6 +300,16 @@ class Simulator:
         _check(lib.qsv_get_expectation(self._h, len(c), _ptr(x), _ptr(z), _ptr(c),
                                        ctypes.byref(out)), self._h)
         return out.value
+
+    def get_expectation_complex(self, xmask, zmask, coeff):
+        """(Re, Im) of sum_t coeff[t] <P_t>; Im is zero up to rounding."""
+        x = np.ascontiguousarray(xmask, dtype=np.uint64)
+        z = np.ascontiguousarray(zmask, dtype=np.uint64)
+        c = np.ascontiguousarray(coeff, dtype=np.float64)
+        re, im = ctypes.c_double(), ctypes.c_double()
+        _check(lib.qsv_get_expectation_complex(self._h, len(c), _ptr(x), _ptr(z), _ptr(c),
+                                               ctypes.byref(re), ctypes.byref(im)), self._h)
+        return re.value, im.value
 
     def expectation(self, ham, qubit_ids: Optional[Sequence[int]] = None) -> float:
         """<H> for a workloads.PauliSum whose bit j refers to qubit_ids[j]

@@ -241,6 +241,11 @@ def test_expectation(dtype):
         tol = 1e-12 * max(1.0, np.sum(np.abs(ham.coeff))) if dtype == "c128" else \
             1e-5 * np.sum(np.abs(ham.coeff))
         assert abs(got - want) <= tol, (n, got, want)
+        # the sum is Hermitian: its imaginary part vanishes up to rounding
+        # (qubit id j is bit j here, so the masks go in unchanged)
+        re, im = s.get_expectation_complex(ham.xmask, ham.zmask, ham.coeff)
+        assert abs(re - got) <= 1e-13 * max(1.0, abs(got))
+        assert abs(im) <= tol, (n, im)
         s.close()
 
 
