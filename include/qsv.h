@@ -137,6 +137,14 @@ qsv_status qsv_qubits(const qsv_sim *sim, int32_t *n, int32_t *ids);
 qsv_status qsv_apply(qsv_sim *sim, const double *U, int32_t k, const int32_t *targets,
                      int32_t c, const int32_t *controls);
 
+/* Queue the diagonal gate diag(d[0], ..., d[2^k - 1]) on targets[k] under
+ * controls[c] (Sec. 4: Gate | qubits, with a Control block): d holds 2^k
+ * interleaved complex128 entries, bit j of the row index <-> targets[j].
+ * The same as qsv_apply with the diagonal matrix; diagonal gates take the
+ * kernels' diagonal paths either way.  EINVAL as qsv_apply, or d NULL. */
+qsv_status qsv_apply_diag(qsv_sim *sim, const double *d, int32_t k, const int32_t *targets,
+                          int32_t c, const int32_t *controls);
+
 /* Emulated math gate (Sec. 4.3.3: a BasicMathGate such as AddConstant applied
  * as the classical function it computes instead of its gate decomposition).
  * The register is qubits[0..w-1] (qubit ids, qubits[0] the least significant

@@ -760,6 +760,20 @@ qsv_status qsv_apply(qsv_sim *s, const double *U, int32_t k, const int32_t *targ
     return QSV_OK;
 }
 
+qsv_status qsv_apply_diag(qsv_sim *s, const double *d, int32_t k, const int32_t *targets,
+                          int32_t c, const int32_t *controls) {
+    QSV_CHECK(s);
+    if (!d) return fail(s, QSV_EINVAL, "NULL diagonal");
+    if (k < 1 || k > qsv::kMaxK) return fail(s, QSV_EINVAL, "k must be in 1..5");
+    const int D = 1 << k;
+    std::vector<double> U((size_t)D * D * 2, 0.0);
+    for (int r = 0; r < D; ++r) {
+        U[2 * ((size_t)r * D + r)] = d[2 * r];
+        U[2 * ((size_t)r * D + r) + 1] = d[2 * r + 1];
+    }
+    return qsv_apply(s, U.data(), k, targets, c, controls);
+}
+
 qsv_status qsv_flush(qsv_sim *s) {
     QSV_CHECK(s);
     return do_flush(s);

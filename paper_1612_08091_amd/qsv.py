@@ -88,6 +88,7 @@ _SIGS = {
     "qsv_deallocate": (ctypes.c_int, [_P, ctypes.c_int32]),
     "qsv_qubits": (ctypes.c_int, [_P, _P, _P]),
     "qsv_apply": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
+    "qsv_apply_diag": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
     "qsv_apply_math": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P]),
     "qsv_dm_apply": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
     "qsv_dm_apply_kraus": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
@@ -243,6 +244,17 @@ class Simulator:
         t = np.ascontiguousarray(list(targets) or [0], dtype=np.int32)
         c = np.ascontiguousarray(list(controls) or [0], dtype=np.int32)
         _check(lib.qsv_apply(self._h, _ptr(u), len(targets), _ptr(t), len(controls), _ptr(c)),
+               self._h)
+
+    def apply_diag(self, diag, targets: Sequence[int], controls: Sequence[int] = ()):
+        """Queue diag(diag[0], ..., diag[2^k - 1]) on ``targets`` (bit j of the
+        row index is targets[j]) under ``controls``."""
+        d = np.ascontiguousarray(diag, dtype=np.complex128)
+        t = np.ascontiguousarray(list(targets) or [0], dtype=np.int32)
+        c = np.ascontiguousarray(list(controls) or [0], dtype=np.int32)
+        if d.shape != (1 << len(targets),):
+            raise ValueError("diag must have 2**len(targets) entries")
+        _check(lib.qsv_apply_diag(self._h, _ptr(d), len(targets), _ptr(t), len(controls), _ptr(c)),
                self._h)
 
     def apply_math(self, qubits: Sequence[int], table, controls: Sequence[int] = ()):

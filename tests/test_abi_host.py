@@ -133,6 +133,27 @@ def test_reductions_validate_before_device():
     expect_status(1, s.get_amplitudes, [8])               # index >= 2^n
 
 
+def test_apply_diag_validation_and_plan():
+    s, ids = new_sim(3)
+    assert Q.lib.qsv_apply_diag(s._h, None, 1, Q._ptr(np.zeros(1, np.int32)), 0, None) == 1
+    d = np.exp(1j * np.array([0.1, 0.2, 0.3, 0.4]))
+    expect_status(1, s.apply_diag, d, [0, 0])            # repeated target
+    expect_status(1, s.apply_diag, d, [0, 7])            # unknown id
+    bad = d.copy()
+    bad[2] = np.nan
+    expect_status(1, s.apply_diag, bad, [0, 1])          # non-finite entry
+    s.apply_diag(d, [2, 0], [1])                         # queued as the diagonal matrix
+    ops, npass = s.plan()
+    assert len(ops) == 1
+    mat, targets, cmask = ops[0]
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal(8) + 1j * rng.standard_normal(8)
+    want = oracle.apply(psi.copy(), np.diag(d), [2, 0], [1])
+    controls = [p for p in range(64) if (cmask >> p) & 1]
+    got = oracle.apply(psi.copy(), mat, targets, controls)
+    assert np.max(np.abs(got - want)) <= 1e-15
+
+
 def test_sampled_channel_validates_before_device():
     s, ids = new_sim(3)
     ad = W.amplitude_damping(0.2)

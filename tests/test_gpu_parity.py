@@ -160,6 +160,32 @@ def test_diagonal_runs_tiled(dtype, n):
     s.close()
 
 
+@pytest.mark.parametrize("mode,k_max", [("pergate", 1), ("fused", 3), ("tiled", 2), ("tiled", 4)])
+def test_apply_diag_matches_oracle(mode, k_max):
+    n = 14
+    rng = np.random.default_rng(515 + k_max)
+    s = make(n, mode=mode, k_max=k_max)
+    psi = oracle.zero_state(n)
+    for q in range(n):
+        s.apply(W.H, [q])
+        oracle.apply(psi, W.H, [q])
+    for _ in range(60):
+        k = int(rng.integers(1, 4))
+        nc = int(rng.integers(0, 3))
+        qs = rng.permutation(n)[:k + nc].tolist()
+        d = np.exp(1j * rng.uniform(0, 6, size=1 << k))
+        s.apply_diag(d, qs[:k], qs[k:])
+        oracle.apply(psi, np.diag(d), qs[:k], qs[k:])
+        if rng.uniform() < 0.2:
+            q = int(rng.integers(0, n))
+            u = W.haar_2x2(rng)
+            s.apply(u, [q])
+            oracle.apply(psi, u, [q])
+    log("case apply_diag", mode, k_max)
+    check_c128(s.get_state(), psi)
+    s.close()
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_long_single_pass_scheduling(dtype):
     # 12 qubits fit one tile: 1200 gates become one pass of several hundred
