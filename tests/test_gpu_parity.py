@@ -143,6 +143,40 @@ def diag_circuit(rng, n, count):
     return c
 
 
+@pytest.mark.parametrize("mode,k_max,tile_bits", MODES)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_one_and_two_qubit_states(mode, k_max, tile_bits, dtype):
+    # states smaller than a tile, a register group and a wavefront: every
+    # mode clamps its tile to the state and still matches the oracle
+    for n in (1, 2):
+        rng = np.random.default_rng(700 + 10 * n + k_max + tile_bits)
+        circ = random_circuit(rng, n, 30)
+        log("case", mode, k_max, tile_bits, dtype, n)
+        s = make(n, mode=mode, k_max=k_max, tile_bits=tile_bits, dtype=dtype)
+        s.run(W.Circuit(n))
+        zero = np.zeros(1 << n, dtype=np.complex128)
+        zero[0] = 1.0
+        assert np.array_equal(s.get_state().astype(np.complex128), zero)
+        s.run(circ)
+        want = oracle.run(circ)
+        got = s.get_state()
+        if dtype == "c128":
+            check_c128(got, want)
+        else:
+            check_c64(got, want)
+        tol = 1e-13 if dtype == "c128" else 1e-6
+        for q in range(n):
+            assert abs(s.get_probability([q], [1]) - oracle.prob_bits(want, [q], [1])) <= tol
+        u = rng.random(200)
+        u[:2] = [0.0, np.nextafter(1.0, 0)]
+        if dtype == "c128":
+            check_samples(s.sample(u), oracle.sample(want, u), want, u)
+        else:
+            g = got.astype(np.complex128)
+            check_samples(s.sample(u), oracle.sample(g, u), g, u)
+        s.close()
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n", [13, 16])
 def test_diagonal_runs_tiled(dtype, n):
