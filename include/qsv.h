@@ -200,7 +200,9 @@ qsv_status qsv_dm_expectation(qsv_sim *sim, int32_t nterms, const uint64_t *xmas
                               const uint64_t *zmask, const double *coeff, double *out);
 
 /* Execute every queued gate (Sec. 4.1.3 eng.flush()): plan fusion and passes,
- * enqueue the kernels on the stream.  Asynchronous. */
+ * enqueue the kernels on the stream.  Asynchronous.  The state is allocated
+ * on first use: ENOMEM if the device cannot hold it, with the queue and the
+ * register left as they were (the handle can still be destroyed). */
 qsv_status qsv_flush(qsv_sim *sim);
 
 /* Wait for the stream; EDEVICE if any enqueued work failed. */

@@ -366,6 +366,25 @@ def test_teleportation(branch):
     s.close()
 
 
+def test_state_beyond_device_memory_fails_cleanly():
+    # 2^35 complex128 amplitudes (512 GiB) exceed one GPU's memory: the
+    # first flush, which allocates the state, reports ENOMEM, and the device
+    # stays usable for the next simulator
+    log("case", "35 qubits c128, flush -> ENOMEM")
+    s = make(35, dtype="c128")
+    s.apply(W.H, [0], [])
+    with pytest.raises(Q.QsvError) as ei:
+        s.flush()
+    assert ei.value.code == 2, str(ei.value)
+    s.close()
+    rng = np.random.default_rng(35)
+    circ = random_circuit(rng, 10, 40)
+    t = make(10)
+    t.run(circ)
+    check_c128(t.get_state(), oracle.run(circ))
+    t.close()
+
+
 def test_allocate_deallocate_sequence():
     rng = np.random.default_rng(14)
     s = Q.Simulator(n_max=12, use_torch_stream=False)
