@@ -87,3 +87,29 @@ def test_config3_subset_against_oracle_and_single_path():
     for i in pick:
         want = oracle.energy(circuits[i], hams[i])
         assert abs(got[i] - want) <= 1e-5 * np.sum(np.abs(hams[i].coeff)), i
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_tiny_and_empty_circuits(dtype):
+    from paper_1612_08091_amd import qsv as Q
+    # 1- and 2-qubit circuits (some with no gates at all), and a batch that
+    # holds a single circuit
+    rng = np.random.default_rng(47)
+    circuits, hams = [], []
+    for i in range(12):
+        n = 1 + i % 2
+        c = W.Circuit(n)
+        for _ in range(0 if i % 3 == 0 else 6):
+            c.add(W.haar_2x2(rng), (int(rng.integers(0, n)),))
+            if n == 2:
+                c.add(W.X, (1,), (0,))
+        circuits.append(c)
+        hams.append(W.random_pauli_dense(n, 4, rng))
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    for lo, hi in [(0, 12), (5, 6)]:
+        b = Q.Batch(circuits[lo:hi], hams[lo:hi], dtype=dtype, autotune=False)
+        got = b.run()
+        want = np.array([oracle.energy(c, h) for c, h in zip(circuits[lo:hi], hams[lo:hi])])
+        scale = np.array([np.sum(np.abs(h.coeff)) for h in hams[lo:hi]])
+        assert np.all(np.abs(got - want) <= tol * scale), np.max(np.abs(got - want) / scale)
+        b.close()
