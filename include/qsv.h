@@ -303,6 +303,21 @@ qsv_status qsv_reset_stats(qsv_sim *sim);
 qsv_status qsv_plan(qsv_sim *sim, int32_t *n_ops, int32_t *n_passes, int32_t max_ops,
                     int32_t *ks, int32_t *targets, uint64_t *ctrls, double *mats);
 
+/* Host-side check of the register-tile programs (the lowering behind the
+ * bulk execution of cached gates, Sec. 4.3.2), for tests: plans the queued
+ * gates as qsv_flush does in mode TILED, lowers every pass to the
+ * instruction list of the register-resident tile kernel, and runs those
+ * lists on the host over state[2 * 2^n] (complex128, interleaved, updated in
+ * place) thread by thread, with the kernel's layouts, LDS byte offsets and
+ * table lookups, every address bounds-checked.  state NULL: lower only (for
+ * the counts).  No device call; the queue is kept.  info[9] (may be NULL)
+ * receives: passes, register passes, real-split ops, table (diagonal) ops,
+ * layout changes, largest LDS image in bytes, instructions, diagonal ops
+ * merged into another, layout changes within each wave (no barrier).  EINVAL: not in mode TILED, or an address check
+ * failed (qsv_last_error names it); EUNSUPPORTED: a pass needs the LDS-tile
+ * kernel (an op wider than 2 qubits, or too many tables). */
+qsv_status qsv_check_tile_programs(qsv_sim *sim, double *state, int32_t *info);
+
 /* ----------------------------------------------------------------------- */
 /* Circuits with parameters, Pauli sums: flat arrays used by the adjoint      */
 /* gradient and by the batched form.                                          */
@@ -376,6 +391,15 @@ qsv_status qsv_batch_destroy(qsv_batch *b);
 const char *qsv_last_error(const qsv_sim *sim);
 
 const char *qsv_version(void);
+
+/* Bandwidth probe: enqueue a streaming copy of `bytes` (a multiple of 16)
+ * from device buffer src to device buffer dst on `stream` (a hipStream_t,
+ * NULL = null stream).  Every state pass reads and writes the state once, so
+ * this copy is the practical ceiling beside the HBM peak; timing it is the
+ * caller's (HIP events on the same stream).  The buffers are the caller's and
+ * must not overlap.  EINVAL: NULL buffer or bad size; EDEVICE: launch
+ * failed (qsv_last_error(NULL) says why). */
+qsv_status qsv_copy_probe(const void *src, void *dst, uint64_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -62,46 +62,73 @@ struct TileArgs {
     int32_t tile_pos_n;   // == m
     uint32_t tpos[40];    // tile positions, ascending (words: uniform indexed loads stay scalar)
     uint64_t n_tiles;
-    uint8_t reg_lbit[8];  // register kernel: initial layout, tile bit of register bit j
-    uint8_t thr_lbit[16]; //                  tile bit of thread-id bit i
     int32_t rb;           // register bits per thread (threads = 2^(m - rb))
     int32_t mfma_k;       // LDS kernel: widest matrix-core op of the pass (0 = none)
     int32_t no_diag;      // register kernel: 1 if the program has no ROP_DIAG op (a
                           // leaner kernel instance without that case runs it)
-    uint64_t g_reg[8];    // register kernel, initial layout: global index bit of register
-                          // bit j, and of thread-id bit i
+    uint32_t img_bytes;   // register kernel: bytes of the pass's LDS image (multiple of 16)
+    int64_t img_off;      // register kernel: byte offset of the LDS image in the pool
+    uint64_t g_reg[8];    // register kernel, layout at load time: global index bit of
+                          // register bit j, and of thread-id bit i
     uint64_t g_thr[16];
+    uint64_t g_reg_f[8];  // register kernel, layout at store time (after the last remap)
+    uint64_t g_thr_f[16];
     uint64_t dep_hi[64];  // LDS kernel: global offset of local index 256 * i (tile bits >= 8)
 };
 
 // One operation of the register-resident tile kernel.
-enum RegOpKind : int32_t { ROP_G1 = 0, ROP_G2 = 1, ROP_DIAG = 2, ROP_REMAP = 3, ROP_LDS = 4 };
-// Widest diagonal op of the register kernel (targets; its table of 2^k
-// factors is staged per wave in LDS).
+//   G1/G2: complex 1- or 2-qubit matrix on register bits.
+//   R1/R2: real 1- or 2-qubit matrix on register bits (a complex matrix that
+//          is real up to diagonal phases on either side; the phases become
+//          DIAG ops), half the arithmetic of G1/G2 per amplitude.
+//   DIAG:  per-amplitude factor from a table in the pass's LDS image.
+//   REMAP: layout change through the LDS half-tile buffer.
+enum RegOpKind : int32_t { ROP_G1 = 0, ROP_G2 = 1, ROP_DIAG = 2, ROP_REMAP = 3, ROP_R1 = 5, ROP_R2 = 6 };
+// Widest diagonal op of the register kernel (table bits; its table of 2^k
+// factors lives in the pass's LDS image).
 constexpr int kRegDiagMax = 8;
+// LDS-image bytes of a register pass (tables and per-lane words): the
+// lowering narrows the tables to stay within kRegImageSoft where it can; a
+// larger image lowers occupancy; past kRegImageMax the pass runs on the
+// LDS-tile kernel.
+constexpr uint32_t kRegImageSoft = 20480;
+constexpr uint32_t kRegImageMax = 65536;
 
+// The LDS image of a register pass holds the DIAG tables (each aligned to its
+// own size, in the state's complex type) and, for each REMAP, 32-bit words:
+// the buffer write offsets of the 64 lanes' thread-id bits, then their read
+// offsets.  The wave's part of the same offsets is uniform (wwave/rwave).
 struct RegOp {
     int32_t kind;
-    int32_t a;            // G1: register bit; G2: lower register bit (matrix bit 0);
-                          // DIAG: number of targets; LDS: index into the TileOp list
-    int32_t b;            // G2: higher register bit (matrix bit 1)
-    uint32_t pad0;
-    uint64_t ctrl;        // G1/G2/DIAG: control bits over the global index
-    int64_t mat;          // offset (complex entries of the tile dtype) into the pool
-    uint32_t gt[8];       // DIAG: global target positions (words: scalar loads)
-    uint8_t reg_lbit[8];  // REMAP: new layout
-    uint8_t thr_lbit[16];
-    // REMAP (a = register slot whose tile bit stays put): byte offsets into the
-    // half-tile LDS buffer.  The buffer address of an amplitude is a linear map
-    // (over GF(2)) of its local index, so it splits into a register part (per
-    // register, uniform) XOR a thread part (XOR of the parts of the set
-    // thread-id bits): wr/wthr in the old layout, rd/rthr in the new one.
-    uint32_t wr[32];
-    uint32_t rd[32];
-    uint32_t wthr[16];
-    uint32_t rthr[16];
-    uint64_t g_reg[8];    // new layout: global index bit of register bit j
-    uint64_t g_thr[16];   //             and of thread-id bit i
+    int32_t a;            // G1/R1: register bit; G2/R2: lower register bit (matrix bit 0);
+                          // REMAP: register slot whose tile bit stays put;
+                          // DIAG: number of table bits outside the tile
+    int32_t b;            // G2/R2: higher register bit (matrix bit 1); DIAG: byte offset
+                          // of a table of ones, read by tiles that fail `octrl`
+    uint32_t creg;        // G/R: register bits that are controls (mask over register index)
+    uint64_t octrl;       // controls outside the tile: the op runs on a tile only if its
+                          // base index has all these bits
+    uint64_t lane_ok;     // G/R: bit l set if lane l meets the controls on thread-id bits;
+                          // DIAG: bit t set if lane bit t (thread-id bit t < 6) is a
+                          // table bit, rd[t] then its place in the table byte offset
+    uint32_t wave_ok;     // G/R: bit w set if wave w meets them
+    uint32_t lane_off;    // REMAP: byte offset of the op's per-lane words in the image
+    int64_t mat;          // DIAG: byte offset of the factor table in the image
+    // G/R: the matrix, row-major over (bit 0 <-> a, bit 1 <-> b), inline so
+    // that one burst of scalar loads brings an op's fields and its matrix:
+    // R1 4 and R2 16 reals, G1 4 and G2 16 complex (re, im); in double for a
+    // complex128 state (md) and in float for complex64 (mf)
+    double md[32];
+    float mf[32];
+    uint32_t gt[8];       // DIAG: global positions of the table bits outside the tile
+    uint32_t gtb[8];      //       and their byte weights in the table
+    uint32_t wr[32];      // DIAG: table byte offset of register index i;
+                          // REMAP: buffer byte offset of register i in the old layout
+    uint32_t rd[32];      // REMAP: buffer byte offset of register i in the new layout;
+                          // DIAG: see lane_ok
+    uint32_t wwave[8];    // DIAG: table byte offset of the wave's thread-id bits;
+                          // REMAP: write offset of the wave's thread-id bits
+    uint32_t rwave[8];    // REMAP: read offset of the wave's thread-id bits
 };
 
 // ------------------------------------------------------------------ gates
@@ -119,6 +146,10 @@ hipError_t launch_tile_reg(int dtype, void *psi, const TileArgs &ta, const RegOp
                            const void *pool, unsigned int *counter, hipStream_t s);
 int tile_pass_max_bits(int dtype);
 int tile_reg_bits(int dtype);     // default register bits per thread
+
+// Streaming copy of `bytes` (a multiple of 16) from src to dst (the
+// bandwidth probe).
+hipError_t copy_probe(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 
 // ------------------------------------------------------------ state ops
 hipError_t fill_basis0(int dtype, void *psi, uint64_t dim, hipStream_t s);

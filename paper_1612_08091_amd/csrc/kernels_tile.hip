@@ -6,12 +6,15 @@
 // 4.3.2 executed in bulk).
 //
 // Two kernels:
-//  * k_tile_reg<R, RB>: m = RB + 8.  Each of the 256 threads keeps 2^RB
-//    amplitudes in registers.  Register bit j and thread bit i each stand for
-//    one tile bit (the layout).  1- and 2-qubit dense operations on register
-//    bits run in registers; diagonal operations on any bits use the global
-//    index of each amplitude; a REMAP op moves the tile through LDS (XOR
-//    swizzled against bank conflicts) into a new layout.  Passes holding
+//  * k_tile_reg<R, RB, TB>: m = RB + TB.  Each of the 2^TB threads keeps
+//    2^RB amplitudes in registers.  Register bit j and thread bit i each
+//    stand for one tile bit (the layout).  1- and 2-qubit operations on
+//    register bits run in registers, as complex matrices or, when the host
+//    split them into phases times a real matrix, as real matrices at half the
+//    arithmetic; diagonal operations multiply by factors from tables that the
+//    workgroup keeps in LDS; a REMAP op moves the tile through LDS (XOR
+//    swizzled against bank conflicts) into a new layout.  Every
+//    layout-dependent offset comes precomputed from the host.  Passes holding
 //    wider operations use k_tile_lds.
 //  * k_tile_lds<R>: any m <= 14; the tile lives in LDS and every operation
 //    sweeps it (used for small states).
@@ -103,45 +106,51 @@ __global__ __launch_bounds__(kNT) void k_tile_lds(typename VT<R>::T *__restrict_
 }
 
 // ------------------------------------------------------- k_tile_reg
-template <typename T, int NR, int RB>
-__device__ __forceinline__ uint64_t greg(int i, const uint64_t *gbit) {
-    uint64_t g = 0;
-#pragma unroll
-    for (int j = 0; j < RB; ++j)
-        if ((i >> j) & 1) g |= gbit[j];
-    return g;
-}
+__device__ __forceinline__ double rfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float rfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-template <typename T, int NR, int RB, int J, bool CTRL>
-__device__ __forceinline__ void reg_g1(T *amp, const T *__restrict__ U, uint64_t gb,
-                                       const uint64_t *gbit, uint64_t ctrl) {
-    const T u00 = U[0], u01 = U[1], u10 = U[2], u11 = U[3];
+// Register ops run in place, one group of 2 or 4 amplitudes at a time, and
+// never skip: an op under controls (CTRL) computes every group and keeps the
+// old value where the controls fail, so the register allocation of the
+// uncontrolled path holds no copies for a skipped case.  `on` is the lane's
+// share of the controls (thread-id bits, bits outside the tile); creg holds
+// the register bits that are controls.  Matrices arrive in scalar registers
+// (m: the op's inline coefficients, row-major; complex ones as re, im).
+template <typename T, typename R, int NR, int J, bool CTRL>
+__device__ __forceinline__ void reg_g1(T *amp, const R *m, bool on, uint32_t creg) {
+    T u[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        u[e].x = m[2 * e];
+        u[e].y = m[2 * e + 1];
+    }
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         if (i & (1 << J)) continue;
         const int i1 = i | (1 << J);
         const T a = amp[i], b = amp[i1];
-        T na = cmul(u00, a);
-        na = cmadd(na, u01, b);
-        T nb = cmul(u10, a);
-        nb = cmadd(nb, u11, b);
+        T na = cmul(u[0], a);
+        na = cmadd(na, u[1], b);
+        T nb = cmul(u[2], a);
+        nb = cmadd(nb, u[3], b);
         if (CTRL) {
-            const bool c = ((gb | greg<T, NR, RB>(i, gbit)) & ctrl) == ctrl;
-            amp[i] = csel(c, na, a);
-            amp[i1] = csel(c, nb, b);
-        } else {
-            amp[i] = na;
-            amp[i1] = nb;
+            const bool c = on && ((i & creg) == creg);
+            na = csel(c, na, a);
+            nb = csel(c, nb, b);
         }
+        amp[i] = na;
+        amp[i1] = nb;
     }
 }
 
-template <typename T, int NR, int RB, int J1, int J2, bool CTRL>
-__device__ __forceinline__ void reg_g2(T *amp, const T *__restrict__ U, uint64_t gb,
-                                       const uint64_t *gbit, uint64_t ctrl) {
+template <typename T, typename R, int NR, int J1, int J2, bool CTRL>
+__device__ __forceinline__ void reg_g2(T *amp, const R *m, bool on, uint32_t creg) {
     T u[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) u[e] = U[e];
+    for (int e = 0; e < 16; ++e) {
+        u[e].x = m[2 * e];
+        u[e].y = m[2 * e + 1];
+    }
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         if (i & ((1 << J1) | (1 << J2))) continue;
@@ -149,8 +158,7 @@ __device__ __forceinline__ void reg_g2(T *amp, const T *__restrict__ U, uint64_t
         T x[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) x[c] = amp[idx[c]];
-        bool c = true;
-        if (CTRL) c = ((gb | greg<T, NR, RB>(i, gbit)) & ctrl) == ctrl;
+        const bool c = !CTRL || (on && ((i & creg) == creg));
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             T y = cmul(u[r * 4], x[0]);
@@ -161,41 +169,91 @@ __device__ __forceinline__ void reg_g2(T *amp, const T *__restrict__ U, uint64_t
     }
 }
 
-// Diagonal op: amplitude i of the thread takes the factor val[r], where the
-// row index r = r_thr ^ op.wr[i] splits into the bits of the targets that
-// are not register bits (read once per thread from its global base gb;
-// op.pad0 marks them) and the bits from the register index (op.wr[i],
-// precomputed on the host for the current layout).  Controls that are not
-// register bits are in op.ctrl; those that are, as register-index bits, in
-// op.b.  The wave first copies the op's 2^k factors into its own LDS table
-// `tab` (every lane takes part, before any lane leaves on its controls), so
-// the 16 gathers per thread are LDS reads instead of vector-memory reads
-// that compete with the tile loads.  LDS operations of one wave are
-// performed in order, so the reads see the copy and the next op's copy
-// comes after these reads.
-template <typename T, int NR, int RB>
-__device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const T *__restrict__ pool,
-                                         uint64_t gb, T *tab) {
-    const int k = op.a;
-    const uint32_t lane = threadIdx.x & 63u;
-    const T *val = pool + op.mat;
-    for (uint32_t e = lane; e < (1u << k); e += 64) tab[e] = val[e];
-    __builtin_amdgcn_wave_barrier();
-    if ((gb & op.ctrl) != op.ctrl) return;
-    const uint32_t thr_targets = op.pad0;
-    uint32_t rt = 0;
-    for (int q = 0; q < k; ++q)
-        if ((thr_targets >> q) & 1u) rt |= (uint32_t)((gb >> op.gt[q]) & 1u) << q;
-    const int creg = op.b;
-    // rows outside the register controls take the factor 1
+// Real matrices: the real and imaginary parts of the amplitudes transform
+// separately, 2 (1-qubit) or 4 (2-qubit) multiply-adds per part.
+template <typename T, typename R, int NR, int J, bool CTRL>
+__device__ __forceinline__ void reg_r1(T *amp, const R *m, bool on, uint32_t creg) {
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        const T v = tab[rt ^ op.wr[i]];
-        const bool on = (i & creg) == creg;
-        T f;
-        f.x = on ? v.x : decltype(v.x)(1);
-        f.y = on ? v.y : decltype(v.y)(0);
-        amp[i] = cmul(f, amp[i]);
+        if (i & (1 << J)) continue;
+        const int i1 = i | (1 << J);
+        const T a = amp[i], b = amp[i1];
+        T na, nb;
+        na.x = rfma(m[1], b.x, m[0] * a.x);
+        na.y = rfma(m[1], b.y, m[0] * a.y);
+        nb.x = rfma(m[3], b.x, m[2] * a.x);
+        nb.y = rfma(m[3], b.y, m[2] * a.y);
+        if (CTRL) {
+            const bool c = on && ((i & creg) == creg);
+            na = csel(c, na, a);
+            nb = csel(c, nb, b);
+        }
+        amp[i] = na;
+        amp[i1] = nb;
+    }
+}
+
+template <typename T, typename R, int NR, int J1, int J2, bool CTRL>
+__device__ __forceinline__ void reg_r2(T *amp, const R *m, bool on, uint32_t creg) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i & ((1 << J1) | (1 << J2))) continue;
+        const int idx[4] = {i, i | (1 << J1), i | (1 << J2), i | (1 << J1) | (1 << J2)};
+        T x[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[c] = amp[idx[c]];
+        const bool c = !CTRL || (on && ((i & creg) == creg));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            T y;
+            y.x = m[r * 4] * x[0].x;
+            y.y = m[r * 4] * x[0].y;
+#pragma unroll
+            for (int cc = 1; cc < 4; ++cc) {
+                y.x = rfma(m[r * 4 + cc], x[cc].x, y.x);
+                y.y = rfma(m[r * 4 + cc], x[cc].y, y.y);
+            }
+            amp[idx[r]] = CTRL ? csel(c, y, x[r]) : y;
+        }
+    }
+}
+
+// Diagonal op: amplitude i of the thread takes the factor at byte offset
+// (lane part ^ wave part ^ tile part ^ wr[i]) of the op's table in the LDS
+// image; the lane part places the lane's table bits (a bit-field extract and
+// a shift per lane bit).  The four parts come from disjoint table bits (lane
+// and wave thread-id bits, bits outside the tile, register bits), so the XOR
+// is their sum; the table sits at a multiple of its size, so the offset
+// never leaves it.  Controls inside the tile are table bits; a tile that
+// fails the controls outside it reads a table of ones (at byte offset b)
+// rather than skipping the op.  The reads go out four at a time.
+template <typename T, int NR>
+__device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const unsigned char *limg,
+                                         uint64_t base, uint32_t lane, uint32_t wave) {
+    uint32_t wr[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) wr[i] = op.wr[i];
+    uint32_t sh[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) sh[t] = op.rd[t];
+    const uint64_t lmask = op.lane_ok;
+    uint32_t s_idx = (uint32_t)op.mat;
+    if ((base & op.octrl) != op.octrl) s_idx = (uint32_t)op.b;
+    s_idx ^= op.wwave[wave];
+    for (int q = 0; q < op.a; ++q)
+        if ((base >> op.gt[q]) & 1) s_idx ^= op.gtb[q];
+    uint32_t v_idx = s_idx;
+#pragma unroll
+    for (int t = 0; t < 6; ++t)
+        v_idx |= __builtin_amdgcn_ubfe(lane, (uint32_t)t, (uint32_t)((lmask >> t) & 1u)) << sh[t];
+#pragma unroll
+    for (int i0 = 0; i0 < NR; i0 += 4) {
+        T f[4];
+#pragma unroll
+        for (int i = 0; i < 4 && i0 + i < NR; ++i)
+            f[i] = *reinterpret_cast<const T *>(limg + (v_idx ^ wr[i0 + i]));
+#pragma unroll
+        for (int i = 0; i < 4 && i0 + i < NR; ++i) amp[i0 + i] = cmul(f[i], amp[i0 + i]);
     }
 }
 
@@ -204,135 +262,220 @@ __device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const T *__res
 // In phase p every thread writes its registers whose slot-J bit is p, then
 // reads the same register indices in the new layout, so no register is
 // overwritten before it was written out.  Addresses are the thread part XOR
-// the (uniform) register part, both precomputed on the host.
+// the (uniform) register part, both precomputed on the host; the register
+// parts come in scalar registers, loaded before the first barrier.
+// Ordering of LDS accesses within one wave: the wave's LDS operations run in
+// order, so only the compiler has to be kept from moving them across.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// mode 1: a wave-local remap (each wave on its own region of the buffer, no
+// workgroup barrier); 0: a workgroup remap; 2: a workgroup remap that first
+// waits for every wave to leave its region of an earlier wave-local one.
 template <typename T, int NR, int J>
 __device__ __forceinline__ void remap_half(T *amp, unsigned char *lds, uint32_t wt, uint32_t rt,
-                                           const RegOp &op) {
+                                           const uint32_t *wr, const uint32_t *rd, int mode) {
+    if (mode == 2) __syncthreads();
+    // the thread parts pass through an empty asm in each phase, so the
+    // addresses are formed next to their accesses (not all hoisted above the
+    // barriers, which would hold 2^RB more VGPRs)
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
+        uint32_t w = wt;
+        asm volatile("" : "+v"(w));
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             if (((i >> J) & 1) != p) continue;
-            *reinterpret_cast<T *>(lds + (wt ^ op.wr[i])) = amp[i];
+            *reinterpret_cast<T *>(lds + (w ^ wr[i])) = amp[i];
         }
-        __syncthreads();
+        if (mode == 1) wave_sync();
+        else __syncthreads();
+        uint32_t r = rt;
+        asm volatile("" : "+v"(r));
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             if (((i >> J) & 1) != p) continue;
-            amp[i] = *reinterpret_cast<const T *>(lds + (rt ^ op.rd[i]));
+            amp[i] = *reinterpret_cast<const T *>(lds + (r ^ rd[i]));
         }
-        __syncthreads();
+        if (mode == 1) wave_sync();
+        else __syncthreads();
     }
 }
 
-template <typename T, int NR, int RB, bool CTRL>
-__device__ __forceinline__ void dispatch_g1(T *amp, int j, const T *U, uint64_t gb,
-                                            const uint64_t *gbit, uint64_t ctrl) {
-    switch (j) {
-    case 0: reg_g1<T, NR, RB, 0, CTRL>(amp, U, gb, gbit, ctrl); break;
-    case 1: reg_g1<T, NR, RB, 1, CTRL>(amp, U, gb, gbit, ctrl); break;
-    case 2: reg_g1<T, NR, RB, 2, CTRL>(amp, U, gb, gbit, ctrl); break;
-    case 3:
-        if constexpr (RB > 3) reg_g1<T, NR, RB, 3, CTRL>(amp, U, gb, gbit, ctrl);
-        else __builtin_unreachable();
-        break;
-    case 4:
-        if constexpr (RB > 4) reg_g1<T, NR, RB, 4, CTRL>(amp, U, gb, gbit, ctrl);
-        else __builtin_unreachable();
-        break;
-    default: __builtin_unreachable();   // the host emits only valid slots
-    }
-}
+template <typename R> __device__ __forceinline__ const R *op_mat(const RegOp &op);
+template <> __device__ __forceinline__ const double *op_mat<double>(const RegOp &op) { return op.md; }
+template <> __device__ __forceinline__ const float *op_mat<float>(const RegOp &op) { return op.mf; }
 
-template <typename T, int NR, int RB, bool CTRL>
-__device__ __forceinline__ void dispatch_g2(T *amp, int a, int b, const T *U, uint64_t gb,
-                                            const uint64_t *gbit, uint64_t ctrl) {
-#define QSV_G2(A, B) \
-    case (A) * 8 + (B): reg_g2<T, NR, RB, A, B, CTRL>(amp, U, gb, gbit, ctrl); break;
-    switch (a * 8 + b) {
-        QSV_G2(0, 1) QSV_G2(0, 2) QSV_G2(1, 2)
-    default:
-        if constexpr (RB == 4) {
-            switch (a * 8 + b) {
-                QSV_G2(0, 3) QSV_G2(1, 3) QSV_G2(2, 3)
-            default: __builtin_unreachable();
-            }
-        } else if constexpr (RB == 5) {
-            switch (a * 8 + b) {
-                QSV_G2(0, 3) QSV_G2(1, 3) QSV_G2(2, 3) QSV_G2(0, 4) QSV_G2(1, 4) QSV_G2(2, 4)
-                QSV_G2(3, 4)
-            default: __builtin_unreachable();
-            }
-        } else {
-            __builtin_unreachable();
+#define QSV_SLOT1(J, CALL)                                        \
+    case J:                                                       \
+        if constexpr (RB > J) { CALL; } else __builtin_unreachable(); \
+        break;
+
+template <typename T, typename R, int NR, int RB, bool CTRL>
+__device__ __forceinline__ void dispatch_1(T *amp, int kind, int j, const R *m, bool on,
+                                           uint32_t creg) {
+    if (kind == ROP_R1) {
+        switch (j) {
+            QSV_SLOT1(0, (reg_r1<T, R, NR, 0, CTRL>(amp, m, on, creg)))
+            QSV_SLOT1(1, (reg_r1<T, R, NR, 1, CTRL>(amp, m, on, creg)))
+            QSV_SLOT1(2, (reg_r1<T, R, NR, 2, CTRL>(amp, m, on, creg)))
+            QSV_SLOT1(3, (reg_r1<T, R, NR, 3, CTRL>(amp, m, on, creg)))
+            QSV_SLOT1(4, (reg_r1<T, R, NR, 4, CTRL>(amp, m, on, creg)))
+        default: __builtin_unreachable();
         }
-        break;
-    }
-#undef QSV_G2
-}
-
-// One operation of a register program on the thread's amplitudes.
-template <typename T, int NR, int RB, int TB, bool DG>
-__device__ __forceinline__ void reg_op(T *amp, const RegOp &op, const T *__restrict__ pool,
-                                       unsigned char *lds, T *dtab, uint64_t base, uint64_t &gthr,
-                                       uint64_t *gbit, uint32_t tid) {
-    const int kind = op.kind;
-    const uint64_t gb = base | gthr;
-    if (kind == ROP_G1) {
-        const T *U = pool + op.mat;
-        if (op.ctrl) dispatch_g1<T, NR, RB, true>(amp, op.a, U, gb, gbit, op.ctrl);
-        else dispatch_g1<T, NR, RB, false>(amp, op.a, U, gb, gbit, 0);
-    } else if (kind == ROP_G2) {
-        const T *U = pool + op.mat;
-        if (op.ctrl) dispatch_g2<T, NR, RB, true>(amp, op.a, op.b, U, gb, gbit, op.ctrl);
-        else dispatch_g2<T, NR, RB, false>(amp, op.a, op.b, U, gb, gbit, 0);
-    } else if (kind == ROP_DIAG) {
-        if constexpr (DG) reg_diag<T, NR, RB>(amp, op, pool, gb, dtab);
-        else __builtin_unreachable();
     } else {
-        // thread parts from the thread-id bits; the empty asm makes the id
-        // opaque so the per-bit masks are not kept live across the op loop
-        uint32_t tr = tid;
-        asm volatile("" : "+v"(tr));
-        uint32_t wt = 0, rt = 0;
-        uint64_t gthr_n = 0;
-#pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            const uint32_t msk = 0u - ((tr >> t) & 1u);
-            wt ^= msk & op.wthr[t];
-            rt ^= msk & op.rthr[t];
-            gthr_n |= (((uint64_t)msk << 32) | msk) & op.g_thr[t];
+        switch (j) {
+            QSV_SLOT1(0, (reg_g1<T, R, NR, 0, CTRL>(amp, m, on, creg)))
+            QSV_SLOT1(1, (reg_g1<T, R, NR, 1, CTRL>(amp, m, on, creg)))
+            QSV_SLOT1(2, (reg_g1<T, R, NR, 2, CTRL>(amp, m, on, creg)))
+            QSV_SLOT1(3, (reg_g1<T, R, NR, 3, CTRL>(amp, m, on, creg)))
+            QSV_SLOT1(4, (reg_g1<T, R, NR, 4, CTRL>(amp, m, on, creg)))
+        default: __builtin_unreachable();
         }
+    }
+}
+
+// m16: the first 16 coefficients (all of a real 2-qubit matrix); a complex
+// 2-qubit matrix reads its other 16 from the op.
+template <typename T, typename R, int NR, int RB, bool CTRL>
+__device__ __forceinline__ void dispatch_2(T *amp, int kind, int a, int b, const R *m16,
+                                           const RegOp &op, bool on, uint32_t creg) {
+#define QSV_PAIR(A, B)                                                                   \
+    case (A) * 8 + (B):                                                                  \
+        if constexpr (RB > (B)) {                                                        \
+            if (kind == ROP_R2) {                                                        \
+                reg_r2<T, R, NR, A, B, CTRL>(amp, m16, on, creg);                        \
+            } else {                                                                     \
+                R m32[32];                                                               \
+                const R *src = op_mat<R>(op);                                            \
+                _Pragma("unroll") for (int e = 0; e < 16; ++e) m32[e] = m16[e];          \
+                _Pragma("unroll") for (int e = 16; e < 32; ++e) m32[e] = src[e];         \
+                reg_g2<T, R, NR, A, B, CTRL>(amp, m32, on, creg);                        \
+            }                                                                            \
+        } else {                                                                         \
+            __builtin_unreachable();                                                     \
+        }                                                                                \
+        break;
+    switch (a * 8 + b) {
+        QSV_PAIR(0, 1) QSV_PAIR(0, 2) QSV_PAIR(1, 2) QSV_PAIR(0, 3) QSV_PAIR(1, 3) QSV_PAIR(2, 3)
+        QSV_PAIR(0, 4) QSV_PAIR(1, 4) QSV_PAIR(2, 4) QSV_PAIR(3, 4)
+    default: __builtin_unreachable();   // the host emits only valid slot pairs
+    }
+#undef QSV_PAIR
+}
+
+// One operation of a register program on the thread's amplitudes.  Every
+// case writes every amplitude (no skipped op or group), see reg_g1.  The
+// fields every op kind may need and the first 16 matrix coefficients are
+// read up front, so their scalar loads go out in one burst and the op waits
+// once instead of once per dependent field.
+template <typename T, typename R, int NR, int RB, bool DG>
+__device__ __forceinline__ void reg_op(T *amp, const RegOp &op, unsigned char *lds,
+                                       const unsigned char *limg, uint64_t base, uint32_t lane,
+                                       uint32_t wave) {
+    const int kind = op.kind;
+    const int a = op.a, b = op.b;
+    const uint32_t creg = op.creg;
+    const uint64_t octrl = op.octrl, lane_ok = op.lane_ok;
+    const uint32_t wave_ok = op.wave_ok;
+    const R *mp = op_mat<R>(op);
+    R m16[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) m16[e] = mp[e];
+    if (kind == ROP_REMAP) {
+        uint32_t wr[NR], rd[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            wr[i] = op.wr[i];
+            rd[i] = op.rd[i];
+        }
+        const uint32_t *lw = reinterpret_cast<const uint32_t *>(limg + op.lane_off);
+        const uint32_t wt = lw[lane] ^ op.wwave[wave];
+        const uint32_t rt = lw[64 + lane] ^ op.rwave[wave];
         // raised priority through the remap (LDS round trips and barriers
         // that the whole workgroup waits on), as for the tile's stores and
         // loads
         __builtin_amdgcn_s_setprio(2);
-        switch (op.a) {
-        case 0: remap_half<T, NR, 0>(amp, lds, wt, rt, op); break;
-        case 1: remap_half<T, NR, 1>(amp, lds, wt, rt, op); break;
-        case 2: remap_half<T, NR, 2>(amp, lds, wt, rt, op); break;
-        case 3:
-            if constexpr (RB > 3) remap_half<T, NR, 3>(amp, lds, wt, rt, op);
-            else __builtin_unreachable();
-            break;
-        case 4:
-            if constexpr (RB > 4) remap_half<T, NR, 4>(amp, lds, wt, rt, op);
-            else __builtin_unreachable();
-            break;
+        switch (a) {
+            QSV_SLOT1(0, (remap_half<T, NR, 0>(amp, lds, wt, rt, wr, rd, b)))
+            QSV_SLOT1(1, (remap_half<T, NR, 1>(amp, lds, wt, rt, wr, rd, b)))
+            QSV_SLOT1(2, (remap_half<T, NR, 2>(amp, lds, wt, rt, wr, rd, b)))
+            QSV_SLOT1(3, (remap_half<T, NR, 3>(amp, lds, wt, rt, wr, rd, b)))
+            QSV_SLOT1(4, (remap_half<T, NR, 4>(amp, lds, wt, rt, wr, rd, b)))
         default: __builtin_unreachable();
         }
         __builtin_amdgcn_s_setprio(0);
+    } else if (kind == ROP_DIAG) {
+        if constexpr (DG) reg_diag<T, NR>(amp, op, limg, base, lane, wave);
+        else __builtin_unreachable();
+    } else if (creg == 0 && octrl == 0 && lane_ok == ~0ull && wave_ok == ~0u) {
+        if (kind == ROP_G2 || kind == ROP_R2)
+            dispatch_2<T, R, NR, RB, false>(amp, kind, a, b, m16, op, true, 0);
+        else
+            dispatch_1<T, R, NR, RB, false>(amp, kind, a, m16, true, 0);
+    } else {
+        // controls outside the tile (uniform), on thread-id bits (lane and
+        // wave masks) and on register bits (creg)
+        const bool on = ((base & octrl) == octrl) && ((wave_ok >> wave) & 1u) &&
+                        ((lane_ok >> lane) & 1ull);
+        if (kind == ROP_G2 || kind == ROP_R2)
+            dispatch_2<T, R, NR, RB, true>(amp, kind, a, b, m16, op, on, creg);
+        else
+            dispatch_1<T, R, NR, RB, true>(amp, kind, a, m16, on, creg);
+    }
+}
+#undef QSV_SLOT1
+
+// Global index of the first amplitude of tile t: a 0 bit inserted at every
+// tile position (opaque positions: their masks are not hoisted out of the
+// tile loop into 2m spilled 64-bit values).
+template <int M>
+__device__ __forceinline__ uint64_t tile_base(uint32_t t, const TileArgs &ta) {
+    uint64_t base = t;
 #pragma unroll
-        for (int j = 0; j < RB; ++j) gbit[j] = op.g_reg[j];
-        gthr = gthr_n;
+    for (int i = 0; i < M; ++i) {
+        uint32_t tp = ta.tpos[i];
+        asm volatile("" : "+s"(tp));
+        const uint64_t lowm = (1ull << tp) - 1;
+        base = ((base & ~lowm) << 1) | (base & lowm);
+    }
+    return base;
+}
+
+// Issue the loads of tile t in the load layout (this thread's part gl of the
+// index).  The empty asms keep the per-register addresses and offsets from
+// being hoisted out of the tile loop (as 2^RB 64-bit values they would
+// spill); the offsets are a few scalar ORs per tile.
+template <typename T, int RB, int M>
+__device__ __forceinline__ void load_tile(T *dst, const T *__restrict__ psi, uint64_t gl,
+                                          uint32_t t, const TileArgs &ta) {
+    const uint64_t base = tile_base<M>(t, ta);
+    const T *lp = psi + gl;
+    asm volatile("" : "+v"(lp));
+    lp += base;
+    uint64_t gr[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+        gr[j] = ta.g_reg[j];
+        asm volatile("" : "+s"(gr[j]));
+    }
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i) {
+        uint64_t g = 0;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+            if ((i >> j) & 1) g |= gr[j];
+        dst[i] = lp[g];
     }
 }
 
-// Persistent: a grid of resident workgroups takes tiles from an atomic
-// counter (one per pass, zeroed by the host upload), so a compute unit or XCD
-// that runs slower simply processes fewer tiles and no dispatch gaps open up
-// between tiles.  Every workgroup leaves once the counter has passed the tile
-// count.
+// Persistent: a grid of resident workgroups takes tiles from a per-pass
+// counter that the host zeroes, in chunks (see below).  Dynamic LDS: the half-tile remap buffer (a workgroup remap uses all of it,
+// a wave-local one its wave's share), then the pass's image (tables and
+// per-lane words), copied in once per workgroup.
 // DG: the instance with the diagonal-op case; programs without one run on
 // the instance without it, whose register allocation the case does not
 // burden.
@@ -344,69 +487,88 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
     using T = typename VT<R>::T;
     constexpr int NR = 1 << RB;
     constexpr int m = RB + TB;
-    // half a tile for the two-phase remaps (static, so addresses need no base)
-    __shared__ T half_tile[1 << (m - 1)];
-    __shared__ unsigned int s_tile;
-    // one table of diagonal factors (at most 2^kRegDiagMax) per wave
-    constexpr int kTab = 1 << kRegDiagMax;
-    __shared__ T diag_tab[DG ? ((1 << TB) >> 6) * kTab : 1];
-    unsigned char *lds = reinterpret_cast<unsigned char *>(half_tile);
+    constexpr uint32_t kHalf = (uint32_t)sizeof(T) << (m - 1);
+    extern __shared__ __align__(16) unsigned char smem_reg[];
+    unsigned char *lds = smem_reg;
+    unsigned char *limg = smem_reg + kHalf;
     const uint32_t tid = threadIdx.x;
-    T *dtab = diag_tab + (DG ? (tid >> 6) * kTab : 0);
-    // layout at load time (the same for every tile): global index bit of each
-    // register bit (uniform) and the global bits of this thread
-    uint64_t gbit0[RB];
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(
+            reinterpret_cast<const unsigned char *>(pool) + ta.img_off);
+        uint4 *dst = reinterpret_cast<uint4 *>(limg);
+        for (uint32_t e = tid; e < (ta.img_bytes >> 4); e += (1u << TB)) dst[e] = src[e];
+    }
+    // this thread's part of the global index in the load and the store layout
+    uint64_t gl = 0, gs = 0;
 #pragma unroll
-    for (int j = 0; j < RB; ++j) gbit0[j] = ta.g_reg[j];
-    uint64_t gthr0 = 0;
-#pragma unroll
-    for (int t = 0; t < TB; ++t) gthr0 |= (0ull - ((tid >> t) & 1u)) & ta.g_thr[t];
+    for (int t = 0; t < TB; ++t) {
+        const uint64_t on = 0ull - (uint64_t)((tid >> t) & 1u);
+        gl |= on & ta.g_thr[t];
+        gs |= on & ta.g_thr_f[t];
+    }
     const uint32_t n_tiles = (uint32_t)ta.n_tiles;
 
-    if (tid == 0) s_tile = atomicAdd(counter, 1u);
-    __syncthreads();
-    uint32_t tile = __builtin_amdgcn_readfirstlane(s_tile);
-    while (tile < n_tiles) {
-        uint64_t base = tile;
-#pragma unroll
-        for (int i = 0; i < m; ++i) {
-            const uint64_t lowm = (1ull << ta.tpos[i]) - 1;
-            base = ((base & ~lowm) << 1) | (base & lowm);
+    // Tiles are claimed kChunk at a time from the pass's counter: a compute
+    // unit or XCD that runs slower takes fewer chunks, and the claim is
+    // broadcast through two alternating LDS slots, so one workgroup barrier
+    // per chunk suffices (the slot a claim overwrites was read before the
+    // barrier of the chunk in between).  Otherwise the waves of a workgroup
+    // meet only at its workgroup remaps.  One tile per claim: the tiles in
+    // flight across the device are then consecutive, so the 128-byte runs
+    // they share a DRAM page with are fetched close together in time
+    // (measured: larger chunks lose a few per cent).
+    constexpr uint32_t kChunk = 1;
+    __shared__ uint32_t s_claim[2];
+    if (tid == 0) s_claim[0] = atomicAdd(counter, kChunk);
+    uint32_t slot = 0;
+    uint32_t tile = 0, left = 0;
+    for (;;) {
+        if (left == 0) {
+            __syncthreads();   // the claim (and, the first time, the image) is in LDS
+            tile = __builtin_amdgcn_readfirstlane(s_claim[slot]);
+            if (tile >= n_tiles) break;
+            left = std::min(kChunk, n_tiles - tile);
+            slot ^= 1u;
+            if (tid == 0) s_claim[slot] = atomicAdd(counter, kChunk);
         }
-        // the empty asm keeps the per-register load addresses from being
-        // hoisted out of the tile loop (32 VGPRs held for its whole life)
-        uint64_t gthr = gthr0;
-        asm volatile("" : "+v"(gthr));
         T amp[NR];
-#pragma unroll
-        for (int i = 0; i < NR; ++i) amp[i] = psi[base | gthr | greg<T, NR, RB>(i, gbit0)];
-        // claim the next tile now; the atomic's latency hides behind the ops
-        unsigned int next = 0;
-        if (tid == 0) next = atomicAdd(counter, 1u);
+        load_tile<T, RB, m>(amp, psi, gl, tile, ta);
+        const uint64_t base = tile_base<m>(tile, ta);
         // back to normal priority for the arithmetic (raised before the
         // stores below: a wave that stores one tile and issues the next
         // tile's loads goes ahead of the other waves' FMAs, so the memory
         // requests of the compute units go out sooner)
         __builtin_amdgcn_s_setprio(0);
-        uint64_t gbit[RB];
-#pragma unroll
-        for (int j = 0; j < RB; ++j) gbit[j] = gbit0[j];
-        // Two ops per iteration (the host pads the program to an even length
-        // with an identity 1-qubit op): the amplitudes then alternate between
-        // two register sets without copies at the loop back edge.  Op fields
-        // are read through references into the uniform op array so they stay
-        // scalar.
+        // Two ops per iteration (the host pads the program to an even
+        // length): the amplitudes then alternate between two register sets
+        // without copies at the loop back edge.  Op fields are read through
+        // references into the uniform op array so they stay scalar.
         for (int oi = 0; oi < ta.n_ops; oi += 2) {
-            reg_op<T, NR, RB, TB, DG>(amp, ops[oi], pool, lds, dtab, base, gthr, gbit, tid);
-            reg_op<T, NR, RB, TB, DG>(amp, ops[oi + 1], pool, lds, dtab, base, gthr, gbit, tid);
+            reg_op<T, R, NR, RB, DG>(amp, ops[oi], lds, limg, base, lane, wave);
+            reg_op<T, R, NR, RB, DG>(amp, ops[oi + 1], lds, limg, base, lane, wave);
         }
         __builtin_amdgcn_s_setprio(2);
+        T *sp = psi + gs;
+        asm volatile("" : "+v"(sp));
+        sp += base;
+        uint64_t gr[RB];
 #pragma unroll
-        for (int i = 0; i < NR; ++i) psi[base | gthr | greg<T, NR, RB>(i, gbit)] = amp[i];
-        __syncthreads();   // every thread has read s_tile and left the LDS buffer
-        if (tid == 0) s_tile = next;
-        __syncthreads();
-        tile = __builtin_amdgcn_readfirstlane(s_tile);
+        for (int j = 0; j < RB; ++j) {
+            gr[j] = ta.g_reg_f[j];
+            asm volatile("" : "+s"(gr[j]));
+        }
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            uint64_t g = 0;
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+                if ((i >> j) & 1) g |= gr[j];
+            sp[g] = amp[i];
+        }
+        ++tile;
+        --left;
     }
 }
 
@@ -479,19 +641,33 @@ static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
     if (ta.n_tiles == 0) return hipSuccess;
     if (ta.n_ops & 1) return hipErrorInvalidValue;   // programs are padded to even length
     if (ta.n_tiles > 0xffffffffull - 65536) return hipErrorInvalidValue;
-    static unsigned resident = 0;   // workgroups the device holds at once
-    if (resident == 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void *>(k_tile_reg<R, RB, TB, DG>), 1 << TB, 0);
+    if (ta.img_bytes > kRegImageMax || (ta.img_bytes & 15u) || (ta.img_off & 15)) return hipErrorInvalidValue;
+    constexpr size_t half = sizeof(T) << (RB + TB - 1);
+    const size_t lds = half + ta.img_bytes;
+    static int cus = 0;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = set_lds_attr(k_tile_reg<R, RB, TB, DG>, half + kRegImageMax);
         if (e != hipSuccess) return e;
-        resident = (unsigned)std::max(1, cus * std::max(1, per_cu));
+        int dev = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        attr = true;
     }
+    // resident workgroups per compute unit for this image size (in 1 KiB steps)
+    static int per_cu[kRegImageMax / 1024 + 2] = {0};
+    const size_t slot = (ta.img_bytes + 1023) / 1024;
+    if (per_cu[slot] == 0) {
+        int occ = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void *>(k_tile_reg<R, RB, TB, DG>), 1 << TB, half + slot * 1024);
+        if (e != hipSuccess) return e;
+        per_cu[slot] = std::max(1, occ);
+    }
+    const uint64_t resident = (uint64_t)std::max(1, cus) * (uint64_t)per_cu[slot];
     const unsigned grid = (unsigned)std::min<uint64_t>(ta.n_tiles, resident);
-    hipLaunchKernelGGL((k_tile_reg<R, RB, TB, DG>), dim3(grid), dim3(1 << TB), 0, s, (T *)psi, ta,
+    hipLaunchKernelGGL((k_tile_reg<R, RB, TB, DG>), dim3(grid), dim3(1 << TB), lds, s, (T *)psi, ta,
                        rops, (const T *)pool, counter);
     return hipGetLastError();
 }

@@ -287,6 +287,13 @@ void account(qsv_sim *s, double touched_amps, double flops_per_amp) {
 
 qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes);
 
+// Register bits per thread of the register-resident tile kernel.
+int reg_bits_for(const qsv_sim *s) {
+    if (s->opt.reg_bits > 0) return s->opt.reg_bits;
+    if (s->opt.tile_bits >= 11 && s->opt.tile_bits <= 13) return s->opt.tile_bits - 8;
+    return qsv::dev::tile_reg_bits(s->opt.dtype);
+}
+
 qsv_status launch_op(qsv_sim *s, const Op &op) {
     const int nq = s->n;
     const int k = op.k;
@@ -346,10 +353,7 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
     using qsv::dev::RegOp;
     using qsv::dev::TileOp;
     const int nq = s->n;
-    const int rb = s->opt.reg_bits > 0 ? s->opt.reg_bits
-                                       : (s->opt.tile_bits >= 11 && s->opt.tile_bits <= 13)
-                                             ? s->opt.tile_bits - 8
-                                             : qsv::dev::tile_reg_bits(s->opt.dtype);
+    const int rb = reg_bits_for(s);
     std::vector<double> mats;
     std::vector<qsv::TileProgram> progs(passes.size());
     size_t n_rops = 0, n_lops = 0;
@@ -359,13 +363,21 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         n_lops += progs[pi].lops.size();
     }
     // pool: [RegOp array][TileOp array][one zeroed tile counter per pass]
-    //       [matrices in the state dtype]
+    //       [matrices in the state dtype][LDS images of the register passes]
     const size_t r_bytes = (n_rops * sizeof(RegOp) + 255) & ~size_t(255);
     const size_t l_bytes = (n_lops * sizeof(TileOp) + 255) & ~size_t(255);
     const size_t c_bytes = (passes.size() * sizeof(unsigned int) + 255) & ~size_t(255);
     const size_t nmat = mats.size();
-    const size_t mat_bytes = s->opt.dtype == QSV_C128 ? nmat * sizeof(double) : nmat * sizeof(float);
-    std::vector<unsigned char> host(r_bytes + l_bytes + c_bytes + mat_bytes + 16, 0);
+    const size_t mat_bytes =
+        ((s->opt.dtype == QSV_C128 ? nmat * sizeof(double) : nmat * sizeof(float)) + 255) &
+        ~size_t(255);
+    std::vector<size_t> img_at(passes.size(), 0);
+    size_t img_bytes = 0;
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+        img_at[pi] = mat_bytes + img_bytes;   // relative to the matrices
+        img_bytes += (progs[pi].img.size() + 255) & ~size_t(255);
+    }
+    std::vector<unsigned char> host(r_bytes + l_bytes + c_bytes + mat_bytes + img_bytes + 16, 0);
     {
         size_t ro = 0, lo = 0;
         for (const auto &pg : progs) {
@@ -378,8 +390,12 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
             lo += pg.lops.size();
         }
     }
+    for (size_t pi = 0; pi < passes.size(); ++pi)
+        if (!progs[pi].img.empty())
+            std::memcpy(host.data() + r_bytes + l_bytes + c_bytes + img_at[pi], progs[pi].img.data(),
+                        progs[pi].img.size());
     if (s->opt.dtype == QSV_C128) {
-        if (nmat) std::memcpy(host.data() + r_bytes + l_bytes + c_bytes, mats.data(), mat_bytes);
+        if (nmat) std::memcpy(host.data() + r_bytes + l_bytes + c_bytes, mats.data(), nmat * sizeof(double));
     } else {
         float *f = reinterpret_cast<float *>(host.data() + r_bytes + l_bytes + c_bytes);
         for (size_t i = 0; i < nmat; ++i) f[i] = (float)mats[i];
@@ -407,10 +423,12 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         for (int p = 0; p < 64; ++p)
             if ((pg.tile >> p) & 1) ta.tpos[c++] = (uint32_t)p;
         ta.n_tiles = 1ull << (nq - pg.m);
-        std::memcpy(ta.reg_lbit, pg.reg_lbit, 8);
-        std::memcpy(ta.thr_lbit, pg.thr_lbit, 16);
         std::memcpy(ta.g_reg, pg.g_reg, sizeof(ta.g_reg));
         std::memcpy(ta.g_thr, pg.g_thr, sizeof(ta.g_thr));
+        std::memcpy(ta.g_reg_f, pg.g_reg_f, sizeof(ta.g_reg_f));
+        std::memcpy(ta.g_thr_f, pg.g_thr_f, sizeof(ta.g_thr_f));
+        ta.img_bytes = (uint32_t)pg.img.size();
+        ta.img_off = (int64_t)img_at[pi];
         ta.rb = rb;
         ta.mfma_k = pg.mfma_k;
         for (int i = 0; i < 64 && (i << 8) < (1 << pg.m); ++i) {
@@ -435,9 +453,12 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         tend(s, tok, QSV_K_TILE, 2.0 * (double)s->dim() * s->elem());
         account(s, (double)s->dim(), pg.flops_per_amp);
         if (log_level() >= 2)
-            std::fprintf(stderr, "qsv: pass %zu tile=%#llx m=%d %s ops=%zu remaps=%d flop/amp=%.0f\n",
+            std::fprintf(stderr,
+                         "qsv: pass %zu tile=%#llx m=%d %s ops=%zu remaps=%d real=%d diag=%d "
+                         "image=%zuB flop/amp=%.0f\n",
                          pi, (unsigned long long)pg.tile, pg.m, pg.reg ? "reg" : "lds",
-                         pg.reg ? nr - pg.remaps : nl, pg.remaps, pg.flops_per_amp);
+                         pg.reg ? nr - pg.remaps : nl, pg.remaps, pg.real_ops, pg.diag_ops,
+                         pg.img.size(), pg.flops_per_amp);
         s->stats_remaps += pg.remaps;
         ro += nr;
         lo += nl;
@@ -560,6 +581,13 @@ void dm_queue(qsv_sim *s, Gate &&g) {
 extern "C" {
 
 const char *qsv_version(void) { return "qsv 0.1 (gfx950)"; }
+
+qsv_status qsv_copy_probe(const void *src, void *dst, uint64_t bytes, void *stream) {
+    if (!src || !dst || bytes % 16) return fail(nullptr, QSV_EINVAL, "copy probe: NULL buffer or size not a multiple of 16");
+    const hipError_t e = qsv::dev::copy_probe(src, dst, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, QSV_EDEVICE, std::string("copy probe: ") + hipGetErrorString(e));
+    return QSV_OK;
+}
 
 const char *qsv_last_error(const qsv_sim *sim) {
     if (sim && live(sim)) return sim->err.c_str();
@@ -1304,6 +1332,65 @@ qsv_status qsv_reset(qsv_sim *s) {
     s->queue.clear();
     if (!s->materialized) return QSV_OK;
     QSV_HIP(s, qsv::dev::fill_basis0(s->opt.dtype, s->d_state, s->dim(), s->stream));
+    return QSV_OK;
+}
+
+qsv_status qsv_check_tile_programs(qsv_sim *s, double *state, int32_t *info) {
+    QSV_CHECK(s);
+    if (s->opt.mode != QSV_MODE_TILED) return fail(s, QSV_EINVAL, "handle is not in tiled mode");
+    std::vector<Op> ops = canonical_queue(s, nullptr);
+    const int m = std::min(tile_bits_for(s), s->n);
+    std::vector<Pass> passes = qsv::plan_tiled(ops, s->n, m, s->opt.k_max);
+    const int rb = reg_bits_for(s);
+    std::vector<cd> psi(state ? s->dim() : 0);
+    for (uint64_t i = 0; state && i < s->dim(); ++i) psi[i] = cd(state[2 * i], state[2 * i + 1]);
+    int32_t counts[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (const Pass &ps : passes) {
+        std::vector<double> mats;
+        qsv::TileProgram pg;
+        qsv::compile_pass(ps, rb, mats, pg, (int)s->elem());
+        counts[0] += 1;
+        if (!pg.reg) {
+            char msg[160];
+            std::snprintf(msg, sizeof msg,
+                          "pass %d (tile %#llx, %d bits, %d register bits) runs on the LDS-tile kernel",
+                          counts[0] - 1, (unsigned long long)ps.tile, pg.m, rb);
+            if (log_level() >= 2)
+                for (const Op &o : ps.ops)
+                    std::fprintf(stderr, "  op kind=%d diag=%d k=%d t0=%d t1=%d ctrl=%#llx touch=%#x\n",
+                                 o.kind, (int)o.diag, o.k, o.t[0], o.k > 1 ? o.t[1] : -1,
+                                 (unsigned long long)o.ctrl, o.touch);
+            return fail(s, QSV_EUNSUPPORTED, msg);
+        }
+        counts[1] += 1;
+        counts[2] += pg.real_ops;
+        counts[3] += pg.diag_ops;
+        counts[4] += pg.remaps;
+        counts[5] = std::max<int32_t>(counts[5], (int32_t)pg.img.size());
+        counts[6] += (int32_t)pg.rops.size();
+        counts[7] += pg.diag_merged;
+        counts[8] += pg.local_remaps;
+        if (log_level() >= 3) {
+            auto pos = [](uint64_t g) { return g ? __builtin_ctzll(g) : -1; };
+            std::fprintf(stderr, "pass %d: load lanes", counts[0] - 1);
+            for (int t = 0; t < 6; ++t) std::fprintf(stderr, " %d", pos(pg.g_thr[t]));
+            std::fprintf(stderr, " | store lanes");
+            for (int t = 0; t < 6; ++t) std::fprintf(stderr, " %d", pos(pg.g_thr_f[t]));
+            std::fprintf(stderr, " | regs");
+            for (int j = 0; j < rb; ++j) std::fprintf(stderr, " %d", pos(pg.g_reg[j]));
+            std::fprintf(stderr, " -> ");
+            for (int j = 0; j < rb; ++j) std::fprintf(stderr, " %d", pos(pg.g_reg_f[j]));
+            std::fprintf(stderr, "\n");
+        }
+        if (!state) continue;
+        const std::string err = qsv::emulate_reg_pass(pg, rb, mats, (int)s->elem(), s->n, psi);
+        if (!err.empty()) return fail(s, QSV_EINVAL, "tile program check: " + err);
+    }
+    for (uint64_t i = 0; state && i < s->dim(); ++i) {
+        state[2 * i] = psi[i].real();
+        state[2 * i + 1] = psi[i].imag();
+    }
+    if (info) std::memcpy(info, counts, sizeof(counts));
     return QSV_OK;
 }
 

@@ -1,14 +1,16 @@
 // Lowering of a planned pass into the instruction list of a tile kernel.
 //
-// For the register-resident kernel (m = RB + 8 tile bits, 2^RB amplitudes per
-// thread) this decides, op by op, which tile bits live in registers: a 1- or
-// 2-qubit dense operation needs its targets there; when it finds them absent
-// a REMAP moves the tile through LDS into a layout holding the targets plus
-// the bits used soonest afterwards (Belady's furthest-next-use rule applied
-// to the RB register slots).  Diagonal operations run in any layout; wider
-// operations run on the LDS copy of the tile.
+// For the register-resident kernel (m = RB + 8 or RB + 9 tile bits, 2^RB
+// amplitudes per thread) this decides, op by op, which tile bits live in
+// registers: a 1- or 2-qubit operation needs its targets there; when it finds
+// them absent a REMAP moves the tile through LDS into a layout holding the
+// targets plus the bits used soonest afterwards (Belady's furthest-next-use
+// rule applied to the RB register slots).  Diagonal operations run in any
+// layout; passes with wider operations run on the LDS-tile kernel.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <string>
 
 #include "device.hpp"
 #include "qsv_internal.hpp"
@@ -113,15 +115,6 @@ dev::TileOp lds_form(const Op &op, const int *li, std::vector<double> &mats, int
     return t;
 }
 
-void set_layout(uint32_t regmask, int m, int rb, uint8_t *reg_lbit, uint8_t *thr_lbit) {
-    int j = 0, i = 0;
-    for (int b = 0; b < m; ++b) {
-        if ((regmask >> b) & 1) reg_lbit[j++] = (uint8_t)b;
-        else thr_lbit[i++] = (uint8_t)b;
-    }
-    (void)rb;
-}
-
 }  // namespace
 
 uint32_t remap_offset(uint32_t l, int kept, int elem_bytes) {
@@ -130,62 +123,206 @@ uint32_t remap_offset(uint32_t l, int kept, int elem_bytes) {
     return swz_elem(h, elem_bytes) * (uint32_t)elem_bytes;
 }
 
+
+// ------------------------------------------------------------- real split
+bool real_split(const std::vector<cd> &U, int k, std::vector<cd> &l, std::vector<double> &M,
+                std::vector<cd> &rr) {
+    const int d = 1 << k;
+    double amax = 0.0;
+    for (const cd &v : U) amax = std::max(amax, std::abs(v));
+    if (!(amax > 0.0)) return false;
+    // Phases travel along the entries that are clearly nonzero: breadth-first
+    // over the bipartite graph of rows and columns they join.  Each phase is
+    // fixed modulo pi only (M may be negative), and the representative with
+    // a positive real part (or +i) is taken, so a real matrix gets phases 1.
+    const double edge = 1e-6 * amax;
+    auto canon = [](cd z) {
+        if (z.real() < 0.0 || (z.real() == 0.0 && z.imag() < 0.0)) z = -z;
+        return z;
+    };
+    l.assign(d, cd(1, 0));
+    rr.assign(d, cd(1, 0));
+    std::vector<char> lset(d, 0), rset(d, 0);
+    std::vector<int> q;
+    for (int r0 = 0; r0 < d; ++r0) {
+        if (lset[r0]) continue;
+        lset[r0] = 1;
+        q.assign(1, r0);
+        for (size_t h = 0; h < q.size(); ++h) {
+            const int v = q[h];
+            if (v < d) {
+                for (int c = 0; c < d; ++c) {
+                    const cd u = U[(size_t)v * d + c];
+                    if (rset[c] || std::abs(u) <= edge) continue;
+                    rr[c] = canon((u / std::abs(u)) * std::conj(l[v]));
+                    rset[c] = 1;
+                    q.push_back(d + c);
+                }
+            } else {
+                const int c = v - d;
+                for (int r = 0; r < d; ++r) {
+                    const cd u = U[(size_t)r * d + c];
+                    if (lset[r] || std::abs(u) <= edge) continue;
+                    l[r] = canon((u / std::abs(u)) * std::conj(rr[c]));
+                    lset[r] = 1;
+                    q.push_back(r);
+                }
+            }
+        }
+    }
+    M.assign((size_t)d * d, 0.0);
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            const cd v = U[(size_t)r * d + c] * std::conj(l[r]) * std::conj(rr[c]);
+            if (std::abs(v.imag()) > 1e-14) return false;
+            M[(size_t)r * d + c] = v.real();
+        }
+    return true;
+}
+
 namespace {
 
-// Global-index bits and LDS byte offsets of every layout of a register
-// program (the kernel then needs no per-lane layout arithmetic).
-void fill_layouts(TileProgram &prog, int rb, int elem_bytes) {
-    uint8_t tpos[64];
-    int c = 0;
-    for (int p = 0; p < 64; ++p)
-        if ((prog.tile >> p) & 1) tpos[c++] = (uint8_t)p;
-    const int tb = prog.m - rb;
-    const int nr = 1 << rb;
-    for (int j = 0; j < rb; ++j) prog.g_reg[j] = 1ull << tpos[prog.reg_lbit[j]];
-    for (int t = 0; t < tb; ++t) prog.g_thr[t] = 1ull << tpos[prog.thr_lbit[t]];
-    uint8_t cur_reg[8], cur_thr[16];
-    std::memcpy(cur_reg, prog.reg_lbit, 8);
-    std::memcpy(cur_thr, prog.thr_lbit, 16);
-    for (dev::RegOp &r : prog.rops) {
-        if (r.kind != dev::ROP_REMAP) continue;
-        const int kept = cur_reg[r.a];
-        for (int i = 0; i < nr; ++i) {
-            uint32_t lo = 0, ln = 0;
-            for (int j = 0; j < rb; ++j)
-                if ((i >> j) & 1) {
-                    lo |= 1u << cur_reg[j];
-                    ln |= 1u << r.reg_lbit[j];
-                }
-            r.wr[i] = remap_offset(lo, kept, elem_bytes);
-            r.rd[i] = remap_offset(ln, kept, elem_bytes);
-        }
-        for (int t = 0; t < tb; ++t) {
-            r.wthr[t] = remap_offset(1u << cur_thr[t], kept, elem_bytes);
-            r.rthr[t] = remap_offset(1u << r.thr_lbit[t], kept, elem_bytes);
-            r.g_thr[t] = 1ull << tpos[r.thr_lbit[t]];
-        }
-        for (int j = 0; j < rb; ++j) r.g_reg[j] = 1ull << tpos[r.reg_lbit[j]];
-        std::memcpy(cur_reg, r.reg_lbit, 8);
-        std::memcpy(cur_thr, r.thr_lbit, 16);
+// Register-kernel layout: register slot j holds tile bit reg[j], thread-id
+// bit t holds tile bit thr[t].
+struct Layout {
+    uint8_t reg[8] = {};
+    uint8_t thr[16] = {};
+};
+
+Layout make_layout(uint32_t regmask, int m) {
+    Layout L;
+    int j = 0, i = 0;
+    for (int b = 0; b < m; ++b) {
+        if ((regmask >> b) & 1) L.reg[j++] = (uint8_t)b;
+        else L.thr[i++] = (uint8_t)b;
     }
+    return L;
+}
+
+// The layout after a remap to register set Sn: the register slots as
+// make_layout orders them (the caller puts the kept bit back in its slot);
+// thread-id bits keep their tile bits where those stay outside the
+// registers, and the bits that leave the registers fill the freed slots.
+// A freed wave-id slot takes the leaving bit used last (next_use), so the
+// wave-id bits change as rarely as possible.
+Layout next_layout(const Layout &cur, uint32_t Sn, int m, int rb, int lane_bits,
+                   const int *next_use) {
+    Layout nw = make_layout(Sn, m);
+    const int tb = m - rb;
+    uint8_t thr[16];
+    bool fixed[16] = {};
+    std::vector<int> leaving;
+    for (int j = 0; j < rb; ++j)
+        if (!((Sn >> cur.reg[j]) & 1)) leaving.push_back(cur.reg[j]);
+    std::sort(leaving.begin(), leaving.end(),
+              [&](int x, int y) { return next_use[x] > next_use[y]; });
+    for (int t = 0; t < tb; ++t)
+        if (!((Sn >> cur.thr[t]) & 1)) {
+            thr[t] = cur.thr[t];
+            fixed[t] = true;
+        }
+    size_t k = 0;
+    for (int t = tb - 1; t >= lane_bits; --t)
+        if (!fixed[t]) thr[t] = (uint8_t)leaving[k++];
+    for (int t = 0; t < lane_bits && t < tb; ++t)
+        if (!fixed[t]) thr[t] = (uint8_t)leaving[k++];
+    std::memcpy(nw.thr, thr, (size_t)tb);
+    return nw;
+}
+
+// A unit of the register program before lowering.
+struct Item {
+    int kind = dev::ROP_G1;    // ROP_G1/G2/R1/R2/DIAG
+    uint32_t need = 0;         // tile bits that must be register bits
+    uint64_t all = 0, mix = 0; // qubits touched / qubits whose value may change
+    Op op;                     // G/R: targets, controls (G: the matrix)
+    std::vector<double> rm;    // R: real matrix over op.t, row-major
+    std::vector<Op> members;   // DIAG: the diagonal ops multiplied into one table
+};
+
+Op diag_op(const int *t, int k, uint64_t ctrl, const std::vector<cd> &val) {
+    Op d;
+    d.kind = Op::MONO;
+    d.diag = true;
+    d.k = k;
+    for (int j = 0; j < k; ++j) d.t[j] = t[j];
+    d.ctrl = ctrl;
+    d.U = val;
+    d.touch = 0;
+    for (int r = 0; r < (1 << k); ++r) {
+        d.perm[r] = (uint8_t)r;
+        if (val[r] != cd(1, 0)) d.touch |= 1u << r;
+    }
+    return d;
+}
+
+bool all_ones(const std::vector<cd> &v) {
+    for (const cd &z : v)
+        if (z != cd(1, 0)) return false;
+    return true;
+}
+
+// Pending image block: a table or a run of lane words, placed at the end.
+struct ImgBlock {
+    std::vector<unsigned char> bytes;
+    uint32_t align = 16;
+    int op = -1;          // index into rops
+    bool table = false;   // patches rops[op].mat (else lane_off)
+    bool ones = false;    // a table of ones: patches rops[op].b instead
+    uint32_t off = 0;
+};
+
+void put_complex(std::vector<unsigned char> &b, const cd &v, int elem_bytes) {
+    if (elem_bytes == 16) {
+        double x[2] = {v.real(), v.imag()};
+        const unsigned char *p = reinterpret_cast<const unsigned char *>(x);
+        b.insert(b.end(), p, p + 16);
+    } else {
+        float x[2] = {(float)v.real(), (float)v.imag()};
+        const unsigned char *p = reinterpret_cast<const unsigned char *>(x);
+        b.insert(b.end(), p, p + 8);
+    }
+}
+
+void put_words(std::vector<unsigned char> &b, const uint32_t *w, int n) {
+    const unsigned char *p = reinterpret_cast<const unsigned char *>(w);
+    b.insert(b.end(), p, p + 4 * n);
 }
 
 }  // namespace
 
+// Lowering of one pass.  For the register kernel:
+//  1. every 1- or 2-qubit op is split, when it can be, into diagonal phases
+//     on either side of a real matrix (real_split); the real matrix costs
+//     half the arithmetic of the complex one;
+//  2. diagonal ops (the pass's own and those phases) are gathered: each may
+//     move between the non-diagonal ops it commutes with, and a greedy
+//     interval stabbing places them at as few points as possible, where they
+//     multiply into tables of at most kRegDiagMax bits;
+//  3. list scheduling orders the commuting ops to need few layout changes,
+//     and Belady's furthest-next-use rule picks the register set of each
+//     REMAP;
+//  4. every layout-dependent offset (table indices, LDS buffer offsets,
+//     per-lane words of the image) is computed here, so the kernel does no
+//     layout arithmetic.
 void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram &prog,
                   int elem_bytes) {
     prog = TileProgram();
     prog.tile = ps.tile;
     int li[64];
     int m = 0;
+    uint8_t tpos[64];
     for (int p = 0; p < 64; ++p) {
         li[p] = -1;
-        if ((ps.tile >> p) & 1) li[p] = m++;
+        if ((ps.tile >> p) & 1) {
+            tpos[m] = (uint8_t)p;
+            li[p] = m++;
+        }
     }
     prog.m = m;
     const int tb = m - rb;
     prog.reg = rb >= 3 && rb <= 5 && (tb == 8 || (tb == 9 && rb <= 4));
-    // the register kernel runs 1- and 2-qubit dense ops and diagonal ops only
+    // the register kernel runs 1- and 2-qubit ops on tile qubits and diagonal ops
     for (const Op &op : ps.ops) {
         if (op.kind == Op::MONO && (op.diag || op.touch == 0)) continue;
         bool inside = true;
@@ -193,7 +330,11 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
             if (li[op.t[j]] < 0) inside = false;
         if (!inside || op.k > 2) prog.reg = false;
     }
-    if (!prog.reg) {
+    auto lds_program = [&]() {
+        prog.reg = false;
+        prog.rops.clear();
+        prog.img.clear();
+        prog.flops_per_amp = 0.0;
         for (const Op &op : ps.ops) {
             if (op.kind == Op::MONO && op.touch == 0) continue;
             double fl = 0.0;
@@ -202,123 +343,74 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
             if (t.kind == dev::TOP_DENSE_MFMA) prog.mfma_k = std::max(prog.mfma_k, t.k);
             prog.lops.push_back(t);
         }
+    };
+    if (!prog.reg) {
+        lds_program();
         return;
     }
-    // classify
-    struct Item {
-        int kind;          // ROP_G1/G2/DIAG/LDS
-        uint32_t need;     // local bits that must be register bits
-        const Op *op;
-        int run;           // DIAG: index into `runs`
+    const size_t mats_mark = mats.size();
+    const uint64_t tile_mask = ps.tile;
+
+    // ---- 1. items in queue order; diagonal pieces remember their position
+    std::vector<Item> nd;                       // non-diagonal items
+    struct DPiece {
+        Op op;
+        int pos;                                // number of nd items before it
     };
-    // A run of consecutive diagonal ops becomes one diagonal op: the controls
-    // that all of them share stay controls, every other qubit of the run
-    // (targets and the remaining controls) indexes the table, while there are
-    // at most kRegDiagMax such qubits.  The kernel's cost of a diagonal op is
-    // one table gather and one complex product per amplitude, whatever its
-    // width.  A run of one op keeps its own targets and controls.
-    struct DiagRun {
-        int k = 0;
-        int t[dev::kRegDiagMax] = {};
-        uint64_t ctrl = 0;
-        std::vector<cd> val;   // val[r], bit j of r <-> qubit t[j]
-    };
-    std::vector<DiagRun> runs;
-    std::vector<uint64_t> run_all;   // qubits of each run (for commutation)
-    std::vector<Item> items;
-    const int n_ops = (int)ps.ops.size();
-    auto is_diag = [](const Op &o) { return o.kind == Op::MONO && o.diag && o.touch != 0; };
-    auto is_noop = [](const Op &o) { return o.kind == Op::MONO && o.touch == 0; };
-    for (int oi = 0; oi < n_ops; ++oi) {
-        const Op &op = ps.ops[oi];
-        if (is_noop(op)) continue;
-        if (is_diag(op)) {
-            uint64_t common = op.ctrl, qs = op.targets();
-            std::vector<const Op *> mem{&op};
-            int oj = oi + 1;
-            for (; oj < n_ops; ++oj) {
-                const Op &o2 = ps.ops[oj];
-                if (is_noop(o2)) continue;
-                if (!is_diag(o2)) break;
-                const uint64_t c2 = common & o2.ctrl;
-                const uint64_t q2 = qs | (common & ~c2) | (o2.qubits() & ~c2);
-                if (popc(q2) > dev::kRegDiagMax) break;
-                common = c2;
-                qs = q2;
-                mem.push_back(&o2);
-            }
-            DiagRun run;
-            if (mem.size() == 1) {
-                run.k = op.k;
-                for (int j = 0; j < op.k; ++j) run.t[j] = op.t[j];
-                run.ctrl = op.ctrl;
-                run.val.assign(op.U.begin(), op.U.begin() + (1 << op.k));
-            } else {
-                run.ctrl = common;
-                for (int p = 0; p < 64; ++p)
-                    if ((qs >> p) & 1) run.t[run.k++] = p;
-                run.val.assign(size_t(1) << run.k, cd(1, 0));
-                for (uint32_t r = 0; r < (1u << run.k); ++r) {
-                    uint64_t bits = common;   // the qubits' values in row r
-                    for (int j = 0; j < run.k; ++j)
-                        if ((r >> j) & 1) bits |= 1ull << run.t[j];
-                    for (const Op *o : mem) {
-                        if ((bits & o->ctrl) != o->ctrl) continue;
-                        uint32_t row = 0;
-                        for (int j = 0; j < o->k; ++j)
-                            if ((bits >> o->t[j]) & 1) row |= 1u << j;
-                        run.val[r] *= o->U[row];
-                    }
-                }
-                prog.diag_merged += (int)mem.size() - 1;
-            }
-            uint64_t all = 0;
-            for (const Op *o : mem) all |= o->qubits();
-            run_all.push_back(all);
-            runs.push_back(std::move(run));
-            items.push_back({dev::ROP_DIAG, 0u, nullptr, (int)runs.size() - 1});
-            oi = oj - 1;
+    std::vector<DPiece> dps;
+    for (const Op &op : ps.ops) {
+        if (op.kind == Op::MONO && op.touch == 0) continue;
+        if (op.kind == Op::MONO && op.diag) {
+            dps.push_back({op, (int)nd.size()});
             continue;
         }
-        bool inside = true;
-        uint32_t need = 0;
-        for (int j = 0; j < op.k; ++j) {
-            if (li[op.t[j]] < 0) inside = false;
-            else need |= 1u << li[op.t[j]];
+        Item it;
+        it.op = op;
+        it.all = op.qubits();
+        it.mix = op.mixing();
+        for (int j = 0; j < op.k; ++j) it.need |= 1u << li[op.t[j]];
+        const std::vector<cd> U = dense_matrix(op);
+        std::vector<cd> lph, rph;
+        if (real_split(U, op.k, lph, it.rm, rph)) {
+            it.kind = op.k == 1 ? dev::ROP_R1 : dev::ROP_R2;
+            if (!all_ones(rph)) dps.push_back({diag_op(op.t, op.k, op.ctrl, rph), (int)nd.size()});
+            nd.push_back(std::move(it));
+            if (!all_ones(lph)) dps.push_back({diag_op(op.t, op.k, op.ctrl, lph), (int)nd.size()});
+            prog.real_ops += 1;
+        } else {
+            it.kind = op.k == 1 ? dev::ROP_G1 : dev::ROP_G2;
+            it.rm.clear();
+            nd.push_back(std::move(it));
         }
-        if (inside && op.k <= 2) items.push_back({op.k == 1 ? dev::ROP_G1 : dev::ROP_G2, need, &op, -1});
-        else items.push_back({dev::ROP_LDS, 0u, &op, -1});
     }
-    // Ops of a pass that commute may run in any order.  List scheduling over
-    // the order that non-commuting ops impose: among the ops whose
-    // predecessors have run, take the first (in queue order) whose bits are
-    // already register bits; if none is, the one with the fewest bits missing
-    // (its layout change keeps more of the register set that the waiting ops
-    // may want, and every change is a workgroup-wide LDS round trip), and
-    // model the new register set as its bits plus the old register bits that
-    // the most waiting ops need.  The lowering below then places the layout
-    // changes.  The choice is among the next kWin unscheduled ops (queue
-    // order), which bounds the cost on long passes: the first unscheduled op
-    // is always ready, and an op further than kWin behind an unscheduled
-    // one cannot be picked, so only dependences within kWin need recording.
+    // ---- 2. the items in queue order, each diagonal piece an item of its own
+    std::vector<Item> items;
+    {
+        const int K = (int)nd.size();
+        size_t d = 0;
+        items.reserve(nd.size() + dps.size());
+        for (int g = 0; g <= K; ++g) {
+            for (; d < dps.size() && dps[d].pos == g; ++d) {
+                Item t;
+                t.kind = dev::ROP_DIAG;
+                t.all = dps[d].op.qubits();
+                t.members.push_back(dps[d].op);
+                items.push_back(std::move(t));
+            }
+            if (g < K) items.push_back(nd[g]);
+        }
+    }
+    // ---- 3. list scheduling (see above), with the diagonal pieces as single
+    // items (merged tables would tie the order of every op on their qubits); the first unscheduled op is always
+    // ready, and the choice is among the next kWin unscheduled ops
     {
         constexpr int kWin = 256;
         const int N = (int)items.size();
-        std::vector<uint64_t> q_all(N), q_mix(N);
-        for (int i = 0; i < N; ++i) {
-            if (items[i].run >= 0) {
-                q_all[i] = run_all[items[i].run];
-                q_mix[i] = 0;
-            } else {
-                q_all[i] = items[i].op->qubits();
-                q_mix[i] = items[i].op->mixing();
-            }
-        }
         std::vector<int> npred(N, 0);
         std::vector<std::vector<int>> succ(N);
         for (int i = 0; i < N; ++i)
             for (int j = std::max(0, i - kWin); j < i; ++j)
-                if (!commute_masks(q_mix[j], q_all[j], q_mix[i], q_all[i])) {
+                if (!commute_masks(items[j].mix, items[j].all, items[i].mix, items[i].all)) {
                     succ[j].push_back(i);
                     npred[i] += 1;
                 }
@@ -329,9 +421,9 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         }
         std::vector<char> ready(N, 0), done(N, 0);
         for (int i = 0; i < N; ++i) ready[i] = npred[i] == 0;
-        std::vector<Item> order;
+        std::vector<int> order;
         order.reserve(N);
-        int first = 0;   // first unscheduled op
+        int first = 0;
         for (int step = 0; step < N; ++step) {
             while (done[first]) ++first;
             const int end = std::min(N, first + kWin);
@@ -348,8 +440,6 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
                             pick = i;
                         }
                     }
-                // new register set: the op's bits, then the old register bits
-                // wanted by the most ops that wait (ready ones count more)
                 uint32_t Sn = items[pick].need;
                 int cnt[32] = {0};
                 for (int i = first; i < end; ++i)
@@ -367,21 +457,94 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
                 Sm = Sn;
             }
             done[pick] = 1;
-            order.push_back(items[pick]);
+            order.push_back(pick);
             for (int j : succ[pick])
                 if (--npred[j] == 0) ready[j] = 1;
         }
-        items.swap(order);
+        std::vector<Item> sorted;
+        sorted.reserve(N);
+        for (int i : order) sorted.push_back(std::move(items[i]));
+        items.swap(sorted);
     }
+    const std::vector<Item> scheduled = std::move(items);
+
+    // Steps 3b-4 build the program with tables of at most `cap` qubits and
+    // return the size of its LDS image.
+    const int real_ops = prog.real_ops;
+    auto lower = [&](int cap) -> uint32_t {
+    mats.resize(mats_mark);
+    prog.rops.clear();
+    prog.img.clear();
+    prog.remaps = prog.diag_ops = prog.diag_merged = prog.local_remaps = 0;
+    prog.real_ops = real_ops;
+    prog.flops_per_amp = 0.0;
+    // ---- 3b. diagonal grouping by interval stabbing in the scheduled order:
+    // each piece may move between the non-diagonal items it commutes with;
+    // greedy stabbing (by right end) places them at as few gaps as possible
+    std::vector<const Item *> nds;
+    std::vector<std::pair<const Item *, int>> pcs;   // piece, nd items before it
+    for (const Item &it : scheduled) {
+        if (it.kind == dev::ROP_DIAG) pcs.push_back({&it, (int)nds.size()});
+        else nds.push_back(&it);
+    }
+    const int K = (int)nds.size();
+    std::vector<std::vector<int>> at_gap(K + 1);   // pieces placed before nds[g]
+    {
+        std::vector<int> L(pcs.size()), R(pcs.size()), order(pcs.size());
+        for (size_t d = 0; d < pcs.size(); ++d) {
+            const uint64_t all = pcs[d].first->all;
+            int lo = 0, hi = K;
+            for (int j = pcs[d].second - 1; j >= 0; --j)
+                if (!commute_masks(nds[j]->mix, nds[j]->all, 0, all)) { lo = j + 1; break; }
+            for (int j = pcs[d].second; j < K; ++j)
+                if (!commute_masks(nds[j]->mix, nds[j]->all, 0, all)) { hi = j; break; }
+            L[d] = lo;
+            R[d] = hi;
+            order[d] = (int)d;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return R[x] < R[y]; });
+        int stab = -1;
+        for (int d : order) {
+            if (L[d] > stab) stab = R[d];
+            at_gap[stab].push_back(d);
+        }
+    }
+    // pieces of one gap multiply into tables of at most `cap` qubits (first
+    // fit; diagonal ops commute, so any grouping is exact)
+    std::vector<Item> items;
+    items.reserve(nds.size() + pcs.size());
+    for (int g = 0; g <= K; ++g) {
+        std::sort(at_gap[g].begin(), at_gap[g].end());
+        std::vector<Item> tabs;
+        for (int d : at_gap[g]) {
+            const Item &pc = *pcs[d].first;
+            Item *dst = nullptr;
+            for (Item &t : tabs)
+                if (popc(t.all | pc.all) <= cap) { dst = &t; break; }
+            if (!dst) {
+                tabs.emplace_back();
+                dst = &tabs.back();
+                dst->kind = dev::ROP_DIAG;
+            } else {
+                prog.diag_merged += 1;
+            }
+            dst->all |= pc.all;
+            dst->members.insert(dst->members.end(), pc.members.begin(), pc.members.end());
+        }
+        for (Item &t : tabs) items.push_back(std::move(t));
+        if (g < K) items.push_back(*nds[g]);
+    }
+
+    // ---- 4. lowering
     const int n_items = (int)items.size();
-    // next_at[i * m + b]: the first op at or after position i that needs
-    // tile bit b (1 << 30: none), for the Belady choices of the remaps
+    const int nr = 1 << rb;
+    const int lane_bits = 6;
+    const int nwaves = 1 << (tb - lane_bits);
     std::vector<int> next_at((size_t)(n_items + 1) * m, 1 << 30);
     for (int i = n_items - 1; i >= 0; --i)
         for (int b = 0; b < m; ++b)
             next_at[(size_t)i * m + b] =
                 ((items[i].need >> b) & 1) ? i : next_at[(size_t)(i + 1) * m + b];
-    // initial register set: the first needed bits, then the highest free bits
     uint32_t S = 0;
     for (const Item &it : items) {
         if (__builtin_popcount(S | it.need) > rb) break;
@@ -389,13 +552,149 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         if (__builtin_popcount(S) == rb) break;
     }
     for (int b = m - 1; b >= 0 && __builtin_popcount(S) < rb; --b) S |= 1u << b;
-    set_layout(S, m, rb, prog.reg_lbit, prog.thr_lbit);
-    uint8_t cur_reg[8], cur_thr[16];
-    std::memcpy(cur_reg, prog.reg_lbit, 8);
-    std::memcpy(cur_thr, prog.thr_lbit, 16);
+    Layout cur = make_layout(S, m);
+    {
+        // the wave-id bits take the thread bits whose first use is latest
+        // (lane bits 0-2 keep the three lowest tile bits: contiguous loads)
+        std::vector<int> cand;
+        for (int t = 3; t < tb; ++t) cand.push_back(cur.thr[t]);
+        std::stable_sort(cand.begin(), cand.end(),
+                         [&](int x, int y) { return next_at[x] > next_at[y]; });
+        const int nwb = tb - lane_bits;
+        std::vector<int> wb(cand.begin(), cand.begin() + nwb), lb(cand.begin() + nwb, cand.end());
+        std::sort(wb.begin(), wb.end());
+        std::sort(lb.begin(), lb.end());
+        for (int t = 3; t < lane_bits; ++t) cur.thr[t] = (uint8_t)lb[t - 3];
+        for (int t = lane_bits; t < tb; ++t) cur.thr[t] = (uint8_t)wb[t - lane_bits];
+    }
+    std::memcpy(prog.reg_lbit, cur.reg, 8);
+    std::memcpy(prog.thr_lbit, cur.thr, 16);
+    for (int j = 0; j < rb; ++j) prog.g_reg[j] = 1ull << tpos[cur.reg[j]];
+    for (int t = 0; t < tb; ++t) prog.g_thr[t] = 1ull << tpos[cur.thr[t]];
+    std::vector<ImgBlock> blocks;
+
+    // A remap that leaves the tile bits of the wave-id bits where they are
+    // moves data only within each wave: it runs on the wave's own region of
+    // the buffer (index over the register and lane bits), with no workgroup
+    // barrier (b = 1).  Otherwise the whole workgroup exchanges through the
+    // buffer; b = 2 adds a barrier before its writes when a wave-local remap
+    // ran since the last workgroup barrier (another wave may still be reading
+    // its region).
+    bool local_since_barrier = false;
+    auto emit_remap = [&](const Layout &nw, int split) {
+        dev::RegOp r{};
+        r.kind = dev::ROP_REMAP;
+        r.a = split;
+        bool local = true;
+        uint32_t wmask = 0;
+        for (int t = lane_bits; t < tb; ++t) {
+            if (cur.thr[t] != nw.thr[t]) local = false;
+            wmask |= 1u << cur.thr[t];
+        }
+        // Buffer address of the amplitude with local index l: a linear map
+        // of its tile bits other than the kept register bit (and, wave-local,
+        // the wave-id bits).  The lane bits 0..q-1 of the old layout take
+        // index bits 0..q-1 (q = 4 for 16-byte, 5 for 8-byte elements: the
+        // lanes a write serves together then hit distinct bank slots), and
+        // each of the new layout's lane bits 0..q-1 that lies higher is
+        // folded (XOR) onto the slot of an old lane bit the new layout does
+        // not use, so the reads are conflict-free too.  Triangular, hence a
+        // bijection onto the buffer.
+        const uint32_t drop = (local ? wmask : 0u) | (1u << cur.reg[split]);
+        const int q = elem_bytes == 16 ? 4 : 5;
+        int pos[32];
+        for (int b = 0; b < 32; ++b) pos[b] = -1;
+        int np = 0;
+        uint32_t A = 0, B = 0;
+        for (int t = 0; t < q; ++t) {
+            A |= 1u << cur.thr[t];
+            B |= 1u << nw.thr[t];
+        }
+        for (int t = 0; t < q; ++t) pos[cur.thr[t]] = np++;
+        for (int b = 0; b < m; ++b)
+            if (!((drop >> b) & 1) && pos[b] < 0) pos[b] = np++;
+        uint32_t fold[32] = {};
+        {
+            std::vector<int> from, to;
+            for (int b = 0; b < m; ++b)
+                if (((B >> b) & 1) && !((A >> b) & 1)) from.push_back(b);
+            for (int t = 0; t < q; ++t)
+                if (!((B >> cur.thr[t]) & 1)) to.push_back(pos[cur.thr[t]]);
+            for (size_t k = 0; k < from.size() && k < to.size(); ++k) fold[from[k]] = 1u << to[k];
+        }
+        auto off = [&](uint32_t l) {
+            uint32_t h = 0;
+            for (int b = 0; b < m; ++b)
+                if (((l >> b) & 1) && pos[b] >= 0) h ^= (1u << pos[b]) ^ fold[b];
+            return h * (uint32_t)elem_bytes;
+        };
+        for (int i = 0; i < nr; ++i) {
+            uint32_t lo = 0, ln = 0;
+            for (int j = 0; j < rb; ++j)
+                if ((i >> j) & 1) {
+                    lo |= 1u << cur.reg[j];
+                    ln |= 1u << nw.reg[j];
+                }
+            r.wr[i] = off(lo);
+            r.rd[i] = off(ln);
+        }
+        uint32_t words[128];
+        for (int l = 0; l < 64; ++l) {
+            uint32_t w = 0, rd = 0;
+            for (int t = 0; t < lane_bits; ++t)
+                if ((l >> t) & 1) {
+                    w ^= off(1u << cur.thr[t]);
+                    rd ^= off(1u << nw.thr[t]);
+                }
+            words[l] = w;
+            words[64 + l] = rd;
+        }
+        const uint32_t region = ((uint32_t)elem_bytes << (m - 1)) / (uint32_t)nwaves;
+        for (int w = 0; w < nwaves; ++w) {
+            uint32_t a = 0, b = 0;
+            if (local) {
+                a = b = (uint32_t)w * region;
+            } else {
+                for (int t = lane_bits; t < tb; ++t)
+                    if ((w >> (t - lane_bits)) & 1) {
+                        a ^= off(1u << cur.thr[t]);
+                        b ^= off(1u << nw.thr[t]);
+                    }
+            }
+            r.wwave[w] = a;
+            r.rwave[w] = b;
+        }
+        if (local) {
+            r.b = 1;
+            local_since_barrier = true;
+            prog.local_remaps += 1;
+        } else {
+            r.b = local_since_barrier ? 2 : 0;
+            local_since_barrier = false;
+        }
+        ImgBlock blk;
+        put_words(blk.bytes, words, 128);
+        blk.op = (int)prog.rops.size();
+        blocks.push_back(std::move(blk));
+        prog.rops.push_back(r);
+        prog.remaps += 1;
+        cur = nw;
+    };
+    auto slot_of = [&](int pos) {
+        const int lb = li[pos];
+        for (int j = 0; j < rb; ++j)
+            if (lb >= 0 && cur.reg[j] == lb) return j;
+        return -1;
+    };
+    auto thr_of = [&](int pos) {
+        const int lb = li[pos];
+        for (int t = 0; t < tb; ++t)
+            if (lb >= 0 && cur.thr[t] == lb) return t;
+        return -1;
+    };
 
     for (int i = 0; i < n_items; ++i) {
-        const Item &it = items[i];
+        Item &it = items[i];
         if ((it.need & ~S) != 0) {
             int next_use[32];
             for (int b = 0; b < m; ++b) next_use[b] = next_at[(size_t)i * m + b];
@@ -411,8 +710,8 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
             });
             for (int c = 0; c < (int)cand.size() && __builtin_popcount(Sn) < rb; ++c)
                 Sn |= 1u << cand[c];
-            // The two-phase remap needs one tile bit that stays in its register
-            // slot: keep the old register bit used soonest if none survived.
+            // the two-phase remap needs one tile bit that stays in its register
+            // slot: keep the old register bit used soonest if none survived
             if ((Sn & S) == 0) {
                 int keep = -1, drop = -1;
                 for (int b = 0; b < m; ++b)
@@ -423,96 +722,161 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
                         drop = b;
                 Sn = (Sn & ~(1u << drop)) | (1u << keep);
             }
-            int split = -1;   // slot of the surviving bit (soonest used)
+            int split = -1;
             for (int j = 0; j < rb; ++j)
-                if (((Sn >> cur_reg[j]) & 1) &&
-                    (split < 0 || next_use[cur_reg[j]] < next_use[cur_reg[split]]))
+                if (((Sn >> cur.reg[j]) & 1) &&
+                    (split < 0 || next_use[cur.reg[j]] < next_use[cur.reg[split]]))
                     split = j;
-            dev::RegOp r{};
-            r.kind = dev::ROP_REMAP;
-            r.a = split;
-            set_layout(Sn, m, rb, r.reg_lbit, r.thr_lbit);
-            // put the surviving bit back into its slot
+            Layout nw = next_layout(cur, Sn, m, rb, lane_bits, next_use);
             for (int j = 0; j < rb; ++j)
-                if (r.reg_lbit[j] == cur_reg[split]) std::swap(r.reg_lbit[j], r.reg_lbit[split]);
-            std::memcpy(cur_reg, r.reg_lbit, 8);
-            std::memcpy(cur_thr, r.thr_lbit, 16);
-            prog.rops.push_back(r);
-            prog.remaps += 1;
+                if (nw.reg[j] == cur.reg[split]) std::swap(nw.reg[j], nw.reg[split]);
+            emit_remap(nw, split);
             S = Sn;
         }
         dev::RegOp r{};
         r.kind = it.kind;
         if (it.kind == dev::ROP_DIAG) {
-            // split the row index and the controls into register bits (wr[i]
-            // per register index i, b) and the rest (pad0, ctrl)
-            auto reg_of = [&](int pos) {
-                for (int j = 0; j < rb; ++j)
-                    if (li[pos] >= 0 && cur_reg[j] == li[pos]) return j;
-                return -1;
-            };
-            const DiagRun &run = runs[it.run];
-            r.a = run.k;
-            r.pad0 = 0;
-            for (int j = 0; j < run.k; ++j) {
-                r.gt[j] = (uint32_t)run.t[j];
-                const int rj = reg_of(run.t[j]);
-                if (rj < 0) r.pad0 |= 1u << j;
-                for (int i = 0; i < (1 << rb); ++i)
-                    if (rj >= 0 && ((i >> rj) & 1)) r.wr[i] |= 1u << j;
+            // table bits: every qubit of the members except the controls that
+            // all of them share and that lie outside the tile
+            uint64_t common = ~0ull;
+            for (const Op &o : it.members) common &= o.ctrl;
+            const uint64_t octrl = common & ~tile_mask;
+            const uint64_t tq_mask = it.all & ~octrl;
+            // table bit order: the qubits on lane bits first, by lane bit, so
+            // that the 16 lanes a ds_read_b128 serves together (lane bits 0-3)
+            // read distinct 16-byte slots of one 256-byte bank row, or the
+            // same slot (a broadcast): no bank conflicts
+            int tq[dev::kRegDiagMax], kt = 0;
+            for (int t = 0; t < lane_bits; ++t)
+                for (int p = 0; p < 64; ++p)
+                    if (((tq_mask >> p) & 1) && li[p] >= 0 && slot_of(p) < 0 && thr_of(p) == t)
+                        tq[kt++] = p;
+            for (int p = 0; p < 64; ++p) {
+                if (!((tq_mask >> p) & 1)) continue;
+                const int t = li[p] >= 0 && slot_of(p) < 0 ? thr_of(p) : -1;
+                if (t < 0 || t >= lane_bits) tq[kt++] = p;
             }
-            r.ctrl = 0;
-            r.b = 0;
-            for (int p = 0; p < 64; ++p)
-                if ((run.ctrl >> p) & 1) {
-                    const int rj = reg_of(p);
-                    if (rj >= 0) r.b |= 1 << rj;
-                    else r.ctrl |= 1ull << p;
+            r.octrl = octrl;
+            const uint32_t eb = (uint32_t)elem_bytes;
+            for (int j = 0; j < kt; ++j) {
+                const uint32_t wgt = eb << j;
+                if (li[tq[j]] < 0) {
+                    r.gt[r.a] = (uint32_t)tq[j];
+                    r.gtb[r.a] = wgt;
+                    r.a += 1;
+                    continue;
                 }
-            r.mat = (int64_t)(mats.size() / 2);
-            int changed = 0;
-            for (int e = 0; e < (1 << run.k); ++e) {
-                push(mats, run.val[e]);
-                if (run.val[e] != cd(1, 0)) ++changed;
-            }
-            prog.flops_per_amp += 6.0 * changed / (double)(1 << run.k) /
-                                  (double)(1ull << popc(run.ctrl));
-        } else if (it.kind == dev::ROP_LDS) {
-            const Op &op = *it.op;
-            double fl = 0.0;
-            dev::TileOp t = lds_form(op, li, mats, elem_bytes, &fl);
-            prog.flops_per_amp += fl;
-            r.a = (int32_t)prog.lops.size();
-            prog.lops.push_back(t);
-        } else {
-            const Op &op = *it.op;
-            auto reg_index = [&](int local_bit) {
-                for (int j = 0; j < rb; ++j)
-                    if (cur_reg[j] == local_bit) return j;
-                return -1;
-            };
-            std::vector<cd> U = dense_matrix(op);
-            r.ctrl = op.ctrl;
-            r.mat = (int64_t)(mats.size() / 2);
-            if (it.kind == dev::ROP_G1) {
-                r.a = reg_index(li[op.t[0]]);
-                for (const cd &v : U) push(mats, v);
-                prog.flops_per_amp += 14.0 / (double)(1ull << popc(op.ctrl));
-            } else {
-                const int j0 = reg_index(li[op.t[0]]), j1 = reg_index(li[op.t[1]]);
-                if (j0 < j1) {
-                    r.a = j0;
-                    r.b = j1;
-                    for (const cd &v : U) push(mats, v);
+                const int sj = slot_of(tq[j]);
+                if (sj >= 0) {
+                    for (int x = 0; x < nr; ++x)
+                        if ((x >> sj) & 1) r.wr[x] |= wgt;
                 } else {
-                    r.a = j1;
-                    r.b = j0;
-                    auto sw = [](int x) { return ((x & 1) << 1) | ((x >> 1) & 1); };
-                    for (int row = 0; row < 4; ++row)
-                        for (int col = 0; col < 4; ++col) push(mats, U[sw(row) * 4 + sw(col)]);
+                    const int t = thr_of(tq[j]);
+                    if (t >= lane_bits)
+                        for (int w = 0; w < nwaves; ++w)
+                            if ((w >> (t - lane_bits)) & 1) r.wwave[w] |= wgt;
                 }
-                prog.flops_per_amp += 30.0 / (double)(1ull << popc(op.ctrl));
             }
+            // lane thread-id bit t that is table bit j: bit t of lane_ok set,
+            // rd[t] = the bit's place in the byte offset (j + log2 eb)
+            r.lane_ok = 0;
+            for (int j = 0; j < kt; ++j) {
+                const int t = li[tq[j]] >= 0 && slot_of(tq[j]) < 0 ? thr_of(tq[j]) : -1;
+                if (t >= 0 && t < lane_bits) {
+                    r.lane_ok |= 1ull << t;
+                    r.rd[t] = (uint32_t)(j + __builtin_ctz(eb));
+                }
+            }
+            ImgBlock tab;
+            int changed = 0;
+            for (uint32_t row = 0; row < (1u << kt); ++row) {
+                uint64_t bits = octrl;
+                for (int j = 0; j < kt; ++j)
+                    if ((row >> j) & 1) bits |= 1ull << tq[j];
+                cd v(1, 0);
+                for (const Op &o : it.members) {
+                    if ((bits & o.ctrl) != o.ctrl) continue;
+                    uint32_t rix = 0;
+                    for (int j = 0; j < o.k; ++j)
+                        if ((bits >> o.t[j]) & 1) rix |= 1u << j;
+                    v *= o.U[rix];
+                }
+                if (v != cd(1, 0)) ++changed;
+                put_complex(tab.bytes, v, elem_bytes);
+            }
+            tab.align = std::max<uint32_t>(16u, eb << kt);
+            tab.op = (int)prog.rops.size();
+            tab.table = true;
+            if (octrl) {
+                // tiles that fail the controls outside the tile read ones
+                ImgBlock ones;
+                for (uint32_t row = 0; row < (1u << kt); ++row) put_complex(ones.bytes, cd(1, 0), elem_bytes);
+                ones.align = tab.align;
+                ones.op = tab.op;
+                ones.table = true;
+                ones.ones = true;
+                blocks.push_back(std::move(ones));
+            }
+            blocks.push_back(std::move(tab));
+            prog.diag_ops += 1;
+            prog.flops_per_amp += 6.0;
+            (void)changed;
+        } else {
+            const Op &op = it.op;
+            const bool two = op.k == 2;
+            const int j0 = slot_of(op.t[0]), j1 = two ? slot_of(op.t[1]) : -1;
+            const bool swap01 = two && j1 < j0;
+            r.a = swap01 ? j1 : j0;
+            r.b = two ? (swap01 ? j0 : j1) : 0;
+            // controls: register bits, thread-id bits (lane and wave masks),
+            // and bits outside the tile
+            r.lane_ok = ~0ull;
+            r.wave_ok = ~0u;
+            for (int p = 0; p < 64; ++p) {
+                if (!((op.ctrl >> p) & 1)) continue;
+                if (li[p] < 0) {
+                    r.octrl |= 1ull << p;
+                    continue;
+                }
+                const int sj = slot_of(p);
+                if (sj >= 0) {
+                    r.creg |= 1u << sj;
+                    continue;
+                }
+                const int t = thr_of(p);
+                if (t < lane_bits) {
+                    uint64_t lm = 0;
+                    for (int l = 0; l < 64; ++l)
+                        if ((l >> t) & 1) lm |= 1ull << l;
+                    r.lane_ok &= lm;
+                } else {
+                    uint32_t wm = 0;
+                    for (int w = 0; w < nwaves; ++w)
+                        if ((w >> (t - lane_bits)) & 1) wm |= 1u << w;
+                    r.wave_ok &= wm;
+                }
+            }
+            auto sw = [](int x) { return ((x & 1) << 1) | ((x >> 1) & 1); };
+            const int D = 1 << op.k;
+            const double frac = 1.0 / (double)(1ull << popc(op.ctrl));
+            int e = 0;
+            if (it.kind == dev::ROP_R1 || it.kind == dev::ROP_R2) {
+                for (int row = 0; row < D; ++row)
+                    for (int col = 0; col < D; ++col)
+                        r.md[e++] = swap01 ? it.rm[(size_t)sw(row) * D + sw(col)]
+                                           : it.rm[(size_t)row * D + col];
+                prog.flops_per_amp += frac * (two ? 14.0 : 6.0);
+            } else {
+                const std::vector<cd> U = dense_matrix(op);
+                for (int row = 0; row < D; ++row)
+                    for (int col = 0; col < D; ++col) {
+                        const cd v = swap01 ? U[(size_t)sw(row) * D + sw(col)] : U[(size_t)row * D + col];
+                        r.md[e++] = v.real();
+                        r.md[e++] = v.imag();
+                    }
+                prog.flops_per_amp += frac * (two ? 30.0 : 14.0);
+            }
+            for (int x = 0; x < 32; ++x) r.mf[x] = (float)r.md[x];
         }
         prog.rops.push_back(r);
     }
@@ -523,40 +887,251 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
     // 2.5 x the state for one pass of the 30-qubit brick circuit).  A final
     // remap to a layout without those bits in registers costs less.
     if (S & 0x7u) {
-        int gpos[32], c = 0;
-        for (int p = 0; p < 64; ++p)
-            if ((ps.tile >> p) & 1) gpos[c++] = p;
-        if (tb >= 2 && (gpos[cur_thr[0]] > 5 || gpos[cur_thr[1]] > 6)) {
+        if (tb >= 2 && (tpos[cur.thr[0]] > 5 || tpos[cur.thr[1]] > 6)) {
             uint32_t Sn = S & ~0x7u;
             for (int b = m - 1; b >= 3 && __builtin_popcount(Sn) < rb; --b) Sn |= 1u << b;
             int split = -1;
             for (int j = 0; j < rb && split < 0; ++j)
-                if ((Sn >> cur_reg[j]) & 1) split = j;
+                if ((Sn >> cur.reg[j]) & 1) split = j;
             if (split >= 0 && __builtin_popcount(Sn) == rb) {
-                dev::RegOp r{};
-                r.kind = dev::ROP_REMAP;
-                r.a = split;
-                set_layout(Sn, m, rb, r.reg_lbit, r.thr_lbit);
+                Layout nw = make_layout(Sn, m);
                 for (int j = 0; j < rb; ++j)
-                    if (r.reg_lbit[j] == cur_reg[split]) std::swap(r.reg_lbit[j], r.reg_lbit[split]);
-                std::memcpy(cur_reg, r.reg_lbit, 8);
-                std::memcpy(cur_thr, r.thr_lbit, 16);
-                prog.rops.push_back(r);
-                prog.remaps += 1;
+                    if (nw.reg[j] == cur.reg[split]) std::swap(nw.reg[j], nw.reg[split]);
+                emit_remap(nw, split);
                 S = Sn;
             }
         }
     }
-    fill_layouts(prog, rb, elem_bytes);
-    // the kernel runs ops in pairs: pad with an identity 1-qubit op
+    // The program runs once per tile with no barrier between tiles: a
+    // wave-local remap after the last workgroup remap is followed, in the
+    // next tile, by the first workgroup remap, which must then wait too.
+    if (local_since_barrier)
+        for (dev::RegOp &r : prog.rops)
+            if (r.kind == dev::ROP_REMAP && r.b != 1) {
+                r.b = 2;
+                break;
+            }
+    for (int j = 0; j < rb; ++j) prog.g_reg_f[j] = 1ull << tpos[cur.reg[j]];
+    for (int t = 0; t < tb; ++t) prog.g_thr_f[t] = 1ull << tpos[cur.thr[t]];
+    // the kernel runs ops in pairs: pad with an identity real 1-qubit op
     if (prog.rops.size() & 1) {
-        dev::RegOp nop{};
-        nop.kind = dev::ROP_G1;
-        nop.a = 0;
-        nop.mat = (int64_t)(mats.size() / 2);
-        push(mats, cd(1, 0)); push(mats, cd(0, 0)); push(mats, cd(0, 0)); push(mats, cd(1, 0));
-        prog.rops.push_back(nop);
+        dev::RegOp pad{};
+        pad.kind = dev::ROP_R1;
+        pad.lane_ok = ~0ull;
+        pad.wave_ok = ~0u;
+        pad.md[0] = pad.md[3] = 1.0;
+        pad.mf[0] = pad.mf[3] = 1.0f;
+        prog.rops.push_back(pad);
     }
+    // LDS image: tables first, largest first (each then sits at a multiple of
+    // its own size), then the lane words
+    std::vector<int> ord(blocks.size());
+    for (size_t b = 0; b < blocks.size(); ++b) ord[b] = (int)b;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+        if (blocks[x].table != blocks[y].table) return blocks[x].table;
+        return blocks[x].align > blocks[y].align;
+    });
+    uint32_t off = 0;
+    for (int b : ord) {
+        ImgBlock &blk = blocks[b];
+        off = (off + blk.align - 1) & ~(blk.align - 1);
+        blk.off = off;
+        off += (uint32_t)blk.bytes.size();
+    }
+    off = (off + 15u) & ~15u;
+    prog.img.assign(off, 0);
+    for (const ImgBlock &blk : blocks) {
+        std::memcpy(prog.img.data() + blk.off, blk.bytes.data(), blk.bytes.size());
+        if (blk.ones) prog.rops[blk.op].b = (int32_t)blk.off;
+        else if (blk.table) prog.rops[blk.op].mat = blk.off;
+        else prog.rops[blk.op].lane_off = blk.off;
+    }
+    return off;
+    };
+    // The widest tables that keep the image within kRegImageSoft (three
+    // workgroups per compute unit with a 12-bit complex128 tile); narrower
+    // tables mean more table ops but a smaller image.  An image past
+    // kRegImageMax sends the pass to the LDS-tile kernel.
+    static const int caps[] = {dev::kRegDiagMax, 6, 4, 3, 2};
+    uint32_t img = 0;
+    for (int cap : caps) {
+        img = lower(cap);
+        if (img <= dev::kRegImageSoft) break;
+    }
+    if (img > dev::kRegImageMax) {
+        mats.resize(mats_mark);
+        prog.rops.clear();
+        prog.img.clear();
+        prog.real_ops = prog.diag_ops = prog.remaps = prog.diag_merged = 0;
+        lds_program();
+    }
+}
+
+// ------------------------------------------------------------- host model
+std::string emulate_reg_pass(const TileProgram &prog, int rb, const std::vector<double> &mats,
+                             int elem_bytes, int n, std::vector<cd> &state) {
+    if (!prog.reg) return "not a register program";
+    const int m = prog.m, tb = m - rb, nt = 1 << tb, nr = 1 << rb;
+    if (n < m) return "state smaller than the tile";
+    uint8_t tpos[64];
+    int c = 0;
+    for (int p = 0; p < 64; ++p)
+        if ((prog.tile >> p) & 1) tpos[c++] = (uint8_t)p;
+    if (c != m) return "tile mask and m disagree";
+    const uint32_t half = (uint32_t)elem_bytes << (m - 1);
+    const size_t img = prog.img.size();
+    auto rd_u32 = [&](uint32_t off, uint32_t *out) -> bool {
+        if (off % 4 || (size_t)off + 4 > img) return false;
+        std::memcpy(out, prog.img.data() + off, 4);
+        return true;
+    };
+    auto rd_cplx = [&](uint32_t off, cd *out) -> bool {
+        if (off % (uint32_t)elem_bytes || (size_t)off + elem_bytes > img) return false;
+        if (elem_bytes == 16) {
+            double x[2];
+            std::memcpy(x, prog.img.data() + off, 16);
+            *out = cd(x[0], x[1]);
+        } else {
+            float x[2];
+            std::memcpy(x, prog.img.data() + off, 8);
+            *out = cd(x[0], x[1]);
+        }
+        return true;
+    };
+    auto gidx = [&](const uint64_t *g_reg, const uint64_t *g_thr, int t, int i) {
+        uint64_t x = 0;
+        for (int j = 0; j < rb; ++j)
+            if ((i >> j) & 1) x |= g_reg[j];
+        for (int s = 0; s < tb; ++s)
+            if ((t >> s) & 1) x |= g_thr[s];
+        return x;
+    };
+    const uint64_t n_tiles = 1ull << (n - m);
+    std::vector<cd> amp((size_t)nt * nr);
+    std::vector<cd> buf(half / elem_bytes);
+    std::vector<char> full(half / elem_bytes);
+    std::vector<char> seen((size_t)1 << m);
+    char msg[256];
+    for (uint64_t tile = 0; tile < n_tiles; ++tile) {
+        uint64_t base = tile;
+        for (int i = 0; i < m; ++i) {
+            const uint64_t lowm = (1ull << tpos[i]) - 1;
+            base = ((base & ~lowm) << 1) | (base & lowm);
+        }
+        for (int t = 0; t < nt; ++t)
+            for (int i = 0; i < nr; ++i) {
+                const uint64_t x = gidx(prog.g_reg, prog.g_thr, t, i);
+                if (x & ~prog.tile) return "load index outside the tile";
+                amp[(size_t)t * nr + i] = state[base | x];
+            }
+        for (size_t oi = 0; oi < prog.rops.size(); ++oi) {
+            const dev::RegOp &op = prog.rops[oi];
+            if (op.kind == dev::ROP_REMAP) {
+                const int J = op.a;
+                // a wave-local remap (b = 1) must keep every wave inside its
+                // own region of the buffer: no barrier orders it against the
+                // other waves
+                const uint32_t region = half >> (tb - 6);
+                auto in_region = [&](int t, uint32_t a) {
+                    return op.b != 1 || (a / region == (uint32_t)(t >> 6));
+                };
+                for (int p = 0; p < 2; ++p) {
+                    std::fill(full.begin(), full.end(), 0);
+                    for (int t = 0; t < nt; ++t) {
+                        uint32_t lw;
+                        if (!rd_u32(op.lane_off + 4 * (t & 63), &lw)) return "remap lane word out of the image";
+                        const uint32_t wt = lw ^ op.wwave[t >> 6];
+                        for (int i = 0; i < nr; ++i) {
+                            if (((i >> J) & 1) != p) continue;
+                            const uint32_t a = wt ^ op.wr[i];
+                            if (a % elem_bytes || a >= half) {
+                                std::snprintf(msg, sizeof msg, "op %zu: remap write at %u (buffer %u)", oi, a, half);
+                                return msg;
+                            }
+                            if (!in_region(t, a)) return "wave-local remap writes outside its wave's region";
+                            if (full[a / elem_bytes]) return "remap writes one slot twice";
+                            full[a / elem_bytes] = 1;
+                            buf[a / elem_bytes] = amp[(size_t)t * nr + i];
+                        }
+                    }
+                    for (int t = 0; t < nt; ++t) {
+                        uint32_t lw;
+                        if (!rd_u32(op.lane_off + 256 + 4 * (t & 63), &lw)) return "remap lane word out of the image";
+                        const uint32_t rt = lw ^ op.rwave[t >> 6];
+                        for (int i = 0; i < nr; ++i) {
+                            if (((i >> J) & 1) != p) continue;
+                            const uint32_t a = rt ^ op.rd[i];
+                            if (a % elem_bytes || a >= half) return "remap read outside the buffer";
+                            if (!in_region(t, a)) return "wave-local remap reads outside its wave's region";
+                            if (full[a / elem_bytes] != 1) return "remap reads a slot not written (or twice)";
+                            full[a / elem_bytes] = 2;
+                            amp[(size_t)t * nr + i] = buf[a / elem_bytes];
+                        }
+                    }
+                }
+                continue;
+            }
+            if (op.kind == dev::ROP_DIAG) {
+                uint32_t s_idx = (uint32_t)op.mat;
+                if ((base & op.octrl) != op.octrl) s_idx = (uint32_t)op.b;
+                for (int q = 0; q < op.a; ++q)
+                    if ((base >> op.gt[q]) & 1) s_idx ^= op.gtb[q];
+                for (int t = 0; t < nt; ++t) {
+                    uint32_t lw = 0;
+                    for (int b = 0; b < 6; ++b)
+                        if ((op.lane_ok >> b) & 1) lw |= (uint32_t)(((t & 63) >> b) & 1) << op.rd[b];
+                    const uint32_t v_idx = lw ^ s_idx ^ op.wwave[t >> 6];
+                    for (int i = 0; i < nr; ++i) {
+                        cd f;
+                        if (!rd_cplx(v_idx ^ op.wr[i], &f)) return "diag table read out of the image";
+                        amp[(size_t)t * nr + i] *= f;
+                    }
+                }
+                continue;
+            }
+            const bool two = op.kind == dev::ROP_G2 || op.kind == dev::ROP_R2;
+            const bool real = op.kind == dev::ROP_R1 || op.kind == dev::ROP_R2;
+            const int D = two ? 4 : 2;
+            auto mval = [&](int x) { return elem_bytes == 16 ? op.md[x] : (double)op.mf[x]; };
+            const int off[4] = {0, 1 << op.a, two ? (1 << op.b) : 0,
+                                two ? ((1 << op.a) | (1 << op.b)) : 0};
+            const int tmask = two ? ((1 << op.a) | (1 << op.b)) : (1 << op.a);
+            if ((base & op.octrl) != op.octrl) continue;
+            for (int t = 0; t < nt; ++t) {
+                if (!((op.wave_ok >> (t >> 6)) & 1)) continue;
+                if (!((op.lane_ok >> (t & 63)) & 1)) continue;
+                for (int i = 0; i < nr; ++i) {
+                    if (i & tmask) continue;
+                    if ((i & (int)op.creg) != (int)op.creg) continue;
+                    cd x[4], y[4];
+                    for (int cc = 0; cc < D; ++cc) x[cc] = amp[(size_t)t * nr + (i | off[cc])];
+                    for (int rr = 0; rr < D; ++rr) {
+                        y[rr] = 0;
+                        for (int cc = 0; cc < D; ++cc) {
+                            const size_t e = (size_t)rr * D + cc;
+                            const cd u = real ? cd(mval((int)e), 0.0)
+                                              : cd(mval(2 * (int)e), mval(2 * (int)e + 1));
+                            y[rr] += u * x[cc];
+                        }
+                    }
+                    for (int rr = 0; rr < D; ++rr) amp[(size_t)t * nr + (i | off[rr])] = y[rr];
+                }
+            }
+        }
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int t = 0; t < nt; ++t)
+            for (int i = 0; i < nr; ++i) {
+                const uint64_t x = gidx(prog.g_reg_f, prog.g_thr_f, t, i);
+                if (x & ~prog.tile) return "store index outside the tile";
+                uint64_t lx = 0;
+                for (int b = 0; b < m; ++b)
+                    if ((x >> tpos[b]) & 1) lx |= 1ull << b;
+                if (seen[lx]) return "store writes one amplitude twice";
+                seen[lx] = 1;
+                state[base | x] = amp[(size_t)t * nr + i];
+            }
+    }
+    return "";
 }
 
 }  // namespace qsv

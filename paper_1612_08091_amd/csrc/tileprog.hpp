@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "device.hpp"
@@ -19,8 +20,14 @@ struct TileProgram {
     uint8_t thr_lbit[16] = {};
     uint64_t g_reg[8] = {};             // initial layout as global index bits
     uint64_t g_thr[16] = {};
+    uint64_t g_reg_f[8] = {};           // layout at store time
+    uint64_t g_thr_f[16] = {};
+    std::vector<unsigned char> img;     // LDS image (register kernel): tables, lane words
     int remaps = 0;                     // layout changes through LDS
-    int diag_merged = 0;                // diagonal ops folded into a preceding one
+    int local_remaps = 0;               // of which within each wave (no workgroup barrier)
+    int diag_merged = 0;                // diagonal ops folded into another
+    int real_ops = 0;                   // register ops split into phases x real matrix
+    int diag_ops = 0;                   // DIAG ops of the register program
     int mfma_k = 0;                     // widest matrix-core op (LDS kernel)
     double flops_per_amp = 0.0;
 };
@@ -44,6 +51,22 @@ uint32_t swz_elem(uint32_t l, int elem_bytes);
 // index, XOR-swizzled against bank conflicts, times elem_bytes.  Linear over
 // GF(2) in l.
 uint32_t remap_offset(uint32_t l, int kept, int elem_bytes);
+
+// Real split of a k-qubit matrix (Sec. 4.3.2's fused gates, applied with less
+// arithmetic): find unit-modulus l[r], rr[c] with U[r][c] = l[r] M[r][c] rr[c]
+// and M real (up to an imaginary residue of 1e-14 per entry, dropped).
+// Returns false when no such split exists.
+bool real_split(const std::vector<cd> &U, int k, std::vector<cd> &l, std::vector<double> &M,
+                std::vector<cd> &rr);
+
+// Host model of the register-resident tile kernel: runs the program of a
+// lowered pass on every tile of `state` (2^n complex amplitudes, in place),
+// thread by thread and register by register, with the kernel's layouts, LDS
+// byte offsets and image lookups, each bounds-checked.  A check of the
+// lowering on the CPU; no product path calls it.  Returns "" on success, else
+// the first violation found.
+std::string emulate_reg_pass(const TileProgram &prog, int rb, const std::vector<double> &mats,
+                             int elem_bytes, int n, std::vector<cd> &state);
 
 // LDS-kernel form of one op; li maps a global bit position to its tile bit
 // (-1 outside the tile); elem_bytes is the state's complex size (16 or 8).

@@ -113,6 +113,8 @@ _SIGS = {
     "qsv_get_kernel_times": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "qsv_reset_stats": (ctypes.c_int, [_P]),
     "qsv_plan": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
+    "qsv_check_tile_programs": (ctypes.c_int, [_P, _P, _P]),
+    "qsv_copy_probe": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P]),
     "qsv_adjoint_gradient": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "qsv_batch_create": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P]),
     "qsv_batch_run": (ctypes.c_int, [_P, _P]),
@@ -174,7 +176,7 @@ class Simulator:
     Qubit ids come from ``allocate``; gates are queued by ``apply`` and run on
     ``flush`` or on any call that reads the state (ProjectQ Sec. 4.3.2)."""
 
-    def __init__(self, n_max: int = 30, dtype="c128", mode="tiled", k_max: int = 3,
+    def __init__(self, n_max: int = 30, dtype="c128", mode="tiled", k_max: int = 2,
                  tile_bits: int = 0, queue_limit: int = 0, stream=None, state=None,
                  use_torch_stream: bool = True, timing: bool = False, reg_bits: int = 0):
         opt = Options()
@@ -434,6 +436,32 @@ class Simulator:
             mat = mats[i * 2048: i * 2048 + 2 * d * d].view(np.complex128).reshape(d, d).copy()
             ops.append((mat, tg[5 * i: 5 * i + k].tolist(), int(cm[i])))
         return ops, npass.value
+
+    def check_tile_programs(self, state: np.ndarray):
+        """Run the register-tile programs planned for the queued gates on a
+        host copy of ``state`` (complex128, 2^n) through the library's host
+        model of the kernel (qsv_check_tile_programs); returns (new state,
+        counts).  ``state`` None: lower only, for the counts.  A test of the
+        lowering; nothing runs on the device."""
+        buf = None if state is None else np.ascontiguousarray(state, dtype=np.complex128).copy()
+        info = np.zeros(9, dtype=np.int32)
+        _check(lib.qsv_check_tile_programs(self._h, _ptr(buf), _ptr(info)), self._h)
+        keys = ("passes", "reg_passes", "real_ops", "diag_ops", "remaps", "max_image",
+                "instructions", "diag_merged", "local_remaps")
+        return buf, dict(zip(keys, info.tolist()))
+
+
+def copy_probe(src, dst, stream=None):
+    """Enqueue the library's streaming copy of torch tensor ``src`` into
+    ``dst`` (same byte size, device memory) on ``stream`` (default: torch's
+    current stream); the caller times it."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy_probe: sizes differ")
+    if stream is None:
+        stream = _torch_stream()
+    _check(lib.qsv_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                              nbytes, stream))
 
 
 # ---------------------------------------------------------------------------

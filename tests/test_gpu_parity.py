@@ -607,3 +607,71 @@ def test_simcomparison_22q_walsh_closed_form(mode, k_max):
             phi += np.where(on, np.where(((xs >> t) & 1) == 1, half, -half), 0.0)
     want = _fwht(np.exp(1j * phi)) / float(1 << n)
     check_c128(got, want, 1e-12)
+
+
+# ------------------------------------------------- the headline path at size
+_C1 = {}
+
+
+def _config1(n):
+    if n not in _C1:
+        circ = W.config1_random(n)
+        _C1[n] = (circ, oracle.run(circ))
+    return _C1[n]
+
+
+@pytest.mark.parametrize("n", [22, 23])
+def test_headline_brick_register_tiles_vs_oracle(n):
+    """The 40-layer Haar + CNOT brick circuit of the 30-qubit benchmark, at
+    22 and 23 qubits, on the benchmark's path: mode tiled, k_max 2, 12-bit
+    tiles of 16 amplitudes per thread, complex128.  2^(n-12) = 1024 / 2048
+    tiles exceed the resident workgroups, so each persistent workgroup runs
+    several tiles.  Every amplitude against the oracle at 1e-12 (A12)."""
+    circ, want = _config1(n)
+    log("case headline brick", n)
+    s = make(n, mode="tiled", k_max=2, tile_bits=12, reg_bits=4, timing=True)
+    s.run(circ)
+    # the lowering the flush will run (host side, nothing executes): every
+    # pass is a register-tile program, most ops split into real matrices
+    _, info = s.check_tile_programs(None)
+    assert info["reg_passes"] == info["passes"]
+    assert info["real_ops"] >= 0.9 * (len(circ.gates) - n * 40) and info["diag_ops"] > 0
+    got = s.get_state()
+    _, launches, _ = s.kernel_times()["tile"]
+    assert launches == info["passes"]
+    check_c128(got, want)
+    assert abs(s.norm2() - 1.0) <= 1e-12
+    s.close()
+
+
+def test_headline_brick_30q_tiled_equals_pergate_every_amplitude():
+    """At the benchmark size (30 qubits, 16 GiB per state): the tiled k = 2
+    state against the plain per-gate FP64 state, every one of the 2^30
+    amplitudes, compared on the device in chunks (max |diff| <= 1e-12)."""
+    import torch
+    n = 30
+    circ = W.config1_random(n)
+    log("case headline brick 30q tiled vs pergate")
+    bufs = []
+    for mode, k in [("tiled", 2), ("pergate", 1)]:
+        buf = torch.empty(2 << n, dtype=torch.float64, device="cuda")
+        s = Q.Simulator(n_max=n, mode=mode, k_max=k, state=buf, use_torch_stream=False)
+        s.allocate(n)
+        s.run(circ)
+        s.flush()
+        s.synchronize()
+        s.close()
+        bufs.append(buf)
+        log("  %s done" % mode)
+    torch.cuda.synchronize()
+    worst = 0.0
+    chunk = 1 << 28
+    for i in range(0, 2 << n, chunk):
+        d = (bufs[0][i:i + chunk] - bufs[1][i:i + chunk]).view(-1, 2)
+        worst = max(worst, float(torch.sqrt((d * d).sum(dim=1)).max()))
+    norm = float((bufs[0] * bufs[0]).sum())
+    del bufs
+    torch.cuda.empty_cache()
+    log("  max |tiled - pergate| = %.3g, norm2 = %.15f" % (worst, norm))
+    assert worst <= 1e-12
+    assert abs(norm - 1.0) <= 1e-11
