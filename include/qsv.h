@@ -213,6 +213,25 @@ qsv_status qsv_synchronize(qsv_sim *sim);
 qsv_status qsv_get_probability(qsv_sim *sim, int32_t m, const int32_t *qubits,
                                const int8_t *bits, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sum of
+ * qsv_get_probability, computed by the same kernels on a caller-owned device
+ * state of 2^n amplitudes (dtype QSV_C128 or QSV_C64, interleaved) over the
+ * indices whose bit positions[j] equals bits[j] for all j < m (positions are
+ * bit positions, not qubit ids; m = 0: the squared norm).  The double result
+ * goes to the device address out_dev; the work is enqueued on `stream` (a
+ * hipStream_t, NULL = null stream) and nothing synchronises.  No device
+ * memory is allocated and no HIP allocation routine is called: the partial
+ * sums (at most 1024 doubles, 8 KiB) live in a static device array of the
+ * library, one per GPU, held until the process ends; every call writes the
+ * slots it reads.  Calls that overlap on one GPU race on that array.
+ * EINVAL: NULL pointer, bad dtype, n outside 0..36, m outside 0..n, a
+ * position outside 0..n-1 or repeated, or partial sums beyond the array;
+ * EDEVICE: a HIP call failed (qsv_last_error(NULL) says which). */
+qsv_status qsv_get_probability_noalloc(const void *state, int32_t dtype, int32_t n, int32_t m,
+                                       const int32_t *positions, const int8_t *bits,
+                                       double *out_dev, void *stream);
+
 /* All 2^n probabilities |psi_i|^2 as doubles into out (host memory if
  * out_is_device == 0, else a device pointer).  Flushes; synchronises. */
 qsv_status qsv_get_probabilities(qsv_sim *sim, double *out, int32_t out_is_device);

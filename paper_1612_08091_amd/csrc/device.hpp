@@ -169,6 +169,12 @@ size_t reduce_workspace_bytes(int nq);
 // Sum of |psi_i|^2 over the indices matching (ia): out_dev[0].
 hipError_t prob_masked(int dtype, const void *psi, uint64_t ngroups, const IndexArgs &ia,
                        double *ws, double *out_dev, hipStream_t s);
+// The same with the partial sums in a static device array of the library
+// (no allocation); hipErrorInvalidValue if they would not fit.
+hipError_t prob_masked_noalloc(int dtype, const void *psi, uint64_t ngroups, const IndexArgs &ia,
+                               double *out_dev, hipStream_t s);
+int prob_noalloc_partials(uint64_t ngroups);   // partial sums a call needs
+int prob_noalloc_capacity();                   // partial sums the array holds
 // p0 (bit q = 0) and p1 (bit q = 1): out_dev[0..1].
 hipError_t prob_split(int dtype, const void *psi, int nq, int q, double *ws, double *out_dev,
                       hipStream_t s);

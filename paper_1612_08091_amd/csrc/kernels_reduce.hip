@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "device.hpp"
 
@@ -103,6 +104,50 @@ __global__ __launch_bounds__(kRedThreads) void k_finish(const double *partial, i
 }
 
 size_t reduce_workspace_bytes(int) { return sizeof(double) * 2 * kRedBlocks; }
+
+// --------------------------------------------------- allocation-free form
+// Partial sums of prob_masked_noalloc: one per block of k_prob_masked (at most
+// kRedBlocks).  Every GPU holds its own copy until the process ends; each call
+// writes the slots it reads, so nothing needs clearing, and calls that overlap
+// on one GPU race on it.
+constexpr int kScratchDoubles = kRedBlocks;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's `scratch` (resolved once per device, with the
+// device current; host code never uses the array's own name).
+hipError_t scratch_ptr(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+int prob_noalloc_partials(uint64_t ngroups) { return (int)red_grid(ngroups); }
+int prob_noalloc_capacity() { return kScratchDoubles; }
+
+hipError_t prob_masked_noalloc(int dtype, const void *psi, uint64_t ngroups, const IndexArgs &ia,
+                               double *out_dev, hipStream_t s) {
+    if ((int)red_grid(ngroups) > kScratchDoubles) return hipErrorInvalidValue;
+    double *ws = nullptr;
+    const hipError_t e = scratch_ptr(&ws);
+    if (e != hipSuccess) return e;
+    return prob_masked(dtype, psi, ngroups, ia, ws, out_dev, s);
+}
 
 hipError_t prob_masked(int dtype, const void *psi, uint64_t ngroups, const IndexArgs &ia,
                        double *ws, double *out_dev, hipStream_t s) {

@@ -1024,6 +1024,34 @@ qsv_status qsv_get_probability(qsv_sim *s, int32_t m, const int32_t *qubits, con
     return sync(s);
 }
 
+qsv_status qsv_get_probability_noalloc(const void *state, int32_t dtype, int32_t n, int32_t m,
+                                       const int32_t *positions, const int8_t *bits,
+                                       double *out_dev, void *stream) {
+    if (!state || !out_dev) return fail(nullptr, QSV_EINVAL, "NULL state or output");
+    if (dtype != QSV_C128 && dtype != QSV_C64) return fail(nullptr, QSV_EINVAL, "bad dtype");
+    if (n < 0 || n > qsv::kMaxQubits) return fail(nullptr, QSV_EINVAL, "n outside 0..36");
+    if (m < 0 || m > n || (m > 0 && (!positions || !bits)))
+        return fail(nullptr, QSV_EINVAL, "bad mask (m outside 0..n or NULL arrays)");
+    uint64_t mask = 0, ones = 0;
+    for (int j = 0; j < m; ++j) {
+        const int p = positions[j];
+        if (p < 0 || p >= n || ((mask >> p) & 1))
+            return fail(nullptr, QSV_EINVAL, "position outside 0..n-1 or repeated");
+        mask |= 1ull << p;
+        if (bits[j]) ones |= 1ull << p;
+    }
+    const uint64_t ngroups = 1ull << (n - m);
+    if (qsv::dev::prob_noalloc_partials(ngroups) > qsv::dev::prob_noalloc_capacity())
+        return fail(nullptr, QSV_EINVAL, "partial sums exceed the static scratch array");
+    qsv::dev::IndexArgs ia;
+    index_args(mask, ones, ia);
+    const hipError_t e = qsv::dev::prob_masked_noalloc(dtype, state, ngroups, ia, out_dev,
+                                                       (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(nullptr, QSV_EDEVICE, std::string("qsv_get_probability_noalloc: ") + hipGetErrorString(e));
+    return QSV_OK;
+}
+
 qsv_status qsv_get_probabilities(qsv_sim *s, double *out, int32_t out_is_device) {
     QSV_CHECK(s);
     if (!out) return fail(s, QSV_EINVAL, "NULL output");

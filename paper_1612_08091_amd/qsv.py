@@ -115,6 +115,8 @@ _SIGS = {
     "qsv_plan": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     "qsv_check_tile_programs": (ctypes.c_int, [_P, _P, _P]),
     "qsv_copy_probe": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P]),
+    "qsv_get_probability_noalloc": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32,
+                                                   ctypes.c_int32, _P, _P, _P, _P]),
     "qsv_adjoint_gradient": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "qsv_batch_create": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P]),
     "qsv_batch_run": (ctypes.c_int, [_P, _P]),
