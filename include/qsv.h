@@ -80,6 +80,11 @@ typedef struct qsv_options {
     int32_t reg_bits;       /* amplitudes per thread = 2^reg_bits in the register-resident
                                tile kernel (3..5; tile_bits - reg_bits thread bits must be
                                8 or 9), 0 = default */
+    int32_t relabel;        /* mode TILED, 1 (default): a pass may move its qubits to other
+                               bit positions within its tile, so that the positions every
+                               tile holds carry qubits in use and tiles span few 2 MiB
+                               pages; every flush ends with each qubit back at its own
+                               position.  0: positions never move */
 } qsv_options;
 
 /* Kernel classes reported by qsv_get_kernel_times. */
@@ -104,7 +109,8 @@ typedef struct qsv_stats {
     double amp_gate_updates;/* sum over original gates of 2^n */
 } qsv_stats;
 
-/* Fill *opt with defaults: n_max 30, C128, mode TILED, k_max 2, tile_bits 0. */
+/* Fill *opt with defaults: n_max 30, C128, mode TILED, k_max 2, tile_bits 0,
+ * relabel 1. */
 qsv_status qsv_options_default(qsv_options *opt);
 
 /* Create a simulator holding 0 qubits (state |>).  No device memory is
@@ -329,10 +335,12 @@ qsv_status qsv_plan(qsv_sim *sim, int32_t *n_ops, int32_t *n_passes, int32_t max
  * lists on the host over state[2 * 2^n] (complex128, interleaved, updated in
  * place) thread by thread, with the kernel's layouts, LDS byte offsets and
  * table lookups, every address bounds-checked.  state NULL: lower only (for
- * the counts).  No device call; the queue is kept.  info[9] (may be NULL)
+ * the counts).  No device call; the queue is kept.  info[10] (may be NULL)
  * receives: passes, register passes, real-split ops, table (diagonal) ops,
  * layout changes, largest LDS image in bytes, instructions, diagonal ops
- * merged into another, layout changes within each wave (no barrier).  EINVAL: not in mode TILED, or an address check
+ * merged into another, layout changes within each wave (no barrier), passes
+ * that move qubits to other positions (option relabel).  The state comes
+ * out with every qubit at its own position.  EINVAL: not in mode TILED, or an address check
  * failed (qsv_last_error names it); EUNSUPPORTED: a pass needs the LDS-tile
  * kernel (an op wider than 2 qubits, or too many tables). */
 qsv_status qsv_check_tile_programs(qsv_sim *sim, double *state, int32_t *info);

@@ -67,6 +67,8 @@ struct TileArgs {
     int32_t no_diag;      // register kernel: 1 if the program has no ROP_DIAG op (a
                           // leaner kernel instance without that case runs it)
     uint32_t img_bytes;   // register kernel: bytes of the pass's LDS image (multiple of 16)
+    int32_t store_sync;   // register kernel: 1 = workgroup barrier between the ops and the
+                          // stores (the stores go where other threads loaded)
     int64_t img_off;      // register kernel: byte offset of the LDS image in the pool
     uint64_t g_reg[8];    // register kernel, layout at load time: global index bit of
                           // register bit j, and of thread-id bit i
@@ -74,6 +76,9 @@ struct TileArgs {
     uint64_t g_reg_f[8];  // register kernel, layout at store time (after the last remap)
     uint64_t g_thr_f[16];
     uint64_t dep_hi[64];  // LDS kernel: global offset of local index 256 * i (tile bits >= 8)
+    uint32_t spos[40];    // LDS kernel, stores: position of tile bit i (== tpos[i] unless
+                          // the pass relabels its qubits)
+    uint64_t dep_hi_f[64];// LDS kernel, stores: dep_hi over spos
 };
 
 // One operation of the register-resident tile kernel.

@@ -47,6 +47,7 @@ __global__ __launch_bounds__(kNT) void k_tile_lds(typename VT<R>::T *__restrict_
     const uint32_t tid = threadIdx.x;
     // this thread's share of every tile: local indices j + tid, j = 0, kNT, ...
     const uint64_t dep_tid = deposit_bits(tid & (tsize - 1), ta.tpos, m);
+    const uint64_t dep_tid_f = deposit_bits(tid & (tsize - 1), ta.spos, m);
     const uint32_t swz_tid = swz<R>(tid & (tsize - 1));
     const uint32_t n_tiles = (uint32_t)ta.n_tiles;
     if (tid == 0) s_tile = atomicAdd(counter, 1u);
@@ -92,12 +93,12 @@ __global__ __launch_bounds__(kNT) void k_tile_lds(typename VT<R>::T *__restrict_
                 for (int u = 0; u < 8; ++u) v[u] = tile[swz_tid ^ swz<R>(j0 + u * kNT)];
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    psi[base | dep_tid | ta.dep_hi[(j0 >> 8) + u]] = v[u];
+                    psi[base | dep_tid_f | ta.dep_hi_f[(j0 >> 8) + u]] = v[u];
             }
         } else {
             for (uint32_t j = 0; j < tsize; j += kNT)
                 if (j + tid < tsize)
-                    psi[base | dep_tid | ta.dep_hi[j >> 8]] = tile[swz_tid ^ swz<R>(j)];
+                    psi[base | dep_tid_f | ta.dep_hi_f[j >> 8]] = tile[swz_tid ^ swz<R>(j)];
         }
         if (tid == 0) s_tile = next;
         __syncthreads();
@@ -549,6 +550,9 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
             reg_op<T, R, NR, RB, DG>(amp, ops[oi], lds, limg, base, lane, wave);
             reg_op<T, R, NR, RB, DG>(amp, ops[oi + 1], lds, limg, base, lane, wave);
         }
+        // a pass that moves its qubits stores where other threads loaded:
+        // every load of the tile completes before the first store
+        if (ta.store_sync) __syncthreads();
         __builtin_amdgcn_s_setprio(2);
         T *sp = psi + gs;
         asm volatile("" : "+v"(sp));

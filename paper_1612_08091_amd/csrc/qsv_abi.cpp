@@ -286,6 +286,7 @@ void account(qsv_sim *s, double touched_amps, double flops_per_amp) {
 }
 
 qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes);
+std::vector<Pass> plan_flush(const qsv_sim *s, const std::vector<Op> &ops, int m);
 
 // Register bits per thread of the register-resident tile kernel.
 int reg_bits_for(const qsv_sim *s) {
@@ -410,7 +411,7 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
     for (size_t pi = 0; pi < passes.size(); ++pi) {
         const qsv::TileProgram &pg = progs[pi];
         const size_t nr = pg.rops.size(), nl = pg.lops.size();
-        if ((pg.reg && nr == 0) || (!pg.reg && nl == 0)) {
+        if (((pg.reg && nr == 0) || (!pg.reg && nl == 0)) && !pg.permutes) {
             ro += nr;
             lo += nl;
             continue;
@@ -428,14 +429,20 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
         std::memcpy(ta.g_reg_f, pg.g_reg_f, sizeof(ta.g_reg_f));
         std::memcpy(ta.g_thr_f, pg.g_thr_f, sizeof(ta.g_thr_f));
         ta.img_bytes = (uint32_t)pg.img.size();
+        ta.store_sync = pg.store_sync ? 1 : 0;
         ta.img_off = (int64_t)img_at[pi];
         ta.rb = rb;
         ta.mfma_k = pg.mfma_k;
+        for (int b = 0; b < pg.m; ++b) ta.spos[b] = pg.spos[b];
         for (int i = 0; i < 64 && (i << 8) < (1 << pg.m); ++i) {
-            uint64_t d = 0;
+            uint64_t d = 0, f = 0;
             for (int b = 8; b < pg.m; ++b)
-                if (((i << 8) >> b) & 1) d |= 1ull << ta.tpos[b];
+                if (((i << 8) >> b) & 1) {
+                    d |= 1ull << ta.tpos[b];
+                    f |= 1ull << ta.spos[b];
+                }
             ta.dep_hi[i] = d;
+            ta.dep_hi_f[i] = f;
         }
         const int tok = tbegin(s);
         if (pg.reg) {
@@ -471,6 +478,13 @@ int tile_bits_for(const qsv_sim *s) {
     return std::min(m, qsv::dev::tile_pass_max_bits(s->opt.dtype));
 }
 
+// Tiled plan of a flush.  The page bit is the amplitude index bit of a 2 MiB
+// page: 17 for 16-byte amplitudes, 18 for 8-byte ones.
+std::vector<Pass> plan_flush(const qsv_sim *s, const std::vector<Op> &ops, int m) {
+    const int page_bit = s->elem() == 16 ? 17 : 18;
+    return qsv::plan_tiled(ops, s->n, m, s->opt.k_max, page_bit, s->opt.relabel != 0);
+}
+
 std::vector<Op> canonical_queue(const qsv_sim *s, uint64_t *dropped) {
     std::vector<Op> ops;
     ops.reserve(s->queue.size());
@@ -500,7 +514,7 @@ qsv_status do_flush(qsv_sim *s) {
         for (const Op &op : f) QSV_TRY(launch_op(s, op));
     } else {
         const int m = std::min(tile_bits_for(s), s->n);
-        std::vector<Pass> passes = qsv::plan_tiled(ops, s->n, m, s->opt.k_max);
+        std::vector<Pass> passes = plan_flush(s, ops, m);
         for (const Pass &p : passes) s->stats.fused_ops += p.ops.size();
         QSV_TRY(run_tile_passes(s, passes));
     }
@@ -603,6 +617,7 @@ qsv_status qsv_options_default(qsv_options *opt) {
     opt->k_max = 2;
     opt->tile_bits = 0;
     opt->queue_limit = 0;
+    opt->relabel = 1;
     return QSV_OK;
 }
 
@@ -624,6 +639,8 @@ qsv_status qsv_create(const qsv_options *opt, qsv_sim **out) {
     if (opt->timing != 0 && opt->timing != 1) return fail(nullptr, QSV_EINVAL, "timing must be 0 or 1");
     if (opt->reg_bits != 0 && (opt->reg_bits < 3 || opt->reg_bits > 5))
         return fail(nullptr, QSV_EINVAL, "reg_bits must be 0 or 3..5");
+    if (opt->relabel != 0 && opt->relabel != 1)
+        return fail(nullptr, QSV_EINVAL, "relabel must be 0 or 1");
     const int elem = opt->dtype == QSV_C128 ? 16 : 8;
     if (opt->state) {
         if (opt->state_bytes < (uint64_t)elem << opt->n_max)
@@ -1368,11 +1385,11 @@ qsv_status qsv_check_tile_programs(qsv_sim *s, double *state, int32_t *info) {
     if (s->opt.mode != QSV_MODE_TILED) return fail(s, QSV_EINVAL, "handle is not in tiled mode");
     std::vector<Op> ops = canonical_queue(s, nullptr);
     const int m = std::min(tile_bits_for(s), s->n);
-    std::vector<Pass> passes = qsv::plan_tiled(ops, s->n, m, s->opt.k_max);
+    std::vector<Pass> passes = plan_flush(s, ops, m);
     const int rb = reg_bits_for(s);
     std::vector<cd> psi(state ? s->dim() : 0);
     for (uint64_t i = 0; state && i < s->dim(); ++i) psi[i] = cd(state[2 * i], state[2 * i + 1]);
-    int32_t counts[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t counts[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (const Pass &ps : passes) {
         std::vector<double> mats;
         qsv::TileProgram pg;
@@ -1398,6 +1415,7 @@ qsv_status qsv_check_tile_programs(qsv_sim *s, double *state, int32_t *info) {
         counts[6] += (int32_t)pg.rops.size();
         counts[7] += pg.diag_merged;
         counts[8] += pg.local_remaps;
+        counts[9] += pg.permutes ? 1 : 0;
         if (log_level() >= 3) {
             auto pos = [](uint64_t g) { return g ? __builtin_ctzll(g) : -1; };
             std::fprintf(stderr, "pass %d: load lanes", counts[0] - 1);
@@ -1437,10 +1455,9 @@ qsv_status qsv_plan(qsv_sim *s, int32_t *n_ops, int32_t *n_passes, int32_t max_o
         np = (int)flat.size();
     } else {
         const int m = std::min(tile_bits_for(s), s->n);
-        std::vector<Pass> passes = qsv::plan_tiled(ops, s->n, m, s->opt.k_max);
+        std::vector<Pass> passes = plan_flush(s, ops, m);
         np = (int)passes.size();
-        for (auto &p : passes)
-            for (auto &o : p.ops) flat.push_back(o);
+        flat = qsv::pass_ops_in_qubit_order(passes, s->n);
     }
     if (n_ops) *n_ops = (int32_t)flat.size();
     if (n_passes) *n_passes = np;
@@ -1561,7 +1578,7 @@ qsv_status run_ops(qsv_sim *s, const std::vector<Op> &ops) {
         return QSV_OK;
     }
     const int m = std::min(tile_bits_for(s), s->n);
-    return run_tile_passes(s, qsv::plan_tiled(ops, s->n, m, s->opt.k_max));
+    return run_tile_passes(s, plan_flush(s, ops, m));
 }
 
 // Tile bits of the tiled reverse sweep: two tiles (psi, phi) per workgroup,

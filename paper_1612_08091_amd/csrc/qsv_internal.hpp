@@ -76,6 +76,10 @@ std::vector<Op> fuse(const std::vector<Op> &ops, int k_max);
 struct Pass {
     uint64_t tile = 0;            // bit positions inside a tile
     std::vector<Op> ops;
+    // Relabeling: empty, or dest[p] = the position that the content of
+    // position p (its qubit) occupies after the pass; a permutation of the
+    // tile's positions, identity outside it.
+    std::vector<uint8_t> dest;
 };
 
 // Greedy grouping behind the pass planner, on plain bit masks: item i needs
@@ -103,10 +107,40 @@ std::vector<PlanGroup> plan_groups(const std::vector<PlanItem> &items, int n, in
 std::vector<Pass> plan_passes(const std::vector<Op> &ops, int n, int m, int low_bits,
                               int k_max, int kd_max = 0);
 
+// The op with its qubit positions moved: position p -> pos[p] (controls and
+// targets; targets come out ascending, the matrix permuted to match).
+Op relabel_op(const Op &o, const int *pos);
+
+// Pass planning with relabeling.  Every pass may also permute the positions
+// of its tile (a permutation of where its qubits live, free in a pass that
+// reads and writes the whole tile anyway).  Ops are planned on qubits; a pass
+// takes its ops at the positions its qubits hold when it runs.  After each
+// pass the qubits needed again soonest take the lowest tile positions: the
+// `low_bits` positions present in every tile then hold useful qubits, and
+// later tiles touch few positions at or above `page_bit` (one position there
+// doubles the 2 MiB pages a tile spans).  Trailing passes without ops restore
+// the identity, so the plan as a whole applies the ops and nothing else.
+std::vector<Pass> plan_passes_relabel(const std::vector<Op> &ops, int n, int m, int low_bits,
+                                      int k_max, int kd_max, int page_bit, int page_cap,
+                                      int op_cap = 1 << 30);
+
+// The ops of a plan in execution order, each on its qubits' own positions
+// (the positions in effect when no pass relabels).
+std::vector<Op> pass_ops_in_qubit_order(const std::vector<Pass> &passes, int n);
+
+// Estimated time of a plan in passes over the state, each weighted by the
+// number of 2 MiB pages its tile spans (a tile spread over 2^h pages reads
+// far slower once h passes about 5).
+double plan_cost(const std::vector<Pass> &passes, int page_bit);
+
 // Whole-queue fusion to k_max first (diagonal runs to kMaxK qubits), then
 // pass planning of the fused ops (blocks are not cut at pass boundaries);
-// three low bits stay in every tile for contiguous HBM runs.
-std::vector<Pass> plan_tiled(const std::vector<Op> &ops, int n, int m, int k_max);
+// three low bits stay in every tile for contiguous HBM runs.  relabel: also
+// plan with plan_passes_relabel under several page caps and keep the plan of
+// least plan_cost (page_bit: the amplitude index bit of a 2 MiB page, 17 for
+// complex128 and 18 for complex64).
+std::vector<Pass> plan_tiled(const std::vector<Op> &ops, int n, int m, int k_max,
+                             int page_bit = 64, bool relabel = false);
 
 // Dense 2^k x 2^k matrix of an op on its own target list (controls excluded).
 std::vector<cd> dense_matrix(const Op &op);

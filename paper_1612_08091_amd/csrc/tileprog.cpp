@@ -320,6 +320,17 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
         }
     }
     prog.m = m;
+    // store position of each tile bit (a relabeling pass moves its qubits)
+    uint8_t spos[64];
+    for (int b = 0; b < m; ++b) {
+        spos[b] = ps.dest.empty() ? tpos[b] : ps.dest[tpos[b]];
+        prog.spos[b] = spos[b];
+        if (spos[b] != tpos[b]) prog.permutes = true;
+    }
+    // A relabeling pass stores amplitudes to addresses that other threads of
+    // the workgroup load (of other waves too): all loads must be complete
+    // before the first store.
+    prog.store_sync = prog.permutes;
     const int tb = m - rb;
     prog.reg = rb >= 3 && rb <= 5 && (tb == 8 || (tb == 9 && rb <= 4));
     // the register kernel runs 1- and 2-qubit ops on tile qubits and diagonal ops
@@ -886,7 +897,44 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
     // lines, and the memory system writes them out more than once (measured:
     // 2.5 x the state for one pass of the 30-qubit brick circuit).  A final
     // remap to a layout without those bits in registers costs less.
-    if (S & 0x7u) {
+    if (prog.permutes) {
+        // A relabeling pass stores to other positions: the tile bits of the
+        // three lowest store positions must be lane bits (each store
+        // instruction then writes whole 128-byte lines).
+        int ord[32];
+        for (int b = 0; b < m; ++b) ord[b] = b;
+        std::sort(ord, ord + m, [&](int x, int y) { return spos[x] < spos[y]; });
+        const uint32_t low3 = (1u << ord[0]) | (1u << ord[1]) | (1u << ord[2]);
+        bool lanes_ok = true;
+        for (int c = 0; c < 3; ++c) {
+            bool in_lane = false;
+            for (int t = 0; t < lane_bits && t < tb; ++t)
+                if (cur.thr[t] == ord[c]) in_lane = true;
+            lanes_ok = lanes_ok && in_lane;
+        }
+        if (!lanes_ok) {
+            uint32_t Sn = S & ~low3;
+            for (int k = m - 1; k >= 0 && __builtin_popcount(Sn) < rb; --k)
+                if (!((low3 >> ord[k]) & 1)) Sn |= 1u << ord[k];
+            int split = -1;
+            for (int j = 0; j < rb && split < 0; ++j)
+                if ((Sn >> cur.reg[j]) & 1) split = j;
+            if (split >= 0 && __builtin_popcount(Sn) == rb) {
+                Layout nw;
+                std::vector<int> regs, th;
+                for (int b = 0; b < m; ++b)
+                    if (((Sn >> b) & 1) && b != cur.reg[split]) regs.push_back(b);
+                for (int j = 0, k = 0; j < rb; ++j)
+                    nw.reg[j] = (uint8_t)(j == split ? cur.reg[split] : regs[k++]);
+                for (int c = 0; c < 3; ++c) th.push_back(ord[c]);
+                for (int b = 0; b < m; ++b)
+                    if (!((Sn >> b) & 1) && !((low3 >> b) & 1)) th.push_back(b);
+                for (int t = 0; t < tb; ++t) nw.thr[t] = (uint8_t)th[t];
+                emit_remap(nw, split);
+                S = Sn;
+            }
+        }
+    } else if (S & 0x7u) {
         if (tb >= 2 && (tpos[cur.thr[0]] > 5 || tpos[cur.thr[1]] > 6)) {
             uint32_t Sn = S & ~0x7u;
             for (int b = m - 1; b >= 3 && __builtin_popcount(Sn) < rb; --b) Sn |= 1u << b;
@@ -911,8 +959,8 @@ void compile_pass(const Pass &ps, int rb, std::vector<double> &mats, TileProgram
                 r.b = 2;
                 break;
             }
-    for (int j = 0; j < rb; ++j) prog.g_reg_f[j] = 1ull << tpos[cur.reg[j]];
-    for (int t = 0; t < tb; ++t) prog.g_thr_f[t] = 1ull << tpos[cur.thr[t]];
+    for (int j = 0; j < rb; ++j) prog.g_reg_f[j] = 1ull << spos[cur.reg[j]];
+    for (int t = 0; t < tb; ++t) prog.g_thr_f[t] = 1ull << spos[cur.thr[t]];
     // the kernel runs ops in pairs: pad with an identity real 1-qubit op
     if (prog.rops.size() & 1) {
         dev::RegOp pad{};
@@ -1011,6 +1059,13 @@ std::string emulate_reg_pass(const TileProgram &prog, int rb, const std::vector<
     std::vector<cd> buf(half / elem_bytes);
     std::vector<char> full(half / elem_bytes);
     std::vector<char> seen((size_t)1 << m);
+    std::vector<int> loaded_by((size_t)1 << m, -1);
+    bool wg_synced = prog.store_sync, wave_synced = false;
+    for (const dev::RegOp &op : prog.rops)
+        if (op.kind == dev::ROP_REMAP) {
+            if (op.b == 1) wave_synced = true;
+            else wg_synced = true;
+        }
     char msg[256];
     for (uint64_t tile = 0; tile < n_tiles; ++tile) {
         uint64_t base = tile;
@@ -1022,6 +1077,10 @@ std::string emulate_reg_pass(const TileProgram &prog, int rb, const std::vector<
             for (int i = 0; i < nr; ++i) {
                 const uint64_t x = gidx(prog.g_reg, prog.g_thr, t, i);
                 if (x & ~prog.tile) return "load index outside the tile";
+                uint64_t lx = 0;
+                for (int b = 0; b < m; ++b)
+                    if ((x >> tpos[b]) & 1) lx |= 1ull << b;
+                loaded_by[lx] = t;
                 amp[(size_t)t * nr + i] = state[base | x];
             }
         for (size_t oi = 0; oi < prog.rops.size(); ++oi) {
@@ -1128,6 +1187,15 @@ std::string emulate_reg_pass(const TileProgram &prog, int rb, const std::vector<
                     if ((x >> tpos[b]) & 1) lx |= 1ull << b;
                 if (seen[lx]) return "store writes one amplitude twice";
                 seen[lx] = 1;
+                // without a workgroup barrier after the loads (a workgroup
+                // remap, or the store barrier) a thread may store only what
+                // its own wave loaded, and without a wave-local remap only
+                // what it loaded itself: the loads of others may be pending
+                const int owner = loaded_by[lx];
+                if (!wg_synced && (owner >> 6) != (t >> 6))
+                    return "store to an amplitude another wave loads, with no barrier between";
+                if (!wg_synced && !wave_synced && owner != t)
+                    return "store to an amplitude another lane loads, with no exchange between";
                 state[base | x] = amp[(size_t)t * nr + i];
             }
     }

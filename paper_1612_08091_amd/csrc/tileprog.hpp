@@ -23,6 +23,10 @@ struct TileProgram {
     uint64_t g_reg_f[8] = {};           // layout at store time
     uint64_t g_thr_f[16] = {};
     std::vector<unsigned char> img;     // LDS image (register kernel): tables, lane words
+    bool permutes = false;              // stores to relabeled positions (Pass::dest)
+    bool store_sync = false;            // workgroup barrier between the ops and the stores
+                                        // (threads store amplitudes other threads loaded)
+    uint8_t spos[64] = {};              // store position of each tile bit
     int remaps = 0;                     // layout changes through LDS
     int local_remaps = 0;               // of which within each wave (no workgroup barrier)
     int diag_merged = 0;                // diagonal ops folded into another

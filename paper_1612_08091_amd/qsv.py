@@ -44,7 +44,8 @@ class Options(ctypes.Structure):
                 ("k_max", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
                 ("queue_limit", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("state", ctypes.c_void_p), ("state_bytes", ctypes.c_uint64),
-                ("timing", ctypes.c_int32), ("reg_bits", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("reg_bits", ctypes.c_int32),
+                ("relabel", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -180,7 +181,8 @@ class Simulator:
 
     def __init__(self, n_max: int = 30, dtype="c128", mode="tiled", k_max: int = 2,
                  tile_bits: int = 0, queue_limit: int = 0, stream=None, state=None,
-                 use_torch_stream: bool = True, timing: bool = False, reg_bits: int = 0):
+                 use_torch_stream: bool = True, timing: bool = False, reg_bits: int = 0,
+                 relabel: bool = True):
         opt = Options()
         _check(lib.qsv_options_default(ctypes.byref(opt)))
         opt.n_max = n_max
@@ -191,6 +193,7 @@ class Simulator:
         opt.queue_limit = queue_limit
         opt.timing = int(bool(timing))
         opt.reg_bits = reg_bits
+        opt.relabel = int(bool(relabel))
         if stream is None and use_torch_stream:
             stream = _torch_stream()
         opt.stream = stream
@@ -446,10 +449,10 @@ class Simulator:
         counts).  ``state`` None: lower only, for the counts.  A test of the
         lowering; nothing runs on the device."""
         buf = None if state is None else np.ascontiguousarray(state, dtype=np.complex128).copy()
-        info = np.zeros(9, dtype=np.int32)
+        info = np.zeros(10, dtype=np.int32)
         _check(lib.qsv_check_tile_programs(self._h, _ptr(buf), _ptr(info)), self._h)
         keys = ("passes", "reg_passes", "real_ops", "diag_ops", "remaps", "max_image",
-                "instructions", "diag_merged", "local_remaps")
+                "instructions", "diag_merged", "local_remaps", "relabel_passes")
         return buf, dict(zip(keys, info.tolist()))
 
 

@@ -148,3 +148,93 @@ def test_real_split_identities():
     psi0 = rand_state(n, rng)
     got, want, info = run_check(c, psi0, tile_bits=12)
     assert float(np.max(np.abs(got - want))) <= 1e-13
+
+
+@pytest.mark.parametrize("n,layers", [(18, 20), (16, 40), (19, 20)])
+def test_relabeling_plans_through_the_kernel_model(n, layers):
+    """Passes that move their qubits to other positions inside the tile: the
+    stores go to the new positions, the next passes find their qubits there,
+    and trailing passes put every qubit back.  At 18 and 19 qubits the tile
+    (12 bits) holds positions at and above the 2 MiB page bit (17), so the
+    planner also caps how many of those a tile takes.  The 16- and 19-qubit
+    plans hold passes without a workgroup remap whose threads store what
+    other threads loaded: the host model rejects such a program unless it
+    has the barrier before its stores."""
+    circ = W.config1_random(n, layers=layers)
+    rng = np.random.default_rng(21)
+    psi0 = rand_state(n, rng)
+    want = oracle.run(circ, psi0.copy())
+    s = Q.Simulator(n_max=n, mode="tiled", k_max=2, use_torch_stream=False, relabel=True)
+    s.allocate(n)
+    s.run(circ)
+    got, info = s.check_tile_programs(psi0)
+    s.close()
+    assert info["relabel_passes"] > 0
+    assert float(np.max(np.abs(got - want))) <= 1e-13
+    s = Q.Simulator(n_max=n, mode="tiled", k_max=2, use_torch_stream=False, relabel=False)
+    s.allocate(n)
+    s.run(circ)
+    got0, info0 = s.check_tile_programs(psi0)
+    s.close()
+    assert info0["relabel_passes"] == 0
+    assert info["passes"] < info0["passes"]
+    assert float(np.max(np.abs(got0 - want))) <= 1e-13
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_relabeling_random_circuits(seed):
+    """Every gate kind of the register kernel under relabeling plans (tile of
+    11 bits on 15 qubits)."""
+    n = 15
+    rng = np.random.default_rng(700 + seed)
+    circ = random_circuit(rng, n, 150)
+    psi0 = rand_state(n, rng)
+    got, want, info = run_check(circ, psi0, tile_bits=11, reg_bits=3)
+    assert float(np.max(np.abs(got - want))) <= 1e-13
+
+
+def plan_passes(circ, relabel, dtype="c128", k_max=2):
+    s = Q.Simulator(n_max=circ.n, mode="tiled", k_max=k_max, use_torch_stream=False,
+                    relabel=relabel, dtype=dtype)
+    s.allocate(circ.n)
+    s.run(circ)
+    ops, npass = s.plan()
+    s.close()
+    return ops, npass
+
+
+def test_relabeling_cuts_passes_of_the_30q_brick_circuit():
+    """Host-side plan of the 30-qubit random brick circuit: with relabeling
+    the three positions every tile holds carry qubits in use and tiles keep
+    to few page positions, so fewer passes over the state (62 with fixed
+    positions)."""
+    circ = W.config1_random(n=30)
+    _, fixed = plan_passes(circ, False)
+    _, moved = plan_passes(circ, True)
+    assert fixed == 62
+    assert moved <= 50
+
+
+def test_relabeling_plan_ops_in_qubit_order():
+    """qsv_plan lists a relabeling plan's ops on their qubits' own
+    positions: applied one after the other by the oracle they give the
+    circuit's state."""
+    n = 12
+    rng = np.random.default_rng(33)
+    circ = random_circuit(rng, n, 100)
+    s = Q.Simulator(n_max=n, mode="tiled", k_max=2, tile_bits=8, reg_bits=0,
+                    use_torch_stream=False, relabel=True)
+    s.allocate(n)
+    s.run(circ)
+    ops, npass = s.plan()
+    s.close()
+    s = Q.Simulator(n_max=n, mode="tiled", k_max=2, tile_bits=8, use_torch_stream=False,
+                    relabel=False)
+    s.allocate(n)
+    s.run(circ)
+    assert npass < s.plan()[1]
+    s.close()
+    psi = oracle.zero_state(n)
+    for mat, targets, cmask in ops:
+        oracle.apply(psi, mat, targets, [p for p in range(64) if (cmask >> p) & 1])
+    assert float(np.max(np.abs(psi - oracle.run(circ)))) <= 1e-13
