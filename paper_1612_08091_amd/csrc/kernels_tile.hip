@@ -66,14 +66,14 @@ __global__ __launch_bounds__(kNT) void k_tile_lds(typename VT<R>::T *__restrict_
                 T v[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    v[u] = psi[base | dep_tid | ta.dep_hi[(j0 >> 8) + u]];
+                    v[u] = gload(psi + (base | dep_tid | ta.dep_hi[(j0 >> 8) + u]));
 #pragma unroll
                 for (int u = 0; u < 8; ++u) tile[swz_tid ^ swz<R>(j0 + u * kNT)] = v[u];
             }
         } else {
             for (uint32_t j = 0; j < tsize; j += kNT)
                 if (j + tid < tsize)
-                    tile[swz_tid ^ swz<R>(j)] = psi[base | dep_tid | ta.dep_hi[j >> 8]];
+                    tile[swz_tid ^ swz<R>(j)] = gload(psi + (base | dep_tid | ta.dep_hi[j >> 8]));
         }
         unsigned int next = 0;
         if (tid == 0) next = atomicAdd(counter, 1u);
@@ -93,12 +93,12 @@ __global__ __launch_bounds__(kNT) void k_tile_lds(typename VT<R>::T *__restrict_
                 for (int u = 0; u < 8; ++u) v[u] = tile[swz_tid ^ swz<R>(j0 + u * kNT)];
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    psi[base | dep_tid_f | ta.dep_hi_f[(j0 >> 8) + u]] = v[u];
+                    gstore(psi + (base | dep_tid_f | ta.dep_hi_f[(j0 >> 8) + u]), v[u]);
             }
         } else {
             for (uint32_t j = 0; j < tsize; j += kNT)
                 if (j + tid < tsize)
-                    psi[base | dep_tid_f | ta.dep_hi_f[j >> 8]] = tile[swz_tid ^ swz<R>(j)];
+                    gstore(psi + (base | dep_tid_f | ta.dep_hi_f[j >> 8]), tile[swz_tid ^ swz<R>(j)]);
         }
         if (tid == 0) s_tile = next;
         __syncthreads();
@@ -244,9 +244,11 @@ __device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const unsigned
     for (int q = 0; q < op.a; ++q)
         if ((base >> op.gt[q]) & 1) s_idx ^= op.gtb[q];
     uint32_t v_idx = s_idx;
+    if (lmask != 0) {   // uniform: tables without lane bits skip the lane part
 #pragma unroll
-    for (int t = 0; t < 6; ++t)
-        v_idx |= __builtin_amdgcn_ubfe(lane, (uint32_t)t, (uint32_t)((lmask >> t) & 1u)) << sh[t];
+        for (int t = 0; t < 6; ++t)
+            v_idx |= __builtin_amdgcn_ubfe(lane, (uint32_t)t, (uint32_t)((lmask >> t) & 1u)) << sh[t];
+    }
 #pragma unroll
     for (int i0 = 0; i0 < NR; i0 += 4) {
         T f[4];
@@ -469,7 +471,7 @@ __device__ __forceinline__ void load_tile(T *dst, const T *__restrict__ psi, uin
 #pragma unroll
         for (int j = 0; j < RB; ++j)
             if ((i >> j) & 1) g |= gr[j];
-        dst[i] = lp[g];
+        dst[i] = gload(lp + g);
     }
 }
 
@@ -521,7 +523,10 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
     // they share a DRAM page with are fetched close together in time
     // (measured: larger chunks lose a few per cent).
     constexpr uint32_t kChunk = 1;
-    __shared__ uint32_t s_claim[2];
+    // the two claim slots follow the image in dynamic LDS (a static
+    // __shared__ variable would move the dynamic block off address 0, and
+    // every LDS address would then take an extra add)
+    uint32_t *s_claim = reinterpret_cast<uint32_t *>(limg + ta.img_bytes);
     if (tid == 0) s_claim[0] = atomicAdd(counter, kChunk);
     uint32_t slot = 0;
     uint32_t tile = 0, left = 0;
@@ -569,7 +574,7 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
 #pragma unroll
             for (int j = 0; j < RB; ++j)
                 if ((i >> j) & 1) g |= gr[j];
-            sp[g] = amp[i];
+            gstore(sp + g, amp[i]);
         }
         ++tile;
         --left;
@@ -647,11 +652,11 @@ static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
     if (ta.n_tiles > 0xffffffffull - 65536) return hipErrorInvalidValue;
     if (ta.img_bytes > kRegImageMax || (ta.img_bytes & 15u) || (ta.img_off & 15)) return hipErrorInvalidValue;
     constexpr size_t half = sizeof(T) << (RB + TB - 1);
-    const size_t lds = half + ta.img_bytes;
+    const size_t lds = half + ta.img_bytes + 16;   // + the two claim slots
     static int cus = 0;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = set_lds_attr(k_tile_reg<R, RB, TB, DG>, half + kRegImageMax);
+        hipError_t e = set_lds_attr(k_tile_reg<R, RB, TB, DG>, half + kRegImageMax + 16);
         if (e != hipSuccess) return e;
         int dev = 0;
         e = hipGetDevice(&dev);
@@ -665,7 +670,8 @@ static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
     if (per_cu[slot] == 0) {
         int occ = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(k_tile_reg<R, RB, TB, DG>), 1 << TB, half + slot * 1024);
+            &occ, reinterpret_cast<const void *>(k_tile_reg<R, RB, TB, DG>), 1 << TB,
+            half + slot * 1024 + 16);
         if (e != hipSuccess) return e;
         per_cu[slot] = std::max(1, occ);
     }

@@ -14,6 +14,36 @@ template <typename R> struct VT;
 template <> struct VT<double> { using T = double2; };
 template <> struct VT<float> { using T = float2; };
 
+// Amplitude loads and stores through global (address space 1) pointers.  A
+// pointer that went through an empty asm, or a copy of the vector struct,
+// loses the address space and compiles to flat accesses, which also count
+// against the LDS wait counter: every LDS or scalar-load wait then waits for
+// the tile's HBM traffic too.
+typedef double __attribute__((ext_vector_type(2))) dvec2;
+typedef float __attribute__((ext_vector_type(2))) fvec2;
+typedef __attribute__((address_space(1))) dvec2 g_dvec2;
+typedef __attribute__((address_space(1))) fvec2 g_fvec2;
+__device__ __forceinline__ double2 gload(const double2 *p) {
+    const dvec2 v = *(const g_dvec2 *)p;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 gload(const float2 *p) {
+    const fvec2 v = *(const g_fvec2 *)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore(double2 *p, double2 a) {
+    dvec2 v;
+    v.x = a.x;
+    v.y = a.y;
+    *(g_dvec2 *)p = v;
+}
+__device__ __forceinline__ void gstore(float2 *p, float2 a) {
+    fvec2 v;
+    v.x = a.x;
+    v.y = a.y;
+    *(g_fvec2 *)p = v;
+}
+
 // XOR swizzle of an LDS element index: the bits above the 256-byte bank span
 // are folded into the bits below it.  A bijection on [0, 2^m).
 template <typename R> __device__ __forceinline__ uint32_t swz(uint32_t l);
