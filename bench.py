@@ -33,15 +33,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 FP64_PEAK = 78.6e12        # MI355X FP64 (vector and matrix), flop/s
 
-# Measured HBM traffic of the dominant kernel (k_tile_reg<double,4,8,false> on this
-# workload), from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
-# WRITE_SIZE, KiB per dispatch, mean over the dispatches of one step).  The
-# counters are scaled by what they read for a plain device copy of known size
-# in the same runs (4 GiB read + 4 GiB write: FETCH_SIZE reads half the bytes,
-# WRITE_SIZE all of them).  Valid only for the sources they were taken with:
-# the digest below covers every file that shapes the kernel or its launches.
-TRAFFIC = {"kernel": "k_tile_reg<double,4,8,false>", "fetch_kib": 8389430.4, "write_kib": 16861954.2,
-           "fetch_scale": 2.0, "write_scale": 1.0, "digest": "9534dcdbadb74f22"}
+# Measured HBM traffic of the dominant kernel (k_tile_reg<double,4,8,*>: the
+# instance with table ops, 132 of 144 launches in the profiled run, and the
+# one without, the 12 passes that only move qubits back), from two rocprofv3
+# --pmc runs of this script's main leg (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch, mean over the tile dispatches).  The counters are scaled by what
+# they read for the copy probe of the same runs (16 GiB read + 16 GiB
+# written: FETCH_SIZE reads half the bytes, WRITE_SIZE all of them).  Valid
+# only for the sources they were taken with: the digest below covers every
+# file that shapes the kernel or its launches.
+TRAFFIC = {"kernel": "k_tile_reg<double,4,8,*>", "fetch_kib": 8395107.6, "write_kib": 16785434.3,
+           "fetch_scale": 2.0, "write_scale": 1.0, "digest": "72239be7fd8213f9"}
 TRAFFIC_SOURCES = ("paper_1612_08091_amd/csrc/kernels_tile.hip",
                    "paper_1612_08091_amd/csrc/lds_ops.hpp",
                    "paper_1612_08091_amd/csrc/device.hpp",
@@ -101,6 +103,15 @@ def run_leg(circ, ham, u, steps, warmup, dtype, mode, k_max, tile_bits, timing=T
     sim = Q.Simulator(n_max=n, dtype=dtype, mode=mode, k_max=k_max, tile_bits=tile_bits,
                       timing=timing, reg_bits=reg_bits)
     sim.allocate(n)
+    diag_ops = 0
+    if mode == "tiled":
+        # the lowering the flushes will run (host side): table ops present?
+        sim.run(circ)
+        try:
+            diag_ops = sim.check_tile_programs(None)[1]["diag_ops"]
+        except Exception:
+            diag_ops = -1
+        sim.reset()
     gates = [(np.ascontiguousarray(g.matrix), list(g.targets), list(g.controls))
              for g in circ.gates]
     out = {}
@@ -134,8 +145,63 @@ def run_leg(circ, ham, u, steps, warmup, dtype, mode, k_max, tile_bits, timing=T
     sim.close()
     wall = t1 - t0
     return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "stats": st, "ktimes": kt,
-            "norm2": out.get("norm2"), "energy": out.get("energy"),
+            "norm2": out.get("norm2"), "energy": out.get("energy"), "diag_ops": diag_ops,
             "updates_per_step": len(circ.gates) * float(1 << n)}
+
+
+def copy_bandwidth(gib: int = 16, reps: int = 5):
+    """Achievable HBM bandwidth: the library's streaming copy kernel
+    (qsv_copy_probe) over two gib-GiB device buffers, timed with events on
+    the stream it runs on; read + write bytes per second."""
+    import torch
+    from paper_1612_08091_amd import qsv as Q
+    a = torch.empty((gib << 30) // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    st = torch.cuda.current_stream()
+    Q.copy_probe(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        Q.copy_probe(a, b)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a[:1 << 20], b[:1 << 20]))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GBps": 2.0 * (gib << 30) / (ms * 1e-3) / 1e9, "ms": ms, "bytes_each_way": gib << 30,
+            "copy_checked": ok}
+
+
+def fp32_state_error(circ):
+    """Normwise relative error of the complex64 state against the complex128
+    state of the same circuit (both from the fused tile passes), over every
+    amplitude: the two states sit in device buffers the simulators borrow."""
+    import torch
+    from paper_1612_08091_amd import qsv as Q
+    n = circ.n
+    b128 = torch.empty(2 << n, dtype=torch.float64, device="cuda")
+    b64 = torch.empty(2 << n, dtype=torch.float32, device="cuda")
+    for dt, buf in (("c128", b128), ("c64", b64)):
+        sim = Q.Simulator(n_max=n, dtype=dt, mode="tiled", k_max=2, state=buf)
+        sim.allocate(n)
+        sim.run(circ)
+        sim.flush()
+        sim.synchronize()
+        sim.close()
+    torch.cuda.synchronize()
+    num = 0.0
+    den = 0.0
+    step = 1 << 26
+    for a in range(0, 2 << n, step):
+        x = b128[a:a + step]
+        d = b64[a:a + step].double() - x
+        num += float(torch.dot(d, d))
+        den += float(torch.dot(x, x))
+    del b128, b64
+    torch.cuda.empty_cache()
+    return math.sqrt(num / den)
 
 
 def _timed_circuit(sim, circ):
@@ -389,68 +455,193 @@ def form_noise(n: int = 15, layers: int = 10):
             "trajectory": {"s_per_trajectory": tt, "channels_per_s": (len(ev) - gates) / tt}}
 
 
-def form_batched():
+def form_batched(pergate_sample: int = 256):
     """Config 3: 4096 HEA circuits (8..20 qubits, depth 6) with 64-term Pauli
-    sums, complex64, one persistent graph-captured launch per evaluation."""
+    sums, complex64, one persistent graph-captured launch per evaluation;
+    beside it the same batch in complex128, and the plain FP64 per-gate path
+    (one circuit at a time) on a seeded sample of circuits.  Accuracy: the
+    largest |<H>_c64 - <H>_fp64| / sum|c| over the circuits."""
     import workloads as W
     from paper_1612_08091_amd import qsv as Q
     t0 = time.perf_counter()
     circuits, hams = W.config3()
-    b = Q.Batch(circuits, hams, dtype="c64", autotune=True, use_graph=True)
-    setup = time.perf_counter() - t0
-    b.run()
-    times = []
-    for _ in range(5):
+    scale = np.array([float(np.sum(np.abs(h.coeff))) for h in hams])
+    out = {"workload": "config 3: 4096 circuits, n ~ U{8..20}, 64-term <H> each"}
+    vals = {}
+    for dt in ("c64", "c128"):
         t1 = time.perf_counter()
-        b.run()
-        times.append(time.perf_counter() - t1)
-    info = b.info()
-    b.close()
-    best = min(times)
-    return {"workload": "config 3: 4096 circuits, n ~ U{8..20}, 64-term <H> each",
-            "circuits_per_s": len(circuits) / best, "s_per_batch": best,
-            "device_ms": info["last_ms"], "tile_bits": info["tile_bits"], "k_fuse": info["k_fuse"],
-            "setup_s_incl_autotune": setup}
+        b = Q.Batch(circuits, hams, dtype=dt, autotune=True, use_graph=True)
+        setup = time.perf_counter() - t1
+        vals[dt] = np.array(b.run())
+        times = []
+        for _ in range(5):
+            t1 = time.perf_counter()
+            b.run()
+            times.append(time.perf_counter() - t1)
+        info = b.info()
+        b.close()
+        best = min(times)
+        out[dt] = {"circuits_per_s": len(circuits) / best, "s_per_batch": best,
+                   "device_ms": info["last_ms"], "tile_bits": info["tile_bits"],
+                   "k_fuse": info["k_fuse"], "setup_s_incl_autotune": setup}
+        log("  batched %s: %.4f s per batch" % (dt, best))
+    out["c64"]["max_abs_err_over_sum_abs_c_vs_c128_batch"] = float(
+        np.max(np.abs(vals["c64"] - vals["c128"]) / scale))
+    # the FP64 per-gate path, one circuit at a time, on a seeded sample
+    pick = np.sort(np.random.default_rng(W.SEED_BASE + 3).choice(len(circuits), pergate_sample,
+                                                                  replace=False))
+    sims = {}
+    ref = np.zeros(len(pick))
+    t1 = time.perf_counter()
+    for j, i in enumerate(pick):
+        c = circuits[i]
+        if c.n not in sims:
+            sims[c.n] = Q.Simulator(n_max=c.n, dtype="c128", mode="pergate", k_max=1)
+            sims[c.n].allocate(c.n)
+        s = sims[c.n]
+        s.reset()
+        s.run(c)
+        s.flush()
+        ref[j] = s.expectation(hams[i])
+    s_pg = time.perf_counter() - t1
+    for s in sims.values():
+        s.close()
+    out["fp64_pergate_sample"] = {
+        "circuits": int(len(pick)), "s": s_pg,
+        "circuits_per_s": len(pick) / s_pg,
+        "c64_batch_max_abs_err_over_sum_abs_c": float(np.max(np.abs(vals["c64"][pick] - ref)
+                                                             / scale[pick])),
+        "c128_batch_max_abs_err_over_sum_abs_c": float(np.max(np.abs(vals["c128"][pick] - ref)
+                                                              / scale[pick]))}
+    out["c64_speedup_vs_fp64_pergate"] = out["c64"]["circuits_per_s"] / (len(pick) / s_pg)
+    out["total_s"] = time.perf_counter() - t0
+    log("  batched per-gate FP64 sample: %.2f s for %d circuits" % (s_pg, len(pick)))
+    return out
 
 
 def form_adjoint():
     """Config 4: 24-qubit HEA (480 angles), 200-term Pauli sum: <H> and the full
-    gradient by the adjoint method, complex128."""
+    gradient by the adjoint method, complex128; the tiled reverse sweep beside
+    the plain per-gate one, both checked against the stored oracle values
+    (tests/golden/config4_adjoint.json: the energy and a seeded subset of the
+    gradient, written by a script that calls only the oracle)."""
     import workloads as W
     from paper_1612_08091_amd import qsv as Q
+    with open(os.path.join(ROOT, "tests", "golden", "config4_adjoint.json")) as f:
+        gold = json.load(f)
     circ, ham = W.config4()
-    sim = Q.Simulator(n_max=24, dtype="c128", mode="tiled", k_max=2)
-    Q.adjoint_gradient(sim, circ, ham)
-    times = []
-    for _ in range(3):
-        t1 = time.perf_counter()
-        val, grad = Q.adjoint_gradient(sim, circ, ham)
-        times.append(time.perf_counter() - t1)
-    sim.close()
-    return {"workload": "config 4: 24-qubit HEA, 480 angles, 200 Pauli terms",
-            "s_per_value_and_gradient": min(times), "energy": val,
-            "grad_norm": float(np.linalg.norm(grad))}
+    scale = float(np.sum(np.abs(ham.coeff)))
+    out = {"workload": "config 4: 24-qubit HEA, 480 angles, 200 Pauli terms"}
+    for mode, k in (("tiled", 2), ("pergate", 1)):
+        sim = Q.Simulator(n_max=24, dtype="c128", mode=mode, k_max=k)
+        Q.adjoint_gradient(sim, circ, ham)
+        times = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            val, grad = Q.adjoint_gradient(sim, circ, ham)
+            times.append(time.perf_counter() - t1)
+        sim.close()
+        got = np.asarray(grad)[gold["params"]]
+        out[mode] = {"s_per_value_and_gradient": min(times), "energy": val,
+                     "energy_abs_err_over_sum_abs_c": abs(val - gold["energy"]) / scale,
+                     "grad_max_abs_err_over_sum_abs_c": float(
+                         np.max(np.abs(got - np.asarray(gold["grad"]))) / scale),
+                     "grad_norm": float(np.linalg.norm(grad))}
+        log("  adjoint %s: %.3f s" % (mode, min(times)))
+    out["tiled_speedup_vs_pergate"] = (out["pergate"]["s_per_value_and_gradient"]
+                                       / out["tiled"]["s_per_value_and_gradient"])
+    return out
 
 
-def cpu_baseline(circ, budget_s=15.0):
-    """The oracle applying the first gates of the same 30-qubit circuit, one
-    at a time, until about budget_s seconds of work (single thread)."""
+def host_description():
+    """Cores this process may use, the CPU model and the RAM of the host."""
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit():
+        cores = min(cores, int(omp))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ram_gib = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram_gib = int(line.split()[1]) / 2**20
+                    break
+    except OSError:
+        pass
+    return {"cores_usable": cores, "nproc": os.cpu_count(), "cpu_model": model,
+            "ram_GiB": ram_gib}
+
+
+def _oracle_circuit(circ, threads, psi=None, max_gates=None, budget_s=None):
+    """Oracle run of the first gates of circ (all by default) on `threads`
+    threads; returns (gates done, seconds)."""
     import oracle
-    n = circ.n
-    psi = np.zeros(1 << n, dtype=np.complex128)
-    psi[0] = 1.0
+    oracle.set_threads(threads)
+    if psi is None:
+        psi = oracle.zero_state(circ.n)
     done = 0
     t0 = time.perf_counter()
     for g in circ.gates:
         oracle.apply(psi, g.matrix, g.targets, g.controls)
         done += 1
-        if time.perf_counter() - t0 > budget_s:
+        if max_gates is not None and done >= max_gates:
+            break
+        if budget_s is not None and time.perf_counter() - t0 > budget_s:
             break
     t = time.perf_counter() - t0
+    oracle.set_threads(1)
+    return done, t
+
+
+def cpu_baseline(circ, budget_s=12.0):
+    """The oracle (plain C, one gate at a time, complex128) on the host cores:
+    a bounded sample of the 30-qubit circuit (its first gates, one thread and
+    all cores, outer loop of each gate shared out), with the full circuit's
+    time extrapolated from it, and two small configurations in full: the
+    16-qubit 20-layer brick circuit and the 20-qubit twin of the 32-qubit
+    Haar + CZ brick circuit."""
+    import oracle
+    import workloads as W
+    host = host_description()
+    cores = host["cores_usable"]
+    n = circ.n
+    psi = oracle.zero_state(n)
+    g1, t1 = _oracle_circuit(circ, 1, psi=psi, max_gates=2, budget_s=budget_s)
+    rate1 = g1 * float(1 << n) / t1
+    gn, tn = _oracle_circuit(circ, cores, psi=psi, max_gates=60, budget_s=budget_s)
+    raten = gn * float(1 << n) / tn
     del psi
-    return {"value": done * float(1 << n) / t, "unit": "amp*gate/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d gates of the %d-qubit circuit, complex128, one thread "
-                      "(%.1f s)" % (done, len(circ.gates), n, t)}
+    log("  cpu: 30q %d gates on 1 thread %.1f s, %d gates on %d threads %.1f s" % (g1, t1, gn, cores, tn))
+    c0, _ = W.config0()
+    d0a, s0a = _oracle_circuit(c0, 1)
+    d0n, s0n = _oracle_circuit(c0, cores)
+    c2 = W.config2(n=20)
+    d2a, s2a = _oracle_circuit(c2, 1)
+    d2n, s2n = _oracle_circuit(c2, cores)
+    log("  cpu: config 0 %.2f s / %.2f s, 20q twin %.2f s / %.2f s" % (s0a, s0n, s2a, s2n))
+    full = len(circ.gates) * float(1 << n)
+    return {"value": raten, "unit": "amp*gate/s", "cores": cores, "kind": "oracle",
+            "sample": "the first %d gates of the %d-qubit circuit (of %d), complex128, the "
+                      "oracle's gate loop shared over %d threads (%.1f s); the full circuit "
+                      "is extrapolated below" % (gn, n, len(circ.gates), cores, tn),
+            "single_thread": {"value": rate1, "sample": "first %d gates, %.1f s" % (g1, t1)},
+            "extrapolated_full_circuit_s": {"threads_%d" % cores: full / raten,
+                                            "threads_1": full / rate1,
+                                            "note": "extrapolation from the sample, not run"},
+            "config0_16q_20layers_full": {"gates": d0a, "s_1_thread": s0a,
+                                          "s_%d_threads" % cores: s0n},
+            "config2_twin_20q_full": {"gates": d2a, "s_1_thread": s2a,
+                                      "s_%d_threads" % cores: s2n},
+            "host": host}
 
 
 def main():
@@ -468,9 +659,6 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-legs", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="first run a plain 4 GiB device copy (read 4 GiB, write 4 GiB), the "
-                         "reference for scaling profiler byte counters")
     ap.add_argument("--fp32-k-max", type=int, default=2)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the 32-qubit precision, batched and adjoint forms")
@@ -489,13 +677,6 @@ def main():
     import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.copy_calibration:
-        a = torch.empty(1 << 29, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     if args.only_form:
         forms = {"adjoint": form_adjoint, "batched": form_batched, "precision": form_precision,
@@ -521,6 +702,9 @@ def main():
     alg_bytes_step = st["alg_bytes"] / steps
     pct_hbm = alg_bytes_step / (main_leg["ms_per_step"] * 1e-3) / HBM_PEAK
 
+    log("copy probe ...")
+    copy = copy_bandwidth()
+    log("copy probe: %.0f GB/s" % copy["GBps"])
     kt = main_leg["ktimes"]
     dom = "tile" if kt.get("tile", (0, 0, 0))[1] > 0 else "dense"
     ms, launches, kbytes = kt[dom]
@@ -533,18 +717,21 @@ def main():
     if dom != "tile":
         kname = "k_dense<%s,1>" % rname
     elif args.k_max <= 2:
-        # the benchmark circuit has no diagonal op: its passes run the kernel
-        # instance without that case
+        # the real split leaves diagonal phases as table ops: passes with one
+        # run the kernel instance with that case
         rb = args.reg_bits or 4
         tb = (args.tile_bits or 12) - rb
-        kname = "k_tile_reg<%s,%d,%d,false>" % (rname, rb, tb)
+        # both instances: with table ops (most passes) and without (the
+        # passes that only move qubits back to their own positions)
+        kname = "k_tile_reg<%s,%d,%d,*>" % (rname, rb, tb)
     else:
         kname = "k_tile_lds<%s,k<=%d> (MFMA for k>=3)" % (rname, args.k_max)
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK,
                 "traffic": measured_traffic() if default_cfg else None,
                 "kernel": kname,
-                "launches": launches, "avg_ms": avg_ms, "alg_bytes_per_launch": per_launch_bytes}
+                "launches": launches, "avg_ms": avg_ms, "alg_bytes_per_launch": per_launch_bytes,
+                "copy_GBps": copy["GBps"], "frac_of_copy": achieved / (copy["GBps"] * 1e9)}
     if dom == "tile" and avg_ms > 0:
         # the same launches against the vector-ALU peak (FP64, and FP32 with
         # packed math off, are both 78.6 TFLOP/s): the pass's arithmetic
@@ -559,13 +746,17 @@ def main():
     if not args.no_extra_legs:
         leg32 = run_leg(circ, ham, u, steps, 1, "c64", args.mode, args.fp32_k_max, 0)
         ms32, l32, b32 = leg32["ktimes"]["tile"]
+        err32 = fp32_state_error(circ)
+        log("fp32 state error: %.3g" % err32)
         extra["fp32_fused"] = {
             "value": leg32["updates_per_step"] * steps / leg32["wall_s"],
             "ms_per_step": leg32["ms_per_step"],
+            "state_rel_err_vs_fp64_all_amplitudes": err32,
             "pct_hbm_peak": leg32["stats"]["alg_bytes"] / steps / (leg32["ms_per_step"] * 1e-3)
             / HBM_PEAK,
             "tile_kernel_GBps": (b32 / max(l32, 1)) / (ms32 / max(l32, 1) * 1e-3) / 1e9 if ms32 else None,
             "energy_abs_diff_vs_fp64": abs(leg32["energy"] - main_leg["energy"]),
+            "speedup_vs_fp64_fused": main_leg["ms_per_step"] / leg32["ms_per_step"],
         }
         log("fp32 leg: %.2f ms/step" % leg32["ms_per_step"])
         pg = run_leg(circ, ham, u, 1, 0, "c128", "pergate", 1, 0, reduce=False)
@@ -578,6 +769,8 @@ def main():
             "cnot_GBps": m_b / (m_ms * 1e-3) / 1e9 if m_ms else None,
             "pct_hbm_peak": pg["stats"]["alg_bytes"] / (pg["ms_per_step"] * 1e-3) / HBM_PEAK,
         }
+        extra["fp64_fused_speedup_vs_fp64_pergate"] = pg["ms_per_step"] / main_leg["ms_per_step"]
+        extra["fp32_fused"]["speedup_vs_fp64_pergate"] = pg["ms_per_step"] / leg32["ms_per_step"]
         log("per-gate leg: %.2f ms/step" % pg["ms_per_step"])
     if not args.no_forms:
         extra["fusion_and_qft_30q"] = form_fusion_qft(n)

@@ -46,7 +46,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no GPU toolchain involved)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c99",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-fopenmp",
                                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -65,6 +65,8 @@ def _load():
         c_d, c_i, c_u64 = ctypes.c_double, ctypes.c_int, ctypes.c_uint64
         lib.oracle_apply.argtypes = [P(c_d), c_i, P(c_d), c_i, P(c_i), c_i, P(c_i)]
         lib.oracle_apply.restype = c_i
+        lib.oracle_set_threads.argtypes = [c_i]
+        lib.oracle_set_threads.restype = c_i
         lib.oracle_probs.argtypes = [P(c_d), c_i, P(c_d)]
         lib.oracle_probs.restype = None
         lib.oracle_prob_bits.argtypes = [P(c_d), c_i, c_i, P(c_i), P(c_i)]
@@ -120,6 +122,12 @@ def basis_state(n: int, x: int) -> np.ndarray:
     psi = np.zeros(1 << n, dtype=np.complex128)
     psi[x] = 1.0
     return psi
+
+
+def set_threads(t: int) -> int:
+    """Threads for the outer loop of ``apply`` (1, the default, is serial);
+    returns the number in effect.  Results do not depend on it."""
+    return int(_load().oracle_set_threads(int(t)))
 
 
 def apply(psi: np.ndarray, matrix, targets: Sequence[int], controls: Sequence[int] = ()):

@@ -22,7 +22,10 @@
  *              is left as it is.
  *   reductions sequential left-to-right sums in double precision.
  *
- * Built with gcc -O2 -ffp-contract=off.  Single-threaded.
+ * Built with gcc -O2 -ffp-contract=off -fopenmp.  Single-threaded unless
+ * oracle_set_threads asks for more: then only the outer loop of
+ * oracle_apply (over the independent index groups of one gate, each written
+ * by one thread) is shared out, which changes no result.
  */
 #include <complex.h>
 #include <math.h>
@@ -31,6 +34,25 @@
 #include <string.h>
 
 typedef double complex cplx;
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int g_threads = 1;
+
+/* Threads for oracle_apply's outer loop (1 = serial, the default).
+ * Returns the number in effect. */
+int oracle_set_threads(int t)
+{
+#ifdef _OPENMP
+    g_threads = t < 1 ? 1 : t;
+#else
+    (void)t;
+    g_threads = 1;
+#endif
+    return g_threads;
+}
 
 static int bit_of(uint64_t i, int q) { return (int)((i >> q) & 1u); }
 
@@ -43,33 +65,45 @@ int oracle_apply(double *psi_d, int n, const double *u_d, int k,
     const cplx *u = (const cplx *)u_d;
     const uint64_t dim = (uint64_t)1 << n;
     const int blk = 1 << k;
-    cplx *in = (cplx *)malloc(sizeof(cplx) * blk);
-    cplx *out = (cplx *)malloc(sizeof(cplx) * blk);
     uint64_t *off = (uint64_t *)malloc(sizeof(uint64_t) * blk);
-    if (!in || !out || !off) { free(in); free(out); free(off); return -1; }
+    if (!off) return -1;
     for (int r = 0; r < blk; ++r) {
         uint64_t o = 0;
         for (int j = 0; j < k; ++j)
             if ((r >> j) & 1) o += (uint64_t)1 << targets[j];
         off[r] = o;
     }
-    for (uint64_t i = 0; i < dim; ++i) {
-        int ok = 1;
-        for (int j = 0; j < k; ++j)
-            if (bit_of(i, targets[j])) { ok = 0; break; }
-        for (int j = 0; ok && j < nc; ++j)
-            if (!bit_of(i, controls[j])) ok = 0;
-        if (!ok) continue;
-        for (int c = 0; c < blk; ++c) in[c] = psi[i + off[c]];
-        for (int r = 0; r < blk; ++r) {
-            cplx acc = 0;
-            for (int c = 0; c < blk; ++c) acc += u[(size_t)r * blk + c] * in[c];
-            out[r] = acc;
+    int failed = 0;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(g_threads) reduction(| : failed)
+#endif
+    {
+        cplx *in = (cplx *)malloc(sizeof(cplx) * blk);
+        cplx *out = (cplx *)malloc(sizeof(cplx) * blk);
+        if (!in || !out) failed = 1;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (uint64_t i = 0; i < dim; ++i) {
+            int ok = !failed;
+            for (int j = 0; ok && j < k; ++j)
+                if (bit_of(i, targets[j])) ok = 0;
+            for (int j = 0; ok && j < nc; ++j)
+                if (!bit_of(i, controls[j])) ok = 0;
+            if (!ok) continue;
+            for (int c = 0; c < blk; ++c) in[c] = psi[i + off[c]];
+            for (int r = 0; r < blk; ++r) {
+                cplx acc = 0;
+                for (int c = 0; c < blk; ++c) acc += u[(size_t)r * blk + c] * in[c];
+                out[r] = acc;
+            }
+            for (int r = 0; r < blk; ++r) psi[i + off[r]] = out[r];
         }
-        for (int r = 0; r < blk; ++r) psi[i + off[r]] = out[r];
+        free(in);
+        free(out);
     }
-    free(in); free(out); free(off);
-    return 0;
+    free(off);
+    return failed ? -1 : 0;
 }
 
 /* p_i = |psi_i|^2 */

@@ -10,21 +10,29 @@
 namespace qsv {
 namespace dev {
 
-// Each thread moves 4 x 16 bytes per step, grid-strided; the four loads are
-// in flight together.
-__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src,
-                                               uint4 *__restrict__ dst, uint64_t n16) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
-                    d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Each workgroup moves contiguous blocks of 256 x 8 sixteen-byte elements,
+// the eight loads of a thread in flight together, with nontemporal loads and
+// stores (the data is not reused).  Of the shapes measured (grid-strided or
+// blocked, 4-16 elements per thread, 4-64 workgroups per compute unit) this
+// one is the fastest over 16 GiB.
+__global__ __launch_bounds__(256) void k_copy16(const u32x4 *__restrict__ src,
+                                               u32x4 *__restrict__ dst, uint64_t n16) {
+    constexpr uint64_t kBlock = 256ull * 8;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * kBlock; b0 < n16; b0 += (uint64_t)gridDim.x * kBlock) {
+        u32x4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint64_t i = b0 + (uint64_t)u * 256 + threadIdx.x;
+            if (i < n16) v[u] = __builtin_nontemporal_load(src + i);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint64_t i = b0 + (uint64_t)u * 256 + threadIdx.x;
+            if (i < n16) __builtin_nontemporal_store(v[u], dst + i);
+        }
     }
-    for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 hipError_t copy_probe(const void *src, void *dst, uint64_t bytes, hipStream_t s) {
@@ -34,9 +42,9 @@ hipError_t copy_probe(const void *src, void *dst, uint64_t bytes, hipStream_t s)
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const uint64_t n16 = bytes / 16;
-    const uint64_t want = (n16 + 255) / 256;
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)cus * 16));
-    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n16);
+    const uint64_t want = (n16 + 2047) / 2048;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)cus * 64));
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const u32x4 *)src, (u32x4 *)dst, n16);
     return hipGetLastError();
 }
 

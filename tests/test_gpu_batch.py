@@ -76,17 +76,42 @@ def test_batch_autotune_and_cache(tmp_path):
     b2.close()
 
 
-def test_config3_subset_against_oracle_and_single_path():
+def test_config3_full_batch_against_single_circuit_fp64_and_oracle():
+    """The benched batch itself: all 4096 circuits of config 3 (complex64,
+    autotuned, graph-captured) against the non-batched FP64 path run circuit
+    by circuit on the GPU, every <H> within 1e-5 * sum|c|; a seeded 64 of
+    them also against the oracle."""
     from paper_1612_08091_amd import qsv as Q
-    circuits, hams = W.config3(count=256)
-    b = Q.Batch(circuits, hams, dtype="c64", autotune=False, tile_bits=12)
+    circuits, hams = W.config3()
+    assert len(circuits) == 4096
+    b = Q.Batch(circuits, hams, dtype="c64", autotune=True, use_graph=True)
     got = b.run()
     b.close()
-    rng = np.random.default_rng(45)
-    pick = rng.choice(256, size=12, replace=False)
-    for i in pick:
-        want = oracle.energy(circuits[i], hams[i])
-        assert abs(got[i] - want) <= 1e-5 * np.sum(np.abs(hams[i].coeff)), i
+    scale = np.array([np.sum(np.abs(h.coeff)) for h in hams])
+    sims = {}
+    ref = np.zeros(len(circuits))
+    for i, (c, h) in enumerate(zip(circuits, hams)):
+        if c.n not in sims:
+            sims[c.n] = Q.Simulator(n_max=c.n, dtype="c128", mode="tiled", k_max=2)
+            sims[c.n].allocate(c.n)
+        s = sims[c.n]
+        s.reset()
+        s.run(c)
+        s.flush()
+        ref[i] = s.expectation(h)
+    for s in sims.values():
+        s.close()
+    err = np.abs(got - ref) / scale
+    assert np.all(err <= 1e-5), (int(np.argmax(err)), float(np.max(err)))
+    pick = np.random.default_rng(45).choice(len(circuits), size=64, replace=False)
+    oracle.set_threads(8)
+    try:
+        for i in pick:
+            want = oracle.energy(circuits[i], hams[i])
+            assert abs(ref[i] - want) <= 1e-12 * scale[i], i
+            assert abs(got[i] - want) <= 1e-5 * scale[i], i
+    finally:
+        oracle.set_threads(1)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])

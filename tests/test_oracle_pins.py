@@ -671,3 +671,20 @@ def test_workload_shapes_and_determinism():
     b = W.config0()[0].gates[17].matrix
     assert np.array_equal(a, b)
     assert np.allclose(a.conj().T @ a, np.eye(2), atol=1e-15)
+
+
+def test_oracle_threads_change_no_result():
+    """oracle.set_threads shares out only the outer loop of a gate (index
+    groups written by one thread each): the state is bit-identical to the
+    serial run."""
+    n = 14
+    c = W.config1_random(n, layers=4)
+    for g in W.qft(n).gates[:40]:
+        c.gates.append(g)
+    psi1 = oracle.run(c)
+    assert oracle.set_threads(4) == 4
+    try:
+        psi4 = oracle.run(c)
+    finally:
+        oracle.set_threads(1)
+    assert np.array_equal(psi1, psi4)
