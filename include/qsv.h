@@ -85,6 +85,9 @@ typedef struct qsv_options {
                                tile holds carry qubits in use and tiles span few 2 MiB
                                pages; every flush ends with each qubit back at its own
                                position.  0: positions never move */
+    uint64_t mem_limit;     /* bytes the state buffer may take; ENOMEM, decided before any
+                               allocation, when it needs more.  0 (default): the device's
+                               free memory (hipMemGetInfo) at the time of the allocation */
 } qsv_options;
 
 /* Kernel classes reported by qsv_get_kernel_times. */
@@ -207,8 +210,14 @@ qsv_status qsv_dm_expectation(qsv_sim *sim, int32_t nterms, const uint64_t *xmas
 
 /* Execute every queued gate (Sec. 4.1.3 eng.flush()): plan fusion and passes,
  * enqueue the kernels on the stream.  Asynchronous.  The state is allocated
- * on first use: ENOMEM if the device cannot hold it, with the queue and the
- * register left as they were (the handle can still be destroyed). */
+ * on first use: ENOMEM if it would not fit (mem_limit, else the device's free
+ * memory, checked before allocating), with the queue and the register left as
+ * they were (the handle can still be destroyed).  A failure after some of the
+ * flush's kernels were enqueued drops the queue (its gates would otherwise
+ * run twice) and leaves the state invalid: every call that needs it returns
+ * EDEVICE until qsv_reset or qsv_set_state.  For tests of this path the
+ * environment variable QSV_INJECT_LAUNCH_FAILURE=k, read by qsv_create, makes
+ * the handle's launch number k (counted from 0) fail without launching. */
 qsv_status qsv_flush(qsv_sim *sim);
 
 /* Wait for the stream; EDEVICE if any enqueued work failed. */

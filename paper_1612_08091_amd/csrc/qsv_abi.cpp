@@ -39,6 +39,9 @@ struct qsv_sim {
     int pos_of[64];                    // qubit id -> bit position, -1 if free
     std::vector<Gate> queue;
     bool materialized = false;         // device buffer holds the state
+    bool invalid = false;              // a flush failed after enqueueing kernels
+    int64_t inject_fail_at = -1;       // tests of error handling: launch number that fails
+    int64_t launches_seen = 0;
     void *d_state = nullptr;
     bool owns_state = false;
     uint64_t cap_amps = 0;             // amplitudes the device buffer holds
@@ -143,10 +146,25 @@ qsv_status ensure_capacity(qsv_sim *s, int nq) {
     if (need <= s->cap_amps) return QSV_OK;
     if (!s->owns_state && s->d_state)
         return fail(s, QSV_ENOMEM, "borrowed state buffer too small");
-    // grow: at least 2^10 amplitudes, doubling
     uint64_t amps = std::max<uint64_t>(need, 1024);
+    const uint64_t bytes = amps * s->elem();
+    // decided before allocating: against the handle's limit when it has one
+    // (no device call), else against the device's free memory
+    if (s->opt.mem_limit != 0) {
+        if (bytes > s->opt.mem_limit)
+            return fail(s, QSV_ENOMEM, "the state needs " + std::to_string(bytes) +
+                                           " bytes, over the handle's mem_limit of " +
+                                           std::to_string(s->opt.mem_limit));
+    } else {
+        size_t free_b = 0, total_b = 0;
+        QSV_HIP(s, hipMemGetInfo(&free_b, &total_b));
+        if (bytes > free_b)
+            return fail(s, QSV_ENOMEM, "the state needs " + std::to_string(bytes) +
+                                           " bytes, the device has " + std::to_string(free_b) +
+                                           " free of " + std::to_string(total_b));
+    }
     void *nb = nullptr;
-    hipError_t e = hipMalloc(&nb, amps * s->elem());
+    hipError_t e = hipMalloc(&nb, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
@@ -166,7 +184,14 @@ qsv_status ensure_capacity(qsv_sim *s, int nq) {
     return QSV_OK;
 }
 
+qsv_status invalid_state(qsv_sim *s) {
+    return fail(s, QSV_EDEVICE,
+                "the state is invalid after a flush that failed part way; call qsv_reset or "
+                "qsv_set_state");
+}
+
 qsv_status materialize(qsv_sim *s) {
+    if (s->invalid) return invalid_state(s);
     if (s->materialized) return QSV_OK;
     QSV_TRY(ensure_capacity(s, s->n));
     QSV_HIP(s, qsv::dev::fill_basis0(s->opt.dtype, s->d_state, s->dim(), s->stream));
@@ -295,7 +320,17 @@ int reg_bits_for(const qsv_sim *s) {
     return qsv::dev::tile_reg_bits(s->opt.dtype);
 }
 
+// Every kernel launch of a flush passes here first.  QSV_INJECT_LAUNCH_FAILURE=k
+// (read at qsv_create; for tests of error handling) makes launch number k of
+// the handle fail as a device error would, without launching it.
+qsv_status launch_gate(qsv_sim *s) {
+    if (s->inject_fail_at >= 0 && s->launches_seen++ == s->inject_fail_at)
+        return fail(s, QSV_EDEVICE, "injected launch failure");
+    return QSV_OK;
+}
+
 qsv_status launch_op(qsv_sim *s, const Op &op) {
+    QSV_TRY(launch_gate(s));
     const int nq = s->n;
     const int k = op.k;
     const int c = popc(op.ctrl);
@@ -416,6 +451,7 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
             lo += nl;
             continue;
         }
+        QSV_TRY(launch_gate(s));
         qsv::dev::TileArgs ta{};
         ta.m = pg.m;
         ta.nq = nq;
@@ -499,25 +535,44 @@ std::vector<Op> canonical_queue(const qsv_sim *s, uint64_t *dropped) {
 }
 
 qsv_status do_flush(qsv_sim *s) {
+    if (s->invalid) return invalid_state(s);
     if (s->queue.empty()) return QSV_OK;
     QSV_TRY(materialize(s));
     std::vector<Op> ops = canonical_queue(s, nullptr);
+    const uint64_t kernels0 = s->stats.kernels;
+    auto run = [&]() -> qsv_status {
+        const int mode = s->opt.mode;
+        if (mode == QSV_MODE_PERGATE) {
+            s->stats.fused_ops += ops.size();
+            for (const Op &op : ops) QSV_TRY(launch_op(s, op));
+        } else if (mode == QSV_MODE_FUSED) {
+            std::vector<Op> f = qsv::fuse(ops, s->opt.k_max);
+            s->stats.fused_ops += f.size();
+            for (const Op &op : f) QSV_TRY(launch_op(s, op));
+        } else {
+            const int m = std::min(tile_bits_for(s), s->n);
+            std::vector<Pass> passes = plan_flush(s, ops, m);
+            for (const Pass &p : passes) s->stats.fused_ops += p.ops.size();
+            QSV_TRY(run_tile_passes(s, passes));
+        }
+        return QSV_OK;
+    };
+    const qsv_status st = run();
+    if (st != QSV_OK) {
+        // Kernels already enqueued have changed the state: applying the queue
+        // again would apply those gates twice.  Drop it and refuse the state
+        // until it is reset or set.  With nothing enqueued the queue stays.
+        if (s->stats.kernels != kernels0) {
+            s->queue.clear();
+            s->invalid = true;
+            s->err += " (after " + std::to_string(s->stats.kernels - kernels0) +
+                      " kernels of the flush ran: the queue is dropped and the state is invalid "
+                      "until qsv_reset or qsv_set_state)";
+        }
+        return st;
+    }
     s->stats.gates += s->queue.size();
     s->stats.amp_gate_updates += (double)s->queue.size() * (double)s->dim();
-    const int mode = s->opt.mode;
-    if (mode == QSV_MODE_PERGATE) {
-        s->stats.fused_ops += ops.size();
-        for (const Op &op : ops) QSV_TRY(launch_op(s, op));
-    } else if (mode == QSV_MODE_FUSED) {
-        std::vector<Op> f = qsv::fuse(ops, s->opt.k_max);
-        s->stats.fused_ops += f.size();
-        for (const Op &op : f) QSV_TRY(launch_op(s, op));
-    } else {
-        const int m = std::min(tile_bits_for(s), s->n);
-        std::vector<Pass> passes = plan_flush(s, ops, m);
-        for (const Pass &p : passes) s->stats.fused_ops += p.ops.size();
-        QSV_TRY(run_tile_passes(s, passes));
-    }
     s->queue.clear();
     return QSV_OK;
 }
@@ -649,6 +704,7 @@ qsv_status qsv_create(const qsv_options *opt, qsv_sim **out) {
     qsv_sim *s = new qsv_sim();
     s->opt = *opt;
     s->stream = (hipStream_t)opt->stream;
+    if (const char *e = std::getenv("QSV_INJECT_LAUNCH_FAILURE")) s->inject_fail_at = std::atoll(e);
     for (int i = 0; i < 64; ++i) s->pos_of[i] = -1;
     if (opt->state) {
         s->d_state = opt->state;
@@ -1306,6 +1362,7 @@ qsv_status qsv_set_state(qsv_sim *s, const void *src, int32_t src_is_device) {
     QSV_CHECK(s);
     if (!src) return fail(s, QSV_EINVAL, "NULL source");
     s->queue.clear();
+    s->invalid = false;
     QSV_TRY(ensure_capacity(s, s->n));
     if (!s->d_small) QSV_HIP(s, hipMalloc((void **)&s->d_small, 64 * sizeof(double)));
     QSV_HIP(s, hipMemcpyAsync(s->d_state, src, s->dim() * s->elem(),
@@ -1375,6 +1432,7 @@ qsv_status qsv_get_kernel_times(qsv_sim *s, int32_t kclass, double *ms, uint64_t
 qsv_status qsv_reset(qsv_sim *s) {
     QSV_CHECK(s);
     s->queue.clear();
+    s->invalid = false;
     if (!s->materialized) return QSV_OK;
     QSV_HIP(s, qsv::dev::fill_basis0(s->opt.dtype, s->d_state, s->dim(), s->stream));
     return QSV_OK;

@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
                 ("queue_limit", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("state", ctypes.c_void_p), ("state_bytes", ctypes.c_uint64),
                 ("timing", ctypes.c_int32), ("reg_bits", ctypes.c_int32),
-                ("relabel", ctypes.c_int32)]
+                ("relabel", ctypes.c_int32), ("mem_limit", ctypes.c_uint64)]
 
 
 class Stats(ctypes.Structure):
@@ -182,7 +182,7 @@ class Simulator:
     def __init__(self, n_max: int = 30, dtype="c128", mode="tiled", k_max: int = 2,
                  tile_bits: int = 0, queue_limit: int = 0, stream=None, state=None,
                  use_torch_stream: bool = True, timing: bool = False, reg_bits: int = 0,
-                 relabel: bool = True):
+                 relabel: bool = True, mem_limit: int = 0):
         opt = Options()
         _check(lib.qsv_options_default(ctypes.byref(opt)))
         opt.n_max = n_max
@@ -194,6 +194,7 @@ class Simulator:
         opt.timing = int(bool(timing))
         opt.reg_bits = reg_bits
         opt.relabel = int(bool(relabel))
+        opt.mem_limit = int(mem_limit)
         if stream is None and use_torch_stream:
             stream = _torch_stream()
         opt.stream = stream

@@ -293,3 +293,23 @@ def test_bench_traffic_is_tied_to_the_kernel_sources():
         assert b.measured_traffic() is None
     finally:
         b.TRAFFIC.update(t)
+
+
+def test_enomem_decided_on_the_host_before_allocating():
+    """With a mem_limit the allocation decision needs no device: the first
+    flush of a state larger than the limit fails with ENOMEM before any HIP
+    call, and the queue and the register stay as they were."""
+    s = Q.Simulator(n_max=20, mem_limit=1 << 20, use_torch_stream=False)
+    ids = s.allocate(20)
+    s.apply(W.H, [ids[0]])
+    s.apply(W.X, [ids[1]], [ids[0]])
+    with pytest.raises(Q.QsvError) as ei:
+        s.flush()
+    assert ei.value.code == 2
+    assert "16777216 bytes" in str(ei.value) and "mem_limit" in str(ei.value)
+    ops, _ = s.plan()
+    assert len(ops) == 1        # the queue is kept (H and CNOT fuse into one op)
+    with pytest.raises(Q.QsvError) as ei:
+        s.flush()
+    assert ei.value.code == 2
+    s.close()

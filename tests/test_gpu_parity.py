@@ -385,6 +385,62 @@ def test_state_beyond_device_memory_fails_cleanly():
     t.close()
 
 
+def test_state_beyond_device_memory_message_names_free_memory():
+    # the figure comes from hipMemGetInfo before any allocation is tried
+    s = make(35, dtype="c128")
+    s.apply(W.H, [0], [])
+    with pytest.raises(Q.QsvError) as ei:
+        s.flush()
+    assert ei.value.code == 2 and "free of" in str(ei.value), str(ei.value)
+    s.close()
+
+
+def test_mem_limit_bounds_the_state():
+    # 2^16 complex128 amplitudes take 1 MiB: a limit of exactly that fits, one
+    # byte less does not
+    rng = np.random.default_rng(36)
+    circ = random_circuit(rng, 16, 40)
+    ok = Q.Simulator(n_max=16, use_torch_stream=False, mem_limit=1 << 20)
+    ok.allocate(16)
+    ok.run(circ)
+    check_c128(ok.get_state(), oracle.run(circ))
+    ok.close()
+    bad = Q.Simulator(n_max=16, use_torch_stream=False, mem_limit=(1 << 20) - 1)
+    bad.allocate(16)
+    bad.run(circ)
+    with pytest.raises(Q.QsvError) as ei:
+        bad.flush()
+    assert ei.value.code == 2 and "mem_limit" in str(ei.value)
+    bad.close()
+
+
+@pytest.mark.parametrize("mode,k_max,fail_at", [("pergate", 1, 3), ("tiled", 2, 1)])
+def test_failure_part_way_through_a_flush(monkeypatch, mode, k_max, fail_at):
+    """A launch that fails after earlier kernels of the flush ran: the queue
+    is dropped (its gates would run twice) and the state is refused until it
+    is reset; then the handle works again.  The failure is injected on the
+    host (the launch is skipped, no kernel fails)."""
+    n = 16
+    rng = np.random.default_rng(37)
+    circ = random_circuit(rng, n, 60)
+    monkeypatch.setenv("QSV_INJECT_LAUNCH_FAILURE", str(fail_at))
+    s = Q.Simulator(n_max=n, mode=mode, k_max=k_max, tile_bits=12, use_torch_stream=False)
+    monkeypatch.delenv("QSV_INJECT_LAUNCH_FAILURE")
+    s.allocate(n)
+    s.run(circ)
+    with pytest.raises(Q.QsvError) as ei:
+        s.flush()
+    assert ei.value.code == 3 and "injected" in str(ei.value) and "invalid" in str(ei.value)
+    assert s.plan()[0] == []                       # the queue is gone
+    with pytest.raises(Q.QsvError) as ei:
+        s.norm2()
+    assert ei.value.code == 3 and "invalid" in str(ei.value)
+    s.reset()
+    s.run(circ)
+    check_c128(s.get_state(), oracle.run(circ))
+    s.close()
+
+
 def test_allocate_deallocate_sequence():
     rng = np.random.default_rng(14)
     s = Q.Simulator(n_max=12, use_torch_stream=False)
