@@ -315,7 +315,7 @@ int oracle_apply_math(double *psi_d, int n, int w, const int *qubits,
 }
 
 /* ------------------------------------------------------------------------
- * Density matrices (Sec. 4.3.3 names a density-matrix simulator for noise as
+ * Density matrices (Sec. 4.3.2 names a density-matrix simulator for noise as
  * future work).  rho is 2^n x 2^n, row-major, rho[r * 2^n + c].
  * ---------------------------------------------------------------------- */
 
