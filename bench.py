@@ -758,6 +758,17 @@ def main():
             "energy_abs_diff_vs_fp64": abs(leg32["energy"] - main_leg["energy"]),
             "speedup_vs_fp64_fused": main_leg["ms_per_step"] / leg32["ms_per_step"],
         }
+        if ms32:
+            # the FP32 tile kernel against both bounds: HBM (half the bytes
+            # of FP64) and the vector ALU (FP32 issues at the FP64 rate here:
+            # packed FP32 math is off)
+            f32 = leg32["stats"]["alg_flops"] / max(l32, 1)
+            t32 = ms32 / max(l32, 1) * 1e-3
+            gbps = (b32 / max(l32, 1)) / t32
+            extra["fp32_fused"]["roofline"] = {
+                "hbm_frac": gbps / HBM_PEAK, "frac_of_copy": gbps / (copy["GBps"] * 1e9),
+                "alu_TFLOPs": f32 / t32 / 1e12, "alu_frac": f32 / t32 / FP64_PEAK,
+                "bound": "alu" if f32 / t32 / FP64_PEAK > gbps / (copy["GBps"] * 1e9) else "hbm"}
         log("fp32 leg: %.2f ms/step" % leg32["ms_per_step"])
         pg = run_leg(circ, ham, u, 1, 0, "c128", "pergate", 1, 0, reduce=False)
         d_ms, d_l, d_b = pg["ktimes"]["dense"]
@@ -767,6 +778,8 @@ def main():
             "ms_per_step": pg["ms_per_step"],
             "dense_1q_GBps": d_b / (d_ms * 1e-3) / 1e9 if d_ms else None,
             "cnot_GBps": m_b / (m_ms * 1e-3) / 1e9 if m_ms else None,
+            "dense_1q_frac_of_copy": d_b / (d_ms * 1e-3) / (copy["GBps"] * 1e9) if d_ms else None,
+            "cnot_frac_of_copy": m_b / (m_ms * 1e-3) / (copy["GBps"] * 1e9) if m_ms else None,
             "pct_hbm_peak": pg["stats"]["alg_bytes"] / (pg["ms_per_step"] * 1e-3) / HBM_PEAK,
         }
         extra["fp64_fused_speedup_vs_fp64_pergate"] = pg["ms_per_step"] / main_leg["ms_per_step"]

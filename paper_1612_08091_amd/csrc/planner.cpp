@@ -439,6 +439,38 @@ std::vector<Pass> plan_passes_relabel(const std::vector<Op> &ops, int n, int m, 
             }
             if (!in_pass.empty()) break;
         }
+        // Fill the tile up to m qubits: first with qubits that let a qubit
+        // done for this flush go back to its own position (the qubit now at
+        // a done qubit's own position, or a done qubit whose own position is
+        // in the tile), while the tile stays within kFillPages page
+        // positions; then with the qubits at the lowest positions.
+        {
+            uint64_t later = 0;
+            for (int j : deferred) later |= all[j];
+            auto tile_pages = [&](uint64_t t) {
+                int h = 0;
+                for (int q = 0; q < n; ++q)
+                    if (((t >> q) & 1) && pos[q] >= page_bit) ++h;
+                return h;
+            };
+            constexpr int kFillPages = 5;
+            bool grew = true;
+            while (grew && popc(tile) < m) {
+                grew = false;
+                for (int q = 0; q < n && popc(tile) < m; ++q) {
+                    if (((later >> q) & 1) || pos[q] == q) continue;   // in use later, or home
+                    const int r = at[q];                                // the qubit at q's position
+                    uint64_t add = 0;
+                    if (((tile >> q) & 1) && !((tile >> r) & 1)) add = 1ull << r;
+                    else if (!((tile >> q) & 1) && ((tile >> r) & 1)) add = 1ull << q;
+                    if (!add) continue;
+                    const uint64_t t2 = tile | add;
+                    if (tile_pages(t2) > std::max(kFillPages, tile_pages(tile))) continue;
+                    tile = t2;
+                    grew = true;
+                }
+            }
+        }
         for (int p = 0; p < n && popc(tile) < m; ++p) tile |= 1ull << at[p];
         Pass ps;
         ps.tile = to_positions(tile);
