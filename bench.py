@@ -34,16 +34,16 @@ HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 FP64_PEAK = 78.6e12        # MI355X FP64 (vector and matrix), flop/s
 
 # Measured HBM traffic of the dominant kernel (k_tile_reg<double,4,8,*>: the
-# instance with table ops, 132 of 144 launches in the profiled run, and the
-# one without, the 12 passes that only move qubits back), from two rocprofv3
+# instance with table ops, 132 of 141 launches in the profiled run, and the
+# one without, the 9 passes that only move qubits back), from two rocprofv3
 # --pmc runs of this script's main leg (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch, mean over the tile dispatches).  The counters are scaled by what
 # they read for the copy probe of the same runs (16 GiB read + 16 GiB
 # written: FETCH_SIZE reads half the bytes, WRITE_SIZE all of them).  Valid
 # only for the sources they were taken with: the digest below covers every
 # file that shapes the kernel or its launches.
-TRAFFIC = {"kernel": "k_tile_reg<double,4,8,*>", "fetch_kib": 8395107.6, "write_kib": 16785434.3,
-           "fetch_scale": 2.0, "write_scale": 1.0, "digest": "72239be7fd8213f9"}
+TRAFFIC = {"kernel": "k_tile_reg<double,4,8,*>", "fetch_kib": 8395425.1, "write_kib": 16785437.0,
+           "fetch_scale": 2.0, "write_scale": 1.0, "digest": "cb66bb4f2b5f5888"}
 TRAFFIC_SOURCES = ("paper_1612_08091_amd/csrc/kernels_tile.hip",
                    "paper_1612_08091_amd/csrc/lds_ops.hpp",
                    "paper_1612_08091_amd/csrc/device.hpp",
