@@ -108,6 +108,31 @@ def test_random_circuits_c128(mode, k_max, tile_bits, n):
     s.close()
 
 
+@pytest.mark.parametrize("n,k_max,dtype", [(18, 3, "c128"), (20, 4, "c128"), (18, 5, "c64")])
+def test_relabeling_plans_on_the_lds_kernel(n, k_max, dtype):
+    """Fusion wider than 2 qubits sends passes to the LDS-tile kernel (MFMA
+    for the 3- to 5-qubit ops); with relabeling those passes store their
+    tiles to the new positions (the host model covers only the register
+    kernel, so this path is checked here).  The relabeling plan must be the
+    one taken (fewer passes than with fixed positions)."""
+    circ = W.config1_random(n, layers=30)
+    log("case relabel lds", n, k_max, dtype)
+    fixed = make(n, mode="tiled", k_max=k_max, dtype=dtype, relabel=False)
+    fixed.run(circ)
+    _, p_fixed = fixed.plan()
+    fixed.close()
+    s = make(n, mode="tiled", k_max=k_max, dtype=dtype)
+    s.run(circ)
+    _, p_moved = s.plan()
+    assert p_moved < p_fixed
+    got = s.get_state()
+    s.close()
+    if dtype == "c128":
+        check_c128(got, oracle.run(circ))
+    else:
+        check_c64(got, oracle.run(circ))
+
+
 @pytest.mark.parametrize("mode,k_max", [("pergate", 1), ("fused", 3), ("fused", 5), ("tiled", 3),
                                         ("tiled", 5)])
 def test_random_circuits_c64(mode, k_max):
