@@ -98,6 +98,36 @@ int main() {
             for (bool relabel : {false, true}) {
                 const int m = 12, rb = 4;
                 std::vector<Pass> passes = plan_tiled(ops, n, m, k_max, 9, relabel);
+                // relabeling: each pass permutes positions inside its tile
+                // only, and the passes together leave every qubit home
+                int at[64];
+                for (int p = 0; p < 64; ++p) at[p] = p;
+                for (const Pass &ps : passes) {
+                    if (ps.dest.empty()) continue;
+                    if ((int)ps.dest.size() != n) {
+                        std::fprintf(stderr, "dest of size %zu for %d qubits\n", ps.dest.size(), n);
+                        return 1;
+                    }
+                    uint64_t img = 0;
+                    for (int p = 0; p < n; ++p) {
+                        const int d = ps.dest[p];
+                        const bool in = (ps.tile >> p) & 1;
+                        if ((!in && d != p) || (in && !((ps.tile >> d) & 1)) || ((img >> d) & 1)) {
+                            std::fprintf(stderr, "dest is not a permutation of the tile\n");
+                            return 1;
+                        }
+                        img |= 1ull << d;
+                    }
+                    int nat[64];
+                    for (int p = 0; p < 64; ++p) nat[p] = at[p];
+                    for (int p = 0; p < n; ++p) nat[ps.dest[p]] = at[p];
+                    for (int p = 0; p < 64; ++p) at[p] = nat[p];
+                }
+                for (int p = 0; p < n; ++p)
+                    if (at[p] != p) {
+                        std::fprintf(stderr, "qubit %d ends at position %d\n", at[p], p);
+                        return 1;
+                    }
                 std::vector<cd> psi = psi0;
                 bool all_reg = true;
                 for (const Pass &ps : passes) {
