@@ -484,6 +484,21 @@ def form_batched(pergate_sample: int = 256):
         out[dt] = {"circuits_per_s": len(circuits) / best, "s_per_batch": best,
                    "device_ms": info["last_ms"], "tile_bits": info["tile_bits"],
                    "k_fuse": info["k_fuse"], "setup_s_incl_autotune": setup}
+        # Bytes the Pauli sums of the circuits above the LDS limit read (each
+        # term sweeps its circuit's state once; the smaller circuits never
+        # leave LDS).  A lower bound on the batch's memory traffic, most of
+        # it served by L2 and the last-level cache since each state is
+        # re-read per term.
+        elem = 8 if dt == "c64" else 16
+        mb = info["tile_bits"]
+        sweep = float(sum(len(h.coeff) * (1 << c.n) * elem
+                          for c, h in zip(circuits, hams) if c.n > mb))
+        out[dt]["roofline"] = {
+            "pauli_sweep_bytes": sweep,
+            "pauli_sweep_GBps": sweep / (info["last_ms"] * 1e-3) / 1e9 if info["last_ms"] else None,
+            "frac_of_hbm_peak": sweep / (info["last_ms"] * 1e-3) / HBM_PEAK if info["last_ms"] else None,
+            "note": "Pauli-sweep reads only over the whole batch time; the tile passes of the "
+                    "large circuits add 2 x state per pass"}
         log("  batched %s: %.4f s per batch" % (dt, best))
     out["c64"]["max_abs_err_over_sum_abs_c_vs_c128_batch"] = float(
         np.max(np.abs(vals["c64"] - vals["c128"]) / scale))
