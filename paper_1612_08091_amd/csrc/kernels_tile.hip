@@ -229,7 +229,7 @@ __device__ __forceinline__ void reg_r2(T *amp, const R *m, bool on, uint32_t cre
 // fails the controls outside it reads a table of ones (at byte offset b)
 // rather than skipping the op.  The reads go out four at a time.
 template <typename T, int NR>
-__device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const unsigned char *limg,
+__device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, uint32_t limg_a,
                                          uint64_t base, uint32_t lane, uint32_t wave) {
     uint32_t wr[NR];
 #pragma unroll
@@ -243,7 +243,9 @@ __device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const unsigned
     s_idx ^= op.wwave[wave];
     for (int q = 0; q < op.a; ++q)
         if ((base >> op.gt[q]) & 1) s_idx ^= op.gtb[q];
-    uint32_t v_idx = s_idx;
+    // the image's LDS address (a multiple of every table's size) joins the
+    // uniform part; the lane and register parts then still OR and XOR in
+    uint32_t v_idx = s_idx + limg_a;
     if (lmask != 0) {   // uniform: tables without lane bits skip the lane part
 #pragma unroll
         for (int t = 0; t < 6; ++t)
@@ -253,8 +255,7 @@ __device__ __forceinline__ void reg_diag(T *amp, const RegOp &op, const unsigned
     for (int i0 = 0; i0 < NR; i0 += 4) {
         T f[4];
 #pragma unroll
-        for (int i = 0; i < 4 && i0 + i < NR; ++i)
-            f[i] = *reinterpret_cast<const T *>(limg + (v_idx ^ wr[i0 + i]));
+        for (int i = 0; i < 4 && i0 + i < NR; ++i) lds_read(v_idx ^ wr[i0 + i], f[i]);
 #pragma unroll
         for (int i = 0; i < 4 && i0 + i < NR; ++i) amp[i0 + i] = cmul(f[i], amp[i0 + i]);
     }
@@ -279,7 +280,7 @@ __device__ __forceinline__ void wave_sync() {
 // workgroup barrier); 0: a workgroup remap; 2: a workgroup remap that first
 // waits for every wave to leave its region of an earlier wave-local one.
 template <typename T, int NR, int J>
-__device__ __forceinline__ void remap_half(T *amp, unsigned char *lds, uint32_t wt, uint32_t rt,
+__device__ __forceinline__ void remap_half(T *amp, uint32_t wt, uint32_t rt,
                                            const uint32_t *wr, const uint32_t *rd, int mode) {
     if (mode == 2) __syncthreads();
     // the thread parts pass through an empty asm in each phase, so the
@@ -292,7 +293,7 @@ __device__ __forceinline__ void remap_half(T *amp, unsigned char *lds, uint32_t 
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             if (((i >> J) & 1) != p) continue;
-            *reinterpret_cast<T *>(lds + (w ^ wr[i])) = amp[i];
+            lds_write(w ^ wr[i], amp[i]);
         }
         if (mode == 1) wave_sync();
         else __syncthreads();
@@ -301,7 +302,7 @@ __device__ __forceinline__ void remap_half(T *amp, unsigned char *lds, uint32_t 
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             if (((i >> J) & 1) != p) continue;
-            amp[i] = *reinterpret_cast<const T *>(lds + (r ^ rd[i]));
+            lds_read(r ^ rd[i], amp[i]);
         }
         if (mode == 1) wave_sync();
         else __syncthreads();
@@ -376,9 +377,8 @@ __device__ __forceinline__ void dispatch_2(T *amp, int kind, int a, int b, const
 // read up front, so their scalar loads go out in one burst and the op waits
 // once instead of once per dependent field.
 template <typename T, typename R, int NR, int RB, bool DG>
-__device__ __forceinline__ void reg_op(T *amp, const RegOp &op, unsigned char *lds,
-                                       const unsigned char *limg, uint64_t base, uint32_t lane,
-                                       uint32_t wave) {
+__device__ __forceinline__ void reg_op(T *amp, const RegOp &op, uint32_t lds_a, uint32_t limg_a,
+                                       uint64_t base, uint32_t lane, uint32_t wave) {
     const int kind = op.kind;
     const int a = op.a, b = op.b;
     const uint32_t creg = op.creg;
@@ -395,24 +395,26 @@ __device__ __forceinline__ void reg_op(T *amp, const RegOp &op, unsigned char *l
             wr[i] = op.wr[i];
             rd[i] = op.rd[i];
         }
-        const uint32_t *lw = reinterpret_cast<const uint32_t *>(limg + op.lane_off);
-        const uint32_t wt = lw[lane] ^ op.wwave[wave];
-        const uint32_t rt = lw[64 + lane] ^ op.rwave[wave];
+        // the remap buffer's LDS address (a multiple of its size) joins the
+        // thread parts; the register parts then XOR in
+        const uint32_t lw = limg_a + op.lane_off + 4u * lane;
+        const uint32_t wt = (lds_read_u32(lw) ^ op.wwave[wave]) + lds_a;
+        const uint32_t rt = (lds_read_u32(lw + 256u) ^ op.rwave[wave]) + lds_a;
         // raised priority through the remap (LDS round trips and barriers
         // that the whole workgroup waits on), as for the tile's stores and
         // loads
         __builtin_amdgcn_s_setprio(2);
         switch (a) {
-            QSV_SLOT1(0, (remap_half<T, NR, 0>(amp, lds, wt, rt, wr, rd, b)))
-            QSV_SLOT1(1, (remap_half<T, NR, 1>(amp, lds, wt, rt, wr, rd, b)))
-            QSV_SLOT1(2, (remap_half<T, NR, 2>(amp, lds, wt, rt, wr, rd, b)))
-            QSV_SLOT1(3, (remap_half<T, NR, 3>(amp, lds, wt, rt, wr, rd, b)))
-            QSV_SLOT1(4, (remap_half<T, NR, 4>(amp, lds, wt, rt, wr, rd, b)))
+            QSV_SLOT1(0, (remap_half<T, NR, 0>(amp, wt, rt, wr, rd, b)))
+            QSV_SLOT1(1, (remap_half<T, NR, 1>(amp, wt, rt, wr, rd, b)))
+            QSV_SLOT1(2, (remap_half<T, NR, 2>(amp, wt, rt, wr, rd, b)))
+            QSV_SLOT1(3, (remap_half<T, NR, 3>(amp, wt, rt, wr, rd, b)))
+            QSV_SLOT1(4, (remap_half<T, NR, 4>(amp, wt, rt, wr, rd, b)))
         default: __builtin_unreachable();
         }
         __builtin_amdgcn_s_setprio(0);
     } else if (kind == ROP_DIAG) {
-        if constexpr (DG) reg_diag<T, NR>(amp, op, limg, base, lane, wave);
+        if constexpr (DG) reg_diag<T, NR>(amp, op, limg_a, base, lane, wave);
         else __builtin_unreachable();
     } else if (creg == 0 && octrl == 0 && lane_ok == ~0ull && wave_ok == ~0u) {
         if (kind == ROP_G2 || kind == ROP_R2)
@@ -492,8 +494,11 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
     constexpr int m = RB + TB;
     constexpr uint32_t kHalf = (uint32_t)sizeof(T) << (m - 1);
     extern __shared__ __align__(16) unsigned char smem_reg[];
-    unsigned char *lds = smem_reg;
     unsigned char *limg = smem_reg + kHalf;
+    // LDS addresses of the remap buffer and the image (the launch checks
+    // that the dynamic block starts at 0, so both are multiples of kHalf)
+    const uint32_t lds_a = lds_addr(smem_reg);
+    const uint32_t limg_a = lds_a + kHalf;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -552,8 +557,8 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
         // without copies at the loop back edge.  Op fields are read through
         // references into the uniform op array so they stay scalar.
         for (int oi = 0; oi < ta.n_ops; oi += 2) {
-            reg_op<T, R, NR, RB, DG>(amp, ops[oi], lds, limg, base, lane, wave);
-            reg_op<T, R, NR, RB, DG>(amp, ops[oi + 1], lds, limg, base, lane, wave);
+            reg_op<T, R, NR, RB, DG>(amp, ops[oi], lds_a, limg_a, base, lane, wave);
+            reg_op<T, R, NR, RB, DG>(amp, ops[oi + 1], lds_a, limg_a, base, lane, wave);
         }
         // a pass that moves its qubits stores where other threads loaded:
         // every load of the tile completes before the first store
@@ -656,7 +661,13 @@ static hipError_t launch_reg_t(void *psi, const TileArgs &ta, const RegOp *rops,
     static int cus = 0;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = set_lds_attr(k_tile_reg<R, RB, TB, DG>, half + kRegImageMax + 16);
+        // the kernel forms LDS addresses by XOR on top of the dynamic block's
+        // base, which is then 0 only without static LDS
+        hipFuncAttributes fa;
+        hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_tile_reg<R, RB, TB, DG>));
+        if (e != hipSuccess) return e;
+        if (fa.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
+        e = set_lds_attr(k_tile_reg<R, RB, TB, DG>, half + kRegImageMax + 16);
         if (e != hipSuccess) return e;
         int dev = 0;
         e = hipGetDevice(&dev);

@@ -44,6 +44,41 @@ __device__ __forceinline__ void gstore(float2 *p, float2 a) {
     *(g_fvec2 *)p = v;
 }
 
+// LDS accesses at byte addresses formed as integers.  An access through a
+// pointer into the dynamic LDS block compiles to an add of the block's base
+// (a link-time symbol, 0 in a kernel without static LDS) before every access;
+// an address formed once per op, base included, and XORed per access saves
+// that add.  The XOR equals the add where the base is a multiple of the span
+// of the XORed bits, which the callers check on the host (no static LDS: the
+// dynamic block starts at 0).
+typedef __attribute__((address_space(3))) dvec2 l_dvec2;
+typedef __attribute__((address_space(3))) fvec2 l_fvec2;
+typedef __attribute__((address_space(3))) uint32_t l_u32;
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+__device__ __forceinline__ void lds_read(uint32_t a, double2 &out) {
+    const dvec2 v = *(const l_dvec2 *)(uintptr_t)a;
+    out = make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void lds_read(uint32_t a, float2 &out) {
+    const fvec2 v = *(const l_fvec2 *)(uintptr_t)a;
+    out = make_float2(v.x, v.y);
+}
+__device__ __forceinline__ uint32_t lds_read_u32(uint32_t a) { return *(const l_u32 *)(uintptr_t)a; }
+__device__ __forceinline__ void lds_write(uint32_t a, double2 x) {
+    dvec2 v;
+    v.x = x.x;
+    v.y = x.y;
+    *(l_dvec2 *)(uintptr_t)a = v;
+}
+__device__ __forceinline__ void lds_write(uint32_t a, float2 x) {
+    fvec2 v;
+    v.x = x.x;
+    v.y = x.y;
+    *(l_fvec2 *)(uintptr_t)a = v;
+}
+
 // XOR swizzle of an LDS element index: the bits above the 256-byte bank span
 // are folded into the bits below it.  A bijection on [0, 2^m).
 template <typename R> __device__ __forceinline__ uint32_t swz(uint32_t l);

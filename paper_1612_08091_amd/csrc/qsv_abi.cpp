@@ -1474,6 +1474,10 @@ qsv_status qsv_check_tile_programs(qsv_sim *s, double *state, int32_t *info) {
         counts[7] += pg.diag_merged;
         counts[8] += pg.local_remaps;
         counts[9] += pg.permutes ? 1 : 0;
+        if (log_level() >= 2)
+            std::fprintf(stderr, "qsv: check pass %d ops=%zu real=%d diag=%d remaps=%d rops=%zu image=%zuB\n",
+                         counts[0] - 1, ps.ops.size(), pg.real_ops, pg.diag_ops, pg.remaps,
+                         pg.rops.size(), pg.img.size());
         if (log_level() >= 3) {
             auto pos = [](uint64_t g) { return g ? __builtin_ctzll(g) : -1; };
             std::fprintf(stderr, "pass %d: load lanes", counts[0] - 1);
