@@ -119,22 +119,35 @@ struct RegOp {
     uint32_t wave_ok;     // G/R: bit w set if wave w meets them
     uint32_t lane_off;    // REMAP: byte offset of the op's per-lane words in the image
     int64_t mat;          // DIAG: byte offset of the factor table in the image
-    // G/R: the matrix, row-major over (bit 0 <-> a, bit 1 <-> b), inline so
-    // that one burst of scalar loads brings an op's fields and its matrix:
-    // R1 4 and R2 16 reals, G1 4 and G2 16 complex (re, im); in double for a
-    // complex128 state (md) and in float for complex64 (mf)
-    double md[32];
-    float mf[32];
-    uint32_t gt[8];       // DIAG: global positions of the table bits outside the tile
-    uint32_t gtb[8];      //       and their byte weights in the table
-    uint32_t wr[32];      // DIAG: table byte offset of register index i;
-                          // REMAP: buffer byte offset of register i in the old layout
-    uint32_t rd[32];      // REMAP: buffer byte offset of register i in the new layout;
-                          // DIAG: see lane_ok
-    uint32_t wwave[8];    // DIAG: table byte offset of the wave's thread-id bits;
-                          // REMAP: write offset of the wave's thread-id bits
-    uint32_t rwave[8];    // REMAP: read offset of the wave's thread-id bits
+    // The payload of the op's kind.  An op is read through the scalar cache
+    // for every tile, so it keeps to few 64-byte lines: the two kinds share
+    // storage, the fields a kind reads with the header come first, and the
+    // size is a whole number of lines (448 bytes; programs start on 256).
+    union {
+        struct {
+            // G/R: the matrix, row-major over (bit 0 <-> a, bit 1 <-> b),
+            // inline so that one burst of scalar loads brings an op's fields
+            // and its matrix: R1 4 and R2 16 reals, G1 4 and G2 16 complex
+            // (re, im); in double for a complex128 state (md) and in float
+            // for complex64 (mf)
+            double md[32];
+            float mf[32];
+        };
+        struct {
+            uint32_t gt[8];       // DIAG: global positions of the table bits outside the tile
+            uint32_t gtb[8];      //       and their byte weights in the table
+            uint32_t wwave[8];    // DIAG: table byte offset of the wave's thread-id bits;
+                                  // REMAP: write offset of the wave's thread-id bits
+            uint32_t rwave[8];    // REMAP: read offset of the wave's thread-id bits
+            uint32_t wr[32];      // DIAG: table byte offset of register index i;
+                                  // REMAP: buffer byte offset of register i in the old layout
+            uint32_t rd[32];      // REMAP: buffer byte offset of register i in the new layout;
+                                  // DIAG: see lane_ok
+        };
+    };
+    uint32_t pad_[4];
 };
+static_assert(sizeof(RegOp) % 64 == 0, "register ops start on scalar cache lines");
 
 // ------------------------------------------------------------------ gates
 // dtype: 0 = complex128, 1 = complex64.  Sizes in amplitudes.
