@@ -410,6 +410,11 @@ typedef struct qsv_batch_options {
     int32_t use_graph;        /* 1: capture the launch in a HIP graph */
     void *stream;
     const char *tune_cache;   /* JSON cache path, NULL = none */
+    int32_t big_per_workgroup;/* circuits whose state exceeds the LDS tile: 0 (default) run
+                                 pass-major, each state in its own device region, one launch
+                                 per pass index over all their tiles, their Pauli sums in
+                                 chunks (when the states fit in half the free device memory);
+                                 1: each runs on one workgroup of the persistent launch */
 } qsv_batch_options;
 
 qsv_status qsv_batch_create(int32_t count, const qsv_circuit *circuits,

@@ -263,6 +263,17 @@ struct BatchTerm {
     int32_t ny;
     int32_t pad;
 };
+// A run of consecutive work items of one launch that belong to one circuit:
+// a pass's tiles (item - first = tile index) or a state's Pauli chunks
+// (item - first = chunk index).  Segments of a launch are ordered by first.
+struct BatchSeg {
+    uint64_t first;
+    uint64_t state_off;       // amplitude offset of the circuit's state in `states`
+    int32_t pass;             // pass launches: the BatchPass
+    int32_t circuit;          // the BatchCircuit
+    int32_t init;             // 1: the circuit's first pass (tiles start from |0...0>)
+    int32_t pad;
+};
 struct BatchLaunch {
     const BatchCircuit *circuits;
     const int32_t *order;     // processing order (longest first)
@@ -278,9 +289,25 @@ struct BatchLaunch {
     double *out;
     unsigned int grid;
     int32_t mfma_k;           // widest matrix-core op (0 = none), at most 5
+    // Pass-major circuits (more qubits than the LDS holds), each with its
+    // state in its own region of `states`: launch i < n_pass_launches runs
+    // pass i of every such circuit that has one, over all its tiles; launch
+    // n_pass_launches forms the Pauli sums in chunks; a last kernel adds each
+    // circuit's chunk sums in order.  Launch i takes segments
+    // [seg_begin[i], seg_begin[i + 1]) of `segs` and items[i] work items
+    // (host arrays).  count above then counts only the circuits of k_batch.
+    int32_t n_pass_launches;  // 0: no pass-major circuits
+    const BatchSeg *segs;
+    const int32_t *seg_begin; // host, n_pass_launches + 2 entries
+    const uint64_t *items;    // host, n_pass_launches + 1 entries
+    void *states;
+    double *partial;          // one sum per Pauli work item
+    int32_t chunk_log;        // Pauli chunk: 2^chunk_log amplitudes (pairs for X strings)
+    unsigned int grid_big;
 };
 hipError_t batch_launch(int dtype, const BatchLaunch &L, hipStream_t s);
 int batch_occupancy(int dtype, int mb, int mfma_k);   // resident workgroups per CU
+int batch_pass_occupancy(int dtype, int mb, int mfma_k);
 
 // Sampling: out_dev[shots] indices.
 size_t sample_workspace_bytes(int nq);

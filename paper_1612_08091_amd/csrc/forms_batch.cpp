@@ -51,6 +51,13 @@ struct qsv_batch {
     void *d_buf = nullptr;
     void *d_scratch = nullptr;
     size_t scratch_bytes = 0;
+    // pass-major circuits: their states, and the launches' segment ranges
+    // and item counts (host copies that the launches read)
+    bool big_per_wg = false;
+    void *d_states = nullptr;
+    size_t states_bytes = 0;
+    std::vector<int32_t> h_seg_begin;
+    std::vector<uint64_t> h_items;
     qsv::dev::BatchLaunch L{};
     int mb = 0, kfuse = 0;
     hipGraph_t graph = nullptr;
@@ -160,6 +167,12 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
         const int n = b->nq[i];
         const int m = std::min(n, mb);
         std::vector<Pass> ps = qsv::plan_passes(b->ops[i], n, m, std::min(3, m - 1), kf);
+        if (ps.empty() && n > mb) {
+            // a state in global memory is written by its first pass
+            Pass p0;
+            p0.tile = (1ull << m) - 1;
+            ps.push_back(p0);
+        }
         qsv::dev::BatchCircuit &bc = circ[i];
         bc.n = n;
         bc.pass_begin = (int)passes.size();
@@ -196,8 +209,72 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
         cost[i] = dim * (nops + 2.0 * bc.term_count + (n > mb ? 4.0 * ps.size() : 0.0));
         if (n > mb) max_big = std::max(max_big, n);
     }
-    std::vector<int32_t> order(b->count);
-    for (int i = 0; i < b->count; ++i) order[i] = i;
+    // Circuits above the LDS limit run pass-major (one launch per pass index
+    // over all their tiles) when their states fit in half the free device
+    // memory; otherwise, or on request, each runs on one workgroup of the
+    // persistent launch in a slot of its own.
+    const size_t elem = b->dtype == QSV_C128 ? 16 : 8;
+    std::vector<int> big;
+    uint64_t big_amps = 0;
+    for (int i = 0; i < b->count; ++i)
+        if (b->nq[i] > mb) {
+            big.push_back(i);
+            big_amps += 1ull << b->nq[i];
+        }
+    bool pm = !big.empty() && !b->big_per_wg;
+    if (pm) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess || (double)big_amps * elem > 0.5 * (double)fr)
+            pm = false;
+    }
+    if (pm) max_big = 0;
+    std::vector<qsv::dev::BatchSeg> segs;
+    b->h_seg_begin.clear();
+    b->h_items.clear();
+    int n_pass_launches = 0;
+    constexpr int kChunkLog = 14;   // Pauli chunk: 2^14 amplitudes per work item
+    if (pm) {
+        std::vector<uint64_t> state_off(b->count, 0);
+        uint64_t off = 0;
+        for (int i : big) {
+            state_off[i] = off;
+            off += 1ull << b->nq[i];
+        }
+        for (int i : big) n_pass_launches = std::max(n_pass_launches, circ[i].pass_count);
+        for (int p = 0; p < n_pass_launches; ++p) {
+            b->h_seg_begin.push_back((int32_t)segs.size());
+            uint64_t it = 0;
+            for (int i : big) {
+                if (circ[i].pass_count <= p) continue;
+                qsv::dev::BatchSeg sg{};
+                sg.first = it;
+                sg.state_off = state_off[i];
+                sg.pass = circ[i].pass_begin + p;
+                sg.circuit = i;
+                sg.init = p == 0 ? 1 : 0;
+                segs.push_back(sg);
+                it += 1ull << (b->nq[i] - passes[sg.pass].m);
+            }
+            b->h_items.push_back(it);
+        }
+        b->h_seg_begin.push_back((int32_t)segs.size());
+        uint64_t it = 0;
+        for (int i : big) {
+            qsv::dev::BatchSeg sg{};
+            sg.first = it;
+            sg.state_off = state_off[i];
+            sg.pass = -1;
+            sg.circuit = i;
+            segs.push_back(sg);
+            const int cl = std::min(kChunkLog, b->nq[i]);
+            it += 1ull << (b->nq[i] - cl);
+        }
+        b->h_items.push_back(it);
+        b->h_seg_begin.push_back((int32_t)segs.size());
+    }
+    std::vector<int32_t> order;
+    for (int i = 0; i < b->count; ++i)
+        if (!pm || b->nq[i] <= mb) order.push_back(i);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     // matrices in the batch dtype
     std::vector<unsigned char> host;
@@ -215,6 +292,8 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     }
     const size_t o_ctr = put(host, std::vector<uint32_t>(64, 0));
     const size_t o_out = put(host, std::vector<double>(b->count, 0.0));
+    const size_t o_segs = put(host, segs);
+    const size_t o_part = put(host, std::vector<double>(pm ? b->h_items.back() : 1, 0.0));
     hipError_t e = hipMalloc(&b->d_buf, host.size());
     if (e != hipSuccess) return berr(QSV_ENOMEM, "hipMalloc of the batch plan failed");
     e = hipMemcpy(b->d_buf, host.data(), host.size(), hipMemcpyHostToDevice);
@@ -224,9 +303,16 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int occ = std::max(1, qsv::dev::batch_occupancy(b->dtype, mb, mfma_k));
-    const unsigned grid = (unsigned)std::max(1, std::min(cus * occ, b->count));
-    const size_t elem = b->dtype == QSV_C128 ? 16 : 8;
+    const unsigned grid = (unsigned)std::max(1, std::min(cus * occ, (int)order.size()));
     const uint64_t slot = max_big > 0 ? (1ull << max_big) : 1;
+    if (pm && big_amps * elem > b->states_bytes) {
+        if (b->d_states) (void)hipFree(b->d_states);
+        b->d_states = nullptr;
+        b->states_bytes = 0;
+        e = hipMalloc(&b->d_states, big_amps * elem);
+        if (e != hipSuccess) return berr(QSV_ENOMEM, "hipMalloc of the pass-major states failed");
+        b->states_bytes = big_amps * elem;
+    }
     const size_t need = (size_t)grid * slot * elem;
     if (need > b->scratch_bytes) {
         if (b->d_scratch) (void)hipFree(b->d_scratch);
@@ -239,7 +325,7 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     qsv::dev::BatchLaunch &L = b->L;
     L.circuits = (const qsv::dev::BatchCircuit *)(d + o_circ);
     L.order = (const int32_t *)(d + o_order);
-    L.count = b->count;
+    L.count = (int32_t)order.size();
     L.passes = (const qsv::dev::BatchPass *)(d + o_pass);
     L.ops = (const qsv::dev::TileOp *)(d + o_ops);
     L.pool = d + o_pool;
@@ -251,6 +337,14 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     L.out = (double *)(d + o_out);
     L.grid = grid;
     L.mfma_k = mfma_k;
+    L.n_pass_launches = pm ? n_pass_launches : 0;
+    L.segs = (const qsv::dev::BatchSeg *)(d + o_segs);
+    L.seg_begin = b->h_seg_begin.data();
+    L.items = b->h_items.data();
+    L.states = b->d_states;
+    L.partial = (double *)(d + o_part);
+    L.chunk_log = kChunkLog;
+    L.grid_big = (unsigned)(cus * std::max(1, qsv::dev::batch_pass_occupancy(b->dtype, mb, mfma_k)));
     b->mb = mb;
     b->kfuse = kf;
     if (b->use_graph) {
@@ -342,6 +436,7 @@ qsv_status qsv_batch_create(int32_t count, const qsv_circuit *circuits, const qs
     b->count = count;
     b->dtype = opt->dtype;
     b->use_graph = opt->use_graph != 0;
+    b->big_per_wg = opt->big_per_workgroup != 0;
     b->nq.resize(count);
     b->ops.resize(count);
     b->terms.resize(count);
@@ -437,6 +532,7 @@ qsv_status qsv_batch_destroy(qsv_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     free_plan(b);
     if (b->d_scratch) (void)hipFree(b->d_scratch);
+    if (b->d_states) (void)hipFree(b->d_states);
     if (b->e0) (void)hipEventDestroy(b->e0);
     if (b->e1) (void)hipEventDestroy(b->e1);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);

@@ -8,6 +8,8 @@
 // the counter passes the number of circuits.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "lds_ops.hpp"
 
@@ -37,13 +39,17 @@ __device__ __forceinline__ double block_sum_b(double v, double *sh) {
 // sweeps issue the loads of U indices (U pairs) per thread before using any,
 // so enough reads are in flight for a state in global memory; a tail loop
 // takes the indices left over.
+// Indices [lo, hi) only (lo, hi multiples of 2): for a string with X letters
+// the pairs (j, j ^ x) whose lower member has pair index in [lo/2, hi/2), so
+// chunks that split [0, 2^n) split every term's sum.
 template <typename R, bool SWZ>
 __device__ __forceinline__ double pauli_partial(const typename VT<R>::T *st, int n,
-                                                const BatchTerm *__restrict__ terms, int nt) {
+                                                const BatchTerm *__restrict__ terms, int nt,
+                                                uint64_t lo, uint64_t hi) {
     using T = typename VT<R>::T;
     constexpr int U = sizeof(R) == 4 ? 8 : 4;
     double acc = 0.0;
-    const uint64_t dim = 1ull << n;
+    (void)n;
     const uint64_t bd = blockDim.x;
     auto at = [&](uint64_t j) -> T { return st[SWZ ? swz<R>((uint32_t)j) : j]; };
     for (int t = 0; t < nt; ++t) {
@@ -54,15 +60,15 @@ __device__ __forceinline__ double pauli_partial(const typename VT<R>::T *st, int
                 const double p = (double)a.x * a.x + (double)a.y * a.y;
                 sr += (__popcll(j & tm.z) & 1) ? -p : p;
             };
-            uint64_t j = threadIdx.x;
-            for (; j + (U - 1) * bd < dim; j += U * bd) {
+            uint64_t j = lo + threadIdx.x;
+            for (; j + (U - 1) * bd < hi; j += U * bd) {
                 T a[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) a[u] = at(j + u * bd);
 #pragma unroll
                 for (int u = 0; u < U; ++u) add(j + u * bd, a[u]);
             }
-            for (; j < dim; j += bd) add(j, at(j));
+            for (; j < hi; j += bd) add(j, at(j));
         } else {
             const int h = 63 - __builtin_clzll(tm.x);
             const uint64_t lowm = (1ull << h) - 1;
@@ -76,8 +82,8 @@ __device__ __forceinline__ double pauli_partial(const typename VT<R>::T *st, int
                 sr += (s1 + s2) * u;
                 si += (s1 - s2) * v;
             };
-            const uint64_t half = dim >> 1;
-            uint64_t g = threadIdx.x;
+            const uint64_t half = hi >> 1;
+            uint64_t g = (lo >> 1) + threadIdx.x;
             for (; g + (U - 1) * bd < half; g += U * bd) {
                 T a[U], b[U];
 #pragma unroll
@@ -105,6 +111,77 @@ __device__ __forceinline__ double pauli_partial(const typename VT<R>::T *st, int
         acc += tm.c * re;
     }
     return acc;
+}
+
+// One tile t of a pass over a state in global memory (`slot`): load it (from
+// |0...0> on the circuit's first pass), apply the pass's ops in LDS, store
+// it.  The whole workgroup calls it; it ends with a barrier.
+template <typename R, int KM>
+__device__ __forceinline__ void batch_tile(typename VT<R>::T *tile, typename VT<R>::T *slot,
+                                           const BatchPass &bp, uint64_t t, bool init,
+                                           const TileOp *__restrict__ ops,
+                                           const typename VT<R>::T *__restrict__ pool) {
+    using T = typename VT<R>::T;
+    const uint32_t tid = threadIdx.x;
+    const int m = bp.m;
+    const uint32_t *tpos = bp.tpos;
+    const uint32_t tsize = 1u << m;
+    // loads in flight per thread while a tile comes in or goes out
+    constexpr int LD = sizeof(R) == 4 ? 8 : 4;
+    // thread part of local index j0 + tid (used when tsize >= LD kNT)
+    const uint64_t dep_tid = deposit_bits(tid, tpos, m < 8 ? m : 8);
+    const uint32_t swz_tid = swz<R>(tid);
+    uint64_t base = t;
+    for (int i = 0; i < m; ++i) {
+        const uint64_t lowm = (1ull << tpos[i]) - 1;
+        base = ((base & ~lowm) << 1) | (base & lowm);
+    }
+    // loads go out LD at a time, before their LDS writes (tiles of at least
+    // LD * kNT amplitudes; smaller ones one at a time)
+    if (tsize < LD * kNT) {
+        for (uint32_t l = tid; l < tsize; l += kNT) {
+            const uint64_t gi = base | deposit_bits(l, tpos, m);
+            T v;
+            if (init) {
+                v.x = (gi == 0) ? R(1) : R(0);
+                v.y = R(0);
+            } else {
+                v = slot[gi];
+            }
+            tile[swz<R>(l)] = v;
+        }
+    } else for (uint32_t j0 = 0; j0 < tsize; j0 += LD * kNT) {
+        T v[LD];
+#pragma unroll
+        for (int u = 0; u < LD; ++u) {
+            const uint64_t gi = base | dep_tid | deposit_bits(j0 + u * kNT, tpos, m);
+            if (init) {
+                v[u].x = (gi == 0) ? R(1) : R(0);
+                v[u].y = R(0);
+            } else {
+                v[u] = slot[gi];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < LD; ++u) tile[swz_tid ^ swz<R>(j0 + u * kNT)] = v[u];
+    }
+    __syncthreads();
+    for (int o = 0; o < bp.op_count; ++o) {
+        lds_op<R, KM>(tile, m, base, tpos, ops[bp.op_begin + o], pool);
+        __syncthreads();
+    }
+    if (tsize < LD * kNT) {
+        for (uint32_t l = tid; l < tsize; l += kNT)
+            slot[base | deposit_bits(l, tpos, m)] = tile[swz<R>(l)];
+    } else for (uint32_t j0 = 0; j0 < tsize; j0 += LD * kNT) {
+        T v[LD];
+#pragma unroll
+        for (int u = 0; u < LD; ++u) v[u] = tile[swz_tid ^ swz<R>(j0 + u * kNT)];
+#pragma unroll
+        for (int u = 0; u < LD; ++u)
+            slot[base | dep_tid | deposit_bits(j0 + u * kNT, tpos, m)] = v[u];
+    }
+    __syncthreads();
 }
 
 template <typename R, int KM>
@@ -150,73 +227,15 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                     __syncthreads();
                 }
             }
-            part = pauli_partial<R, true>(tile, n, terms + bc.term_begin, bc.term_count);
+            part = pauli_partial<R, true>(tile, n, terms + bc.term_begin, bc.term_count, 0,
+                                          1ull << n);
         } else {
             // state in this workgroup's global slot, updated by tile passes
             for (int p = 0; p < bc.pass_count; ++p) {
                 const BatchPass &bp = passes[bc.pass_begin + p];
-                const int m = bp.m;
-                const uint32_t *tpos = bp.tpos;
-                const uint32_t tsize = 1u << m;
-                const uint64_t ntiles = 1ull << (n - m);
-                // loads in flight per thread while a tile comes in or goes out
-                constexpr int LD = sizeof(R) == 4 ? 8 : 4;
-                // thread part of local index j0 + tid (used when tsize >= LD kNT)
-                const uint64_t dep_tid = deposit_bits(tid, tpos, m < 8 ? m : 8);
-                const uint32_t swz_tid = swz<R>(tid);
-                for (uint64_t t = 0; t < ntiles; ++t) {
-                    uint64_t base = t;
-                    for (int i = 0; i < m; ++i) {
-                        const uint64_t lowm = (1ull << tpos[i]) - 1;
-                        base = ((base & ~lowm) << 1) | (base & lowm);
-                    }
-                    // loads go out LD at a time, before their LDS writes (tiles of
-                    // at least LD * kNT amplitudes; smaller ones one at a time)
-                    if (tsize < LD * kNT) {
-                        for (uint32_t l = tid; l < tsize; l += kNT) {
-                            const uint64_t gi = base | deposit_bits(l, tpos, m);
-                            T v;
-                            if (p == 0) {
-                                v.x = (gi == 0) ? R(1) : R(0);
-                                v.y = R(0);
-                            } else {
-                                v = slot[gi];
-                            }
-                            tile[swz<R>(l)] = v;
-                        }
-                    } else for (uint32_t j0 = 0; j0 < tsize; j0 += LD * kNT) {
-                        T v[LD];
-#pragma unroll
-                        for (int u = 0; u < LD; ++u) {
-                            const uint64_t gi = base | dep_tid | deposit_bits(j0 + u * kNT, tpos, m);
-                            if (p == 0) {   // the first pass starts from |0...0>
-                                v[u].x = (gi == 0) ? R(1) : R(0);
-                                v[u].y = R(0);
-                            } else {
-                                v[u] = slot[gi];
-                            }
-                        }
-#pragma unroll
-                        for (int u = 0; u < LD; ++u) tile[swz_tid ^ swz<R>(j0 + u * kNT)] = v[u];
-                    }
-                    __syncthreads();
-                    for (int o = 0; o < bp.op_count; ++o) {
-                        lds_op<R, KM>(tile, m, base, tpos, ops[bp.op_begin + o], pool);
-                        __syncthreads();
-                    }
-                    if (tsize < LD * kNT) {
-                        for (uint32_t l = tid; l < tsize; l += kNT)
-                            slot[base | deposit_bits(l, tpos, m)] = tile[swz<R>(l)];
-                    } else for (uint32_t j0 = 0; j0 < tsize; j0 += LD * kNT) {
-                        T v[LD];
-#pragma unroll
-                        for (int u = 0; u < LD; ++u) v[u] = tile[swz_tid ^ swz<R>(j0 + u * kNT)];
-#pragma unroll
-                        for (int u = 0; u < LD; ++u)
-                            slot[base | dep_tid | deposit_bits(j0 + u * kNT, tpos, m)] = v[u];
-                    }
-                    __syncthreads();
-                }
+                const uint64_t ntiles = 1ull << (n - bp.m);
+                for (uint64_t t = 0; t < ntiles; ++t)
+                    batch_tile<R, KM>(tile, slot, bp, t, p == 0, ops, pool);
             }
             if (bc.pass_count == 0) {
                 const uint64_t dim = 1ull << n;
@@ -228,7 +247,8 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
                 }
                 __syncthreads();
             }
-            part = pauli_partial<R, false>(slot, n, terms + bc.term_begin, bc.term_count);
+            part = pauli_partial<R, false>(slot, n, terms + bc.term_begin, bc.term_count, 0,
+                                           1ull << n);
         }
         const double tot = block_sum_b<R>(part, sh);
         if (tid == 0) out[bc.out_index] = tot;
@@ -237,6 +257,77 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
 }
 
 __global__ void k_reset_counter(unsigned int *counter) { *counter = 0u; }
+
+// ------------------------------------------------------ pass-major circuits
+// Segment of work item `it`: the last segment whose first item is <= it (the
+// host orders a launch's segments by first item, the first one at 0).
+__device__ __forceinline__ int find_seg(const BatchSeg *__restrict__ segs, int nseg,
+                                        uint64_t it) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].first <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One pass index of every pass-major circuit: work item = (circuit, tile),
+// taken by the workgroups in a fixed stride (no counter, no waiting).  The
+// kernel boundary orders a circuit's passes.
+template <typename R, int KM>
+__global__ __launch_bounds__(kNT) void k_batch_pass(const BatchSeg *__restrict__ segs, int nseg,
+                                                    uint64_t items,
+                                                    const BatchPass *__restrict__ passes,
+                                                    const TileOp *__restrict__ ops,
+                                                    const typename VT<R>::T *__restrict__ pool,
+                                                    typename VT<R>::T *__restrict__ states) {
+    using T = typename VT<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *tile = reinterpret_cast<T *>(smem_raw);
+    for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const BatchSeg sg = segs[find_seg(segs, nseg, it)];
+        batch_tile<R, KM>(tile, states + sg.state_off, passes[sg.pass], it - sg.first,
+                          sg.init != 0, ops, pool);
+    }
+}
+
+// The Pauli sums of the pass-major circuits: work item = (circuit, chunk of
+// 2^chunk_log indices); partial[item] = the chunk's share of sum_t c_t <P_t>.
+template <typename R>
+__global__ __launch_bounds__(kNT) void k_batch_pauli(const BatchSeg *__restrict__ segs, int nseg,
+                                                     uint64_t items,
+                                                     const BatchCircuit *__restrict__ circuits,
+                                                     const BatchTerm *__restrict__ terms,
+                                                     const typename VT<R>::T *__restrict__ states,
+                                                     int chunk_log, double *__restrict__ partial) {
+    __shared__ double sh[16];
+    for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const BatchSeg sg = segs[find_seg(segs, nseg, it)];
+        const BatchCircuit bc = circuits[sg.circuit];
+        const int cl = chunk_log < bc.n ? chunk_log : bc.n;
+        const uint64_t k = it - sg.first;
+        const double part = pauli_partial<R, false>(states + sg.state_off, bc.n,
+                                                    terms + bc.term_begin, bc.term_count,
+                                                    k << cl, (k + 1) << cl);
+        const double tot = block_sum_b<R>(part, sh);
+        if (threadIdx.x == 0) partial[it] = tot;
+        __syncthreads();
+    }
+}
+
+// <H> of each pass-major circuit: its chunk sums added in chunk order (the
+// same order on every run).
+__global__ void k_batch_finish(const BatchSeg *__restrict__ segs, int nseg, uint64_t items,
+                               const BatchCircuit *__restrict__ circuits,
+                               const double *__restrict__ partial, double *__restrict__ out) {
+    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= nseg) return;
+    const uint64_t b = segs[s].first, e = s + 1 < nseg ? segs[s + 1].first : items;
+    double acc = 0.0;
+    for (uint64_t i = b; i < e; ++i) acc += partial[i];
+    out[circuits[segs[s].circuit].out_index] = acc;
+}
 
 template <typename R, int KM>
 static hipError_t batch_t(const BatchLaunch &L, hipStream_t s) {
@@ -249,11 +340,42 @@ static hipError_t batch_t(const BatchLaunch &L, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr = lds;
     }
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, L.counter);
-    hipLaunchKernelGGL((k_batch<R, KM>), dim3(L.grid), dim3(kNT), lds, s, L.circuits, L.order,
-                       L.count, L.passes, L.ops, (const T *)L.pool, L.terms, (T *)L.scratch,
-                       L.slot_amps, L.mb, L.counter, L.out);
-    return hipGetLastError();
+    if (L.count > 0) {
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, L.counter);
+        hipLaunchKernelGGL((k_batch<R, KM>), dim3(L.grid), dim3(kNT), lds, s, L.circuits,
+                           L.order, L.count, L.passes, L.ops, (const T *)L.pool, L.terms,
+                           (T *)L.scratch, L.slot_amps, L.mb, L.counter, L.out);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (L.n_pass_launches <= 0) return hipSuccess;
+    static size_t attr_p = 0;
+    if (attr_p < lds) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_batch_pass<R, KM>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_p = lds;
+    }
+    for (int i = 0; i <= L.n_pass_launches; ++i) {
+        const int sb = L.seg_begin[i], ns = L.seg_begin[i + 1] - sb;
+        const uint64_t items = L.items[i];
+        if (items == 0 || ns <= 0) continue;
+        const unsigned grid = (unsigned)std::min<uint64_t>(items, L.grid_big);
+        if (i < L.n_pass_launches) {
+            hipLaunchKernelGGL((k_batch_pass<R, KM>), dim3(grid), dim3(kNT), lds, s, L.segs + sb,
+                               ns, items, L.passes, L.ops, (const T *)L.pool, (T *)L.states);
+        } else {
+            hipLaunchKernelGGL((k_batch_pauli<R>), dim3(grid), dim3(kNT), 0, s, L.segs + sb, ns,
+                               items, L.circuits, L.terms, (const T *)L.states, L.chunk_log,
+                               L.partial);
+            hipLaunchKernelGGL(k_batch_finish, dim3((ns + 255) / 256), dim3(256), 0, s,
+                               L.segs + sb, ns, items, L.circuits, (const double *)L.partial,
+                               L.out);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Kernel variant for the widest matrix-core op of the batch: up to 3 qubits
@@ -274,6 +396,23 @@ static int batch_occ_t(int mb) {
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &blocks, k_batch<R, KM>, kNT, sizeof(T) << mb);
     return e == hipSuccess ? blocks : 0;
+}
+
+template <typename R, int KM>
+static int batch_pass_occ_t(int mb) {
+    using T = typename VT<R>::T;
+    int blocks = 0;
+    (void)hipFuncSetAttribute((const void *)k_batch_pass<R, KM>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(T) << mb));
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &blocks, k_batch_pass<R, KM>, kNT, sizeof(T) << mb);
+    return e == hipSuccess ? blocks : 0;
+}
+
+int batch_pass_occupancy(int dtype, int mb, int mfma_k) {
+    if (dtype == 0)
+        return mfma_k <= 3 ? batch_pass_occ_t<double, 3>(mb) : batch_pass_occ_t<double, 5>(mb);
+    return mfma_k <= 3 ? batch_pass_occ_t<float, 3>(mb) : batch_pass_occ_t<float, 5>(mb);
 }
 
 int batch_occupancy(int dtype, int mb, int mfma_k) {

@@ -74,7 +74,8 @@ class PauliSumC(ctypes.Structure):
 class BatchOptions(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("tile_bits", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("tune_cache", ctypes.c_char_p)]
+                ("stream", ctypes.c_void_p), ("tune_cache", ctypes.c_char_p),
+                ("big_per_workgroup", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -621,7 +622,7 @@ class Batch:
     launch (replayed from a HIP graph)."""
 
     def __init__(self, circuits, hams, dtype="c64", autotune=True, tile_bits=0,
-                 use_graph=True, stream=None, tune_cache=None):
+                 use_graph=True, stream=None, tune_cache=None, big_per_workgroup=False):
         self._fc = [FlatCircuit(c) for c in circuits]
         self._fp = [FlatPauli(h) for h in hams]
         self.count = len(circuits)
@@ -632,7 +633,7 @@ class Batch:
             stream = _torch_stream()
         self._cache = tune_cache.encode() if tune_cache else None
         opt = BatchOptions(_DTYPES[dtype], int(autotune), tile_bits, int(use_graph), stream,
-                           self._cache)
+                           self._cache, int(bool(big_per_workgroup)))
         h = ctypes.c_void_p()
         _check(lib.qsv_batch_create(self.count, arr_c, arr_h, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h

@@ -138,3 +138,38 @@ def test_batch_tiny_and_empty_circuits(dtype):
         scale = np.array([np.sum(np.abs(h.coeff)) for h in hams[lo:hi]])
         assert np.all(np.abs(got - want) <= tol * scale), np.max(np.abs(got - want) / scale)
         b.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_pass_major_and_per_workgroup_paths(dtype):
+    """Circuits whose state exceeds the LDS tile run pass-major by default
+    (one launch per pass index over every such circuit's tiles, Pauli sums in
+    chunks) or, with big_per_workgroup, each on one workgroup.  Both paths
+    against the oracle, on a batch that mixes sizes on both sides of the tile
+    (with circuits that have no gates at all on the big side), on a batch
+    where every circuit is big and on a batch of one big circuit; a 16-qubit
+    circuit spans several Pauli chunks."""
+    from paper_1612_08091_amd import qsv as Q
+    rng = np.random.default_rng(48)
+    circuits, hams = small_batch(20, 4, 13, 2, 8, seed=49)
+    for n in (10, 12, 16):
+        circuits.append(W.Circuit(n))                    # no gates: |0...0>
+        hams.append(W.random_pauli_dense(n, 6, rng))
+    circuits.append(W.hea(16, 2, rng.uniform(0, 2 * math.pi, 64)))
+    hams.append(W.random_pauli_dense(16, 10, rng))
+    want = np.array([oracle.energy(c, h) for c, h in zip(circuits, hams)])
+    scale = np.array([np.sum(np.abs(h.coeff)) for h in hams])
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    big = [i for i, c in enumerate(circuits) if c.n > 9]
+    cases = [list(range(len(circuits))), big, [big[-1]]]
+    for sel in cases:
+        outs = []
+        for per_wg in (False, True):
+            b = Q.Batch([circuits[i] for i in sel], [hams[i] for i in sel], dtype=dtype,
+                        autotune=False, tile_bits=9, big_per_workgroup=per_wg)
+            got = b.run()
+            b.close()
+            err = np.abs(got - want[sel]) / scale[sel]
+            assert np.all(err <= tol), (per_wg, len(sel), float(np.max(err)))
+            outs.append(got)
+        assert np.all(np.abs(outs[0] - outs[1]) <= 2 * tol * scale[sel])
