@@ -232,7 +232,8 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     b->h_seg_begin.clear();
     b->h_items.clear();
     int n_pass_launches = 0;
-    constexpr int kChunkLog = 14;   // Pauli chunk: 2^14 amplitudes per work item
+    // Pauli chunk per work item, held in LDS: 32 KiB
+    const int kChunkLog = b->dtype == QSV_C128 ? 11 : 12;
     if (pm) {
         std::vector<uint64_t> state_off(b->count, 0);
         uint64_t off = 0;

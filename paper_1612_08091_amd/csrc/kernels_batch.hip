@@ -292,8 +292,15 @@ __global__ __launch_bounds__(kNT) void k_batch_pass(const BatchSeg *__restrict__
     }
 }
 
-// The Pauli sums of the pass-major circuits: work item = (circuit, chunk of
-// 2^chunk_log indices); partial[item] = the chunk's share of sum_t c_t <P_t>.
+// The Pauli sums of the pass-major circuits: work item = (circuit, chunk k of
+// C = 2^cl indices, cl = min(chunk_log, n)); partial[item] = the chunk's
+// share of sum_t c_t <P_t>.  The chunk is read into LDS once and serves
+// every term.  A term with X letters pairs j with j ^ x; the pair is taken
+// by the chunk of its member with bit h = 0 (h: the highest X bit): within
+// the chunk when h < cl, else by the chunks whose index has bit h - cl clear,
+// which read the partner chunk k ^ (x >> cl) from global memory.  So a term
+// reads half a state from global memory instead of a whole one, and a
+// string of Z letters none.
 template <typename R>
 __global__ __launch_bounds__(kNT) void k_batch_pauli(const BatchSeg *__restrict__ segs, int nseg,
                                                      uint64_t items,
@@ -301,18 +308,79 @@ __global__ __launch_bounds__(kNT) void k_batch_pauli(const BatchSeg *__restrict_
                                                      const BatchTerm *__restrict__ terms,
                                                      const typename VT<R>::T *__restrict__ states,
                                                      int chunk_log, double *__restrict__ partial) {
+    using T = typename VT<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *ch = reinterpret_cast<T *>(smem_raw);
     __shared__ double sh[16];
+    constexpr int U = sizeof(R) == 4 ? 8 : 4;   // global reads in flight per thread
+    const uint32_t tid = threadIdx.x;
     for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
         const BatchSeg sg = segs[find_seg(segs, nseg, it)];
         const BatchCircuit bc = circuits[sg.circuit];
         const int cl = chunk_log < bc.n ? chunk_log : bc.n;
+        const uint32_t C = 1u << cl;
         const uint64_t k = it - sg.first;
-        const double part = pauli_partial<R, false>(states + sg.state_off, bc.n,
-                                                    terms + bc.term_begin, bc.term_count,
-                                                    k << cl, (k + 1) << cl);
-        const double tot = block_sum_b<R>(part, sh);
-        if (threadIdx.x == 0) partial[it] = tot;
+        const uint64_t j0 = k << cl;
+        const T *st = states + sg.state_off;
+        for (uint32_t l = tid; l < C; l += kNT) ch[l] = st[j0 + l];
         __syncthreads();
+        double acc = 0.0;
+        for (int t = 0; t < bc.term_count; ++t) {
+            const BatchTerm tm = terms[bc.term_begin + t];
+            double sr = 0.0, si = 0.0;
+            if (tm.x == 0) {
+                for (uint32_t l = tid; l < C; l += kNT) {
+                    const T a = ch[l];
+                    const double p = (double)a.x * a.x + (double)a.y * a.y;
+                    sr += (__popcll((j0 + l) & tm.z) & 1) ? -p : p;
+                }
+            } else {
+                const int h = 63 - __builtin_clzll(tm.x);
+                auto add = [&](uint64_t j, const T &a, const T &b) {
+                    const uint64_t j2 = j ^ tm.x;
+                    const double u = (double)b.x * a.x + (double)b.y * a.y;
+                    const double v = (double)b.x * a.y - (double)b.y * a.x;
+                    const double s1 = (__popcll(j & tm.z) & 1) ? -1.0 : 1.0;
+                    const double s2 = (__popcll(j2 & tm.z) & 1) ? -1.0 : 1.0;
+                    sr += (s1 + s2) * u;
+                    si += (s1 - s2) * v;
+                };
+                if (h < cl) {
+                    // both members in the chunk: pair g has local index g
+                    // with a 0 inserted at bit h
+                    const uint32_t lowm = (1u << h) - 1;
+                    const uint32_t xl = (uint32_t)tm.x;
+                    for (uint32_t g = tid; g < (C >> 1); g += kNT) {
+                        const uint32_t l = ((g & ~lowm) << 1) | (g & lowm);
+                        add(j0 + l, ch[l], ch[l ^ xl]);
+                    }
+                } else if (((j0 >> h) & 1) == 0) {
+                    const T *pp = st + ((j0 ^ tm.x) & ~(uint64_t)(C - 1));
+                    const uint32_t xl = (uint32_t)(tm.x & (C - 1));
+                    uint32_t l = tid;
+                    for (; l + (U - 1) * kNT < C; l += U * kNT) {
+                        T b[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) b[u] = pp[(l + u * kNT) ^ xl];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) add(j0 + l + u * kNT, ch[l + u * kNT], b[u]);
+                    }
+                    for (; l < C; l += kNT) add(j0 + l, ch[l], pp[l ^ xl]);
+                }
+            }
+            // Re(i^{ny} (sr + i si))
+            double re;
+            switch (tm.ny & 3) {
+            case 0: re = sr; break;
+            case 1: re = -si; break;
+            case 2: re = -sr; break;
+            default: re = si; break;
+            }
+            acc += tm.c * re;
+        }
+        const double tot = block_sum_b<R>(acc, sh);
+        if (tid == 0) partial[it] = tot;
+        __syncthreads();   // the chunk and sh are rewritten by the next item
     }
 }
 
@@ -365,7 +433,16 @@ static hipError_t batch_t(const BatchLaunch &L, hipStream_t s) {
             hipLaunchKernelGGL((k_batch_pass<R, KM>), dim3(grid), dim3(kNT), lds, s, L.segs + sb,
                                ns, items, L.passes, L.ops, (const T *)L.pool, (T *)L.states);
         } else {
-            hipLaunchKernelGGL((k_batch_pauli<R>), dim3(grid), dim3(kNT), 0, s, L.segs + sb, ns,
+            const size_t chb = sizeof(T) << L.chunk_log;
+            static size_t attr_c = 0;
+            if (attr_c < chb) {
+                hipError_t e = hipFuncSetAttribute((const void *)k_batch_pauli<R>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)chb);
+                if (e != hipSuccess) return e;
+                attr_c = chb;
+            }
+            hipLaunchKernelGGL((k_batch_pauli<R>), dim3(grid), dim3(kNT), chb, s, L.segs + sb, ns,
                                items, L.circuits, L.terms, (const T *)L.states, L.chunk_log,
                                L.partial);
             hipLaunchKernelGGL(k_batch_finish, dim3((ns + 255) / 256), dim3(256), 0, s,
