@@ -149,6 +149,16 @@ struct RegOp {
 };
 static_assert(sizeof(RegOp) % 64 == 0, "register ops start on scalar cache lines");
 
+// A run of work items of one batched register-tile launch that belong to one
+// circuit's pass: item - first = tile index; the pass's TileArgs (tile
+// positions, layouts, image) at tas[ta], its program at rops[op_begin].
+struct RegSeg {
+    uint64_t first;
+    uint64_t state_off;
+    int32_t ta;
+    int32_t op_begin;
+};
+
 // ------------------------------------------------------------------ gates
 // dtype: 0 = complex128, 1 = complex64.  Sizes in amplitudes.
 hipError_t launch_dense(int dtype, void *psi, int k, uint64_t ngroups, const IndexArgs &ia,
@@ -160,6 +170,12 @@ hipError_t launch_tile_pass(int dtype, void *psi, const TileArgs &ta, const Tile
 // Register-resident tile pass: ta.rb register bits in {3, 4, 5} and
 // ta.m - ta.rb thread bits in {8, 9}.  `counter` is a device word that must
 // hold 0 when the pass starts; the persistent workgroups take tiles from it.
+// Batched register-tile launch (12-bit tiles, 16 amplitudes per thread):
+// items work items over the segments, a fixed stride per workgroup; img_max:
+// the largest image of the segments' passes.
+hipError_t launch_tile_reg_batch(int dtype, bool dg, void *states, const RegSeg *segs, int nseg,
+                                 uint64_t items, const TileArgs *tas, const RegOp *rops,
+                                 const void *pool, uint32_t img_max, hipStream_t s);
 hipError_t launch_tile_reg(int dtype, void *psi, const TileArgs &ta, const RegOp *rops,
                            const void *pool, unsigned int *counter, hipStream_t s);
 int tile_pass_max_bits(int dtype);
@@ -296,7 +312,8 @@ struct BatchLaunch {
     // circuit's chunk sums in order.  Launch i takes segments
     // [seg_begin[i], seg_begin[i + 1]) of `segs` and items[i] work items
     // (host arrays).  count above then counts only the circuits of k_batch.
-    int32_t n_pass_launches;  // 0: no pass-major circuits
+    int32_t pass_major;       // 0: no pass-major circuits
+    int32_t n_pass_launches;  // LDS-tile pass launches
     const BatchSeg *segs;
     const int32_t *seg_begin; // host, n_pass_launches + 2 entries
     const uint64_t *items;    // host, n_pass_launches + 1 entries
@@ -304,6 +321,25 @@ struct BatchLaunch {
     double *partial;          // one sum per Pauli work item
     int32_t chunk_log;        // Pauli chunk: 2^chunk_log amplitudes (pairs for X strings)
     unsigned int grid_big;
+    // Pass-major circuits of at least 13 qubits run on the register-tile
+    // kernel (12-bit tiles, the planning and lowering of the single-state
+    // path): their states (reg_amps amplitudes from amplitude reg_state_off
+    // of `states`, each starting at reg_starts[i]) are set to |0...0> first,
+    // then launch i < n_reg_launches runs segments [reg_seg_begin[i],
+    // reg_seg_begin[i + 1]) of reg_segs over reg_items[i] tiles, with the
+    // table-op instance where reg_dg[i].
+    int32_t n_reg_launches;
+    const RegSeg *reg_segs;
+    const int32_t *reg_seg_begin; // host
+    const uint64_t *reg_items;    // host
+    const int32_t *reg_dg;        // host
+    const TileArgs *tas;
+    const RegOp *rops;
+    const void *reg_pool;         // LDS images
+    uint32_t reg_img_max;
+    uint64_t reg_state_off, reg_amps;
+    const uint64_t *reg_starts;
+    int32_t n_reg_states;
 };
 hipError_t batch_launch(int dtype, const BatchLaunch &L, hipStream_t s);
 int batch_occupancy(int dtype, int mb, int mfma_k);   // resident workgroups per CU

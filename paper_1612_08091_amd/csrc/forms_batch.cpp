@@ -58,6 +58,16 @@ struct qsv_batch {
     size_t states_bytes = 0;
     std::vector<int32_t> h_seg_begin;
     std::vector<uint64_t> h_items;
+    // register-tile programs of the circuits of at least 13 qubits (planned
+    // once per circuit, on first use), and the register launches' host arrays
+    struct RegPlan {
+        bool done = false, ok = false;
+        std::vector<qsv::TileProgram> progs;
+    };
+    std::vector<RegPlan> regplan;
+    std::vector<int32_t> h_reg_seg_begin;
+    std::vector<uint64_t> h_reg_items;
+    std::vector<int32_t> h_reg_dg;
     qsv::dev::BatchLaunch L{};
     int mb = 0, kfuse = 0;
     hipGraph_t graph = nullptr;
@@ -141,6 +151,57 @@ void free_plan(qsv_batch *b) {
     b->graph = nullptr;
     if (b->d_buf) (void)hipFree(b->d_buf);
     b->d_buf = nullptr;
+}
+
+// The register-tile plan of circuit i: the single-state path's planning (12-bit
+// tiles, fusion to 2 qubits, relabeling) and lowering; ok = false when a pass
+// does not lower to the register kernel.
+constexpr int kRegMinQubits = 13;
+const qsv_batch::RegPlan &reg_plan(qsv_batch *b, int i) {
+    qsv_batch::RegPlan &rp = b->regplan[i];
+    if (rp.done) return rp;
+    rp.done = true;
+    const int n = b->nq[i];
+    const int elem = b->dtype == QSV_C128 ? 16 : 8;
+    std::vector<Pass> ps = qsv::plan_tiled(b->ops[i], n, 12, 2, elem == 16 ? 17 : 18, true);
+    std::vector<double> mats;
+    for (const Pass &p : ps) {
+        qsv::TileProgram pg;
+        qsv::compile_pass(p, 4, mats, pg, elem);
+        if (!pg.reg || pg.m != 12 || (pg.rops.size() & 1)) {
+            rp.progs.clear();
+            return rp;
+        }
+        if (pg.rops.empty() && !pg.permutes) continue;
+        rp.progs.push_back(std::move(pg));
+    }
+    rp.ok = true;
+    return rp;
+}
+
+qsv::dev::TileArgs reg_args(const qsv::TileProgram &pg, int n, int64_t img_off) {
+    qsv::dev::TileArgs ta{};
+    ta.m = pg.m;
+    ta.nq = n;
+    ta.tile_pos_n = pg.m;
+    int c = 0;
+    for (int p = 0; p < 64; ++p)
+        if ((pg.tile >> p) & 1) ta.tpos[c++] = (uint32_t)p;
+    ta.n_tiles = 1ull << (n - pg.m);
+    std::memcpy(ta.g_reg, pg.g_reg, sizeof(ta.g_reg));
+    std::memcpy(ta.g_thr, pg.g_thr, sizeof(ta.g_thr));
+    std::memcpy(ta.g_reg_f, pg.g_reg_f, sizeof(ta.g_reg_f));
+    std::memcpy(ta.g_thr_f, pg.g_thr_f, sizeof(ta.g_thr_f));
+    ta.img_bytes = (uint32_t)pg.img.size();
+    ta.store_sync = 1;
+    ta.img_off = img_off;
+    ta.rb = 4;
+    ta.n_ops = (int32_t)pg.rops.size();
+    ta.no_diag = 1;
+    for (const qsv::dev::RegOp &r : pg.rops)
+        if (r.kind == qsv::dev::ROP_DIAG) ta.no_diag = 0;
+    for (int b2 = 0; b2 < pg.m; ++b2) ta.spos[b2] = pg.spos[b2];
+    return ta;
 }
 
 template <typename X>
@@ -234,18 +295,78 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     int n_pass_launches = 0;
     // Pauli chunk per work item, held in LDS: 32 KiB
     const int kChunkLog = b->dtype == QSV_C128 ? 11 : 12;
+    // register-path circuits (at least 13 qubits, every pass lowered to the
+    // register kernel) and LDS-path ones; states: LDS-path first, then the
+    // register-path ones in one range (set to |0...0> by one fill)
+    std::vector<int> big_lds, big_reg;
+    std::vector<qsv::dev::TileArgs> tas;
+    std::vector<qsv::dev::RegOp> rops;
+    std::vector<unsigned char> imgs;
+    std::vector<qsv::dev::RegSeg> rsegs;
+    std::vector<uint64_t> reg_starts;
+    uint32_t img_max = 0;
+    uint64_t reg_state_off = 0, reg_amps = 0;
+    b->h_reg_seg_begin.clear();
+    b->h_reg_items.clear();
+    b->h_reg_dg.clear();
     if (pm) {
+        for (int i : big) {
+            if (b->nq[i] >= kRegMinQubits && reg_plan(b, i).ok) big_reg.push_back(i);
+            else big_lds.push_back(i);
+        }
         std::vector<uint64_t> state_off(b->count, 0);
         uint64_t off = 0;
-        for (int i : big) {
+        for (int i : big_lds) {
             state_off[i] = off;
             off += 1ull << b->nq[i];
         }
-        for (int i : big) n_pass_launches = std::max(n_pass_launches, circ[i].pass_count);
+        reg_state_off = off;
+        for (int i : big_reg) {
+            state_off[i] = off;
+            reg_starts.push_back(off);
+            off += 1ull << b->nq[i];
+        }
+        reg_amps = off - reg_state_off;
+        // register launches: pass p of every register-path circuit that has one
+        std::vector<std::vector<int>> ta_of(b->count), op_of(b->count);
+        for (int i : big_reg) {
+            for (const qsv::TileProgram &pg : b->regplan[i].progs) {
+                const size_t io = (imgs.size() + 255) & ~size_t(255);
+                imgs.resize(io + pg.img.size());
+                if (!pg.img.empty()) std::memcpy(imgs.data() + io, pg.img.data(), pg.img.size());
+                img_max = std::max<uint32_t>(img_max, (uint32_t)((pg.img.size() + 15) & ~size_t(15)));
+                ta_of[i].push_back((int)tas.size());
+                op_of[i].push_back((int)rops.size());
+                tas.push_back(reg_args(pg, b->nq[i], (int64_t)io));
+                rops.insert(rops.end(), pg.rops.begin(), pg.rops.end());
+            }
+        }
+        size_t p_reg = 0;
+        for (int i : big_reg) p_reg = std::max(p_reg, b->regplan[i].progs.size());
+        for (size_t p = 0; p < p_reg; ++p) {
+            b->h_reg_seg_begin.push_back((int32_t)rsegs.size());
+            uint64_t it = 0;
+            int dg = 0;
+            for (int i : big_reg) {
+                if (b->regplan[i].progs.size() <= p) continue;
+                qsv::dev::RegSeg sg{};
+                sg.first = it;
+                sg.state_off = state_off[i];
+                sg.ta = ta_of[i][p];
+                sg.op_begin = op_of[i][p];
+                rsegs.push_back(sg);
+                it += tas[sg.ta].n_tiles;
+                if (!tas[sg.ta].no_diag) dg = 1;
+            }
+            b->h_reg_items.push_back(it);
+            b->h_reg_dg.push_back(dg);
+        }
+        b->h_reg_seg_begin.push_back((int32_t)rsegs.size());
+        for (int i : big_lds) n_pass_launches = std::max(n_pass_launches, circ[i].pass_count);
         for (int p = 0; p < n_pass_launches; ++p) {
             b->h_seg_begin.push_back((int32_t)segs.size());
             uint64_t it = 0;
-            for (int i : big) {
+            for (int i : big_lds) {
                 if (circ[i].pass_count <= p) continue;
                 qsv::dev::BatchSeg sg{};
                 sg.first = it;
@@ -294,6 +415,11 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     const size_t o_ctr = put(host, std::vector<uint32_t>(64, 0));
     const size_t o_out = put(host, std::vector<double>(b->count, 0.0));
     const size_t o_segs = put(host, segs);
+    const size_t o_tas = put(host, tas);
+    const size_t o_rops = put(host, rops);
+    const size_t o_imgs = put(host, imgs);
+    const size_t o_rsegs = put(host, rsegs);
+    const size_t o_rstarts = put(host, reg_starts);
     const size_t o_part = put(host, std::vector<double>(pm ? b->h_items.back() : 1, 0.0));
     hipError_t e = hipMalloc(&b->d_buf, host.size());
     if (e != hipSuccess) return berr(QSV_ENOMEM, "hipMalloc of the batch plan failed");
@@ -338,7 +464,21 @@ qsv_status build_plan(qsv_batch *b, int mb, int kf) {
     L.out = (double *)(d + o_out);
     L.grid = grid;
     L.mfma_k = mfma_k;
+    L.pass_major = pm ? 1 : 0;
     L.n_pass_launches = pm ? n_pass_launches : 0;
+    L.n_reg_launches = pm ? (int32_t)b->h_reg_items.size() : 0;
+    L.reg_segs = (const qsv::dev::RegSeg *)(d + o_rsegs);
+    L.reg_seg_begin = b->h_reg_seg_begin.data();
+    L.reg_items = b->h_reg_items.data();
+    L.reg_dg = b->h_reg_dg.data();
+    L.tas = (const qsv::dev::TileArgs *)(d + o_tas);
+    L.rops = (const qsv::dev::RegOp *)(d + o_rops);
+    L.reg_pool = d + o_imgs;
+    L.reg_img_max = img_max;
+    L.reg_state_off = reg_state_off;
+    L.reg_amps = reg_amps;
+    L.reg_starts = (const uint64_t *)(d + o_rstarts);
+    L.n_reg_states = (int32_t)reg_starts.size();
     L.segs = (const qsv::dev::BatchSeg *)(d + o_segs);
     L.seg_begin = b->h_seg_begin.data();
     L.items = b->h_items.data();
@@ -441,6 +581,7 @@ qsv_status qsv_batch_create(int32_t count, const qsv_circuit *circuits, const qs
     b->nq.resize(count);
     b->ops.resize(count);
     b->terms.resize(count);
+    b->regplan.resize(count);
     for (int i = 0; i < count; ++i) {
         qsv_status st = parse(circuits[i], hams[i], i, b->ops[i], b->terms[i]);
         if (st != QSV_OK) {

@@ -259,6 +259,30 @@ __global__ __launch_bounds__(kNT) void k_batch(const BatchCircuit *__restrict__ 
 __global__ void k_reset_counter(unsigned int *counter) { *counter = 0u; }
 
 // ------------------------------------------------------ pass-major circuits
+// |0...0> in the states of the register-path circuits: the region zeroed,
+// then amplitude 0 of each state set to 1.
+template <typename R>
+__global__ void k_batch_zero(typename VT<R>::T *p, uint64_t n) {
+    using T = typename VT<R>::T;
+    T z;
+    z.x = R(0);
+    z.y = R(0);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = z;
+}
+template <typename R>
+__global__ void k_batch_one(typename VT<R>::T *states, const uint64_t *__restrict__ starts,
+                            int count) {
+    using T = typename VT<R>::T;
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= count) return;
+    T o;
+    o.x = R(1);
+    o.y = R(0);
+    states[starts[i]] = o;
+}
+
 // Segment of work item `it`: the last segment whose first item is <= it (the
 // host orders a launch's segments by first item, the first one at 0).
 __device__ __forceinline__ int find_seg(const BatchSeg *__restrict__ segs, int nseg,
@@ -416,7 +440,23 @@ static hipError_t batch_t(const BatchLaunch &L, hipStream_t s) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (L.n_pass_launches <= 0) return hipSuccess;
+    if (!L.pass_major) return hipSuccess;
+    if (L.n_reg_launches > 0) {
+        T *rs = (T *)L.states + L.reg_state_off;
+        const unsigned zg = (unsigned)std::min<uint64_t>((L.reg_amps + 255) / 256, 65536);
+        hipLaunchKernelGGL((k_batch_zero<R>), dim3(zg), dim3(256), 0, s, rs, L.reg_amps);
+        hipLaunchKernelGGL((k_batch_one<R>), dim3((L.n_reg_states + 255) / 256), dim3(256), 0, s,
+                           (T *)L.states, L.reg_starts, L.n_reg_states);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        for (int i = 0; i < L.n_reg_launches; ++i) {
+            const int sb = L.reg_seg_begin[i], ns = L.reg_seg_begin[i + 1] - sb;
+            e = launch_tile_reg_batch(sizeof(R) == 8 ? 0 : 1, L.reg_dg[i] != 0, L.states,
+                                      L.reg_segs + sb, ns, L.reg_items[i], L.tas, L.rops,
+                                      L.reg_pool, L.reg_img_max, s);
+            if (e != hipSuccess) return e;
+        }
+    }
     static size_t attr_p = 0;
     if (attr_p < lds) {
         hipError_t e = hipFuncSetAttribute((const void *)k_batch_pass<R, KM>,

@@ -586,6 +586,137 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
     }
 }
 
+// Batched form: one pass index of many states (segments of tiles, each
+// segment one state's pass with its own program and image), work items
+// taken in a fixed stride.  A workgroup reloads the image and its thread
+// parts of the layouts when its segment changes.
+template <typename R, int RB, int TB, bool DG>
+__global__ __launch_bounds__(1 << TB) void k_tile_reg_batch(typename VT<R>::T *__restrict__ states,
+                                                        const RegSeg *__restrict__ segs, int nseg,
+                                                        uint64_t items,
+                                                        const TileArgs *__restrict__ tas,
+                                                        const RegOp *__restrict__ ops,
+                                                        const unsigned char *__restrict__ pool) {
+    using T = typename VT<R>::T;
+    constexpr int NR = 1 << RB;
+    constexpr int m = RB + TB;
+    constexpr uint32_t kHalf = (uint32_t)sizeof(T) << (m - 1);
+    extern __shared__ __align__(16) unsigned char smem_reg[];
+    unsigned char *limg = smem_reg + kHalf;
+    const uint32_t lds_a = lds_addr(smem_reg);
+    const uint32_t limg_a = lds_a + kHalf;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int cur = -1;
+    uint64_t gl = 0, gs = 0;
+    for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segs[mid].first <= it) lo = mid;
+            else hi = mid - 1;
+        }
+        const RegSeg sg = segs[lo];
+        const TileArgs &ta = tas[sg.ta];
+        if (lo != cur) {
+            // every wave is past the previous tile (its remaps and table
+            // reads) before the image is overwritten
+            __syncthreads();
+            const uint4 *src = reinterpret_cast<const uint4 *>(pool + ta.img_off);
+            uint4 *dst = reinterpret_cast<uint4 *>(limg);
+            for (uint32_t e = tid; e < (ta.img_bytes >> 4); e += (1u << TB)) dst[e] = src[e];
+            gl = 0;
+            gs = 0;
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                const uint64_t on = 0ull - (uint64_t)((tid >> t) & 1u);
+                gl |= on & ta.g_thr[t];
+                gs |= on & ta.g_thr_f[t];
+            }
+            __syncthreads();
+            cur = lo;
+        }
+        T *psi = states + sg.state_off;
+        const uint32_t tile = (uint32_t)(it - sg.first);
+        const RegOp *prog = ops + sg.op_begin;
+        const int n_ops = ta.n_ops;
+        T amp[NR];
+        load_tile<T, RB, m>(amp, psi, gl, tile, ta);
+        const uint64_t base = tile_base<m>(tile, ta);
+        for (int oi = 0; oi < n_ops; oi += 2) {
+            reg_op<T, R, NR, RB, DG>(amp, prog[oi], lds_a, limg_a, base, lane, wave);
+            reg_op<T, R, NR, RB, DG>(amp, prog[oi + 1], lds_a, limg_a, base, lane, wave);
+        }
+        // stores go where other threads loaded (relabeling passes), and the
+        // next tile's first workgroup remap may follow wave-local ones
+        __syncthreads();
+        T *sp = psi + gs;
+        asm volatile("" : "+v"(sp));
+        sp += base;
+        uint64_t gr[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            gr[j] = ta.g_reg_f[j];
+            asm volatile("" : "+s"(gr[j]));
+        }
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            uint64_t g = 0;
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+                if ((i >> j) & 1) g |= gr[j];
+            gstore(sp + g, amp[i]);
+        }
+    }
+}
+
+template <typename R, bool DG>
+static hipError_t launch_reg_batch_t(void *states, const RegSeg *segs, int nseg, uint64_t items,
+                                     const TileArgs *tas, const RegOp *rops, const void *pool,
+                                     uint32_t img_max, hipStream_t s) {
+    using T = typename VT<R>::T;
+    constexpr int RB = 4, TB = 8;
+    if (items == 0 || nseg <= 0) return hipSuccess;
+    if (img_max > kRegImageMax || (img_max & 15u)) return hipErrorInvalidValue;
+    constexpr size_t half = sizeof(T) << (RB + TB - 1);
+    const size_t lds = half + img_max;
+    static bool attr = false;
+    static int cus = 0;
+    if (!attr) {
+        hipFuncAttributes fa;
+        hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_tile_reg_batch<R, RB, TB, DG>));
+        if (e != hipSuccess) return e;
+        if (fa.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
+        e = set_lds_attr(k_tile_reg_batch<R, RB, TB, DG>, half + kRegImageMax);
+        if (e != hipSuccess) return e;
+        int dev = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    int occ = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, reinterpret_cast<const void *>(k_tile_reg_batch<R, RB, TB, DG>), 1 << TB, lds);
+    if (e != hipSuccess) return e;
+    const uint64_t resident = (uint64_t)std::max(1, cus) * (uint64_t)std::max(1, occ);
+    const unsigned grid = (unsigned)std::min<uint64_t>(items, resident);
+    hipLaunchKernelGGL((k_tile_reg_batch<R, RB, TB, DG>), dim3(grid), dim3(1 << TB), lds, s,
+                       (T *)states, segs, nseg, items, tas, rops, (const unsigned char *)pool);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_reg_batch(int dtype, bool dg, void *states, const RegSeg *segs, int nseg,
+                                 uint64_t items, const TileArgs *tas, const RegOp *rops,
+                                 const void *pool, uint32_t img_max, hipStream_t s) {
+    if (dtype == 0)
+        return dg ? launch_reg_batch_t<double, true>(states, segs, nseg, items, tas, rops, pool, img_max, s)
+                  : launch_reg_batch_t<double, false>(states, segs, nseg, items, tas, rops, pool, img_max, s);
+    return dg ? launch_reg_batch_t<float, true>(states, segs, nseg, items, tas, rops, pool, img_max, s)
+              : launch_reg_batch_t<float, false>(states, segs, nseg, items, tas, rops, pool, img_max, s);
+}
+
 int tile_pass_max_bits(int dtype) { return dtype == 0 ? 13 : 14; }
 // 16 amplitudes per thread: 64 VGPRs of state for complex128, 32 for complex64
 int tile_reg_bits(int) { return 4; }
