@@ -484,21 +484,30 @@ def form_batched(pergate_sample: int = 256):
         out[dt] = {"circuits_per_s": len(circuits) / best, "s_per_batch": best,
                    "device_ms": info["last_ms"], "tile_bits": info["tile_bits"],
                    "k_fuse": info["k_fuse"], "setup_s_incl_autotune": setup}
-        # Bytes the Pauli sums of the circuits above the LDS limit read (each
-        # term sweeps its circuit's state once; the smaller circuits never
-        # leave LDS).  A lower bound on the batch's memory traffic, most of
-        # it served by L2 and the last-level cache since each state is
-        # re-read per term.
+        # Global-memory bytes of the Pauli sums of the circuits above the LDS
+        # limit: each chunk of 2^cl amplitudes is read once into LDS, and a
+        # term whose highest X bit lies above the chunk reads the partner half
+        # of the state (the pairs' other members); strings of Z letters and
+        # pairs inside a chunk add nothing.  A lower bound on the batch's
+        # traffic (the tile passes add 2 x state per pass), much of it served
+        # by L2 and the last-level cache since a state is re-read per term.
         elem = 8 if dt == "c64" else 16
         mb = info["tile_bits"]
-        sweep = float(sum(len(h.coeff) * (1 << c.n) * elem
-                          for c, h in zip(circuits, hams) if c.n > mb))
+        cl = 12 if dt == "c64" else 11
+        sweep = 0.0
+        for c, h in zip(circuits, hams):
+            if c.n <= mb:
+                continue
+            dim = float(1 << c.n)
+            clc = min(cl, c.n)
+            far = sum(1 for x in h.xmask if int(x) and int(x).bit_length() - 1 >= clc)
+            sweep += dim * elem + far * dim / 2 * elem
         out[dt]["roofline"] = {
-            "pauli_sweep_bytes": sweep,
-            "pauli_sweep_GBps": sweep / (info["last_ms"] * 1e-3) / 1e9 if info["last_ms"] else None,
+            "pauli_read_bytes": sweep,
+            "pauli_read_GBps": sweep / (info["last_ms"] * 1e-3) / 1e9 if info["last_ms"] else None,
             "frac_of_hbm_peak": sweep / (info["last_ms"] * 1e-3) / HBM_PEAK if info["last_ms"] else None,
-            "note": "Pauli-sweep reads only over the whole batch time; the tile passes of the "
-                    "large circuits add 2 x state per pass"}
+            "note": "Pauli-sum global reads only, over the whole batch time; the tile passes of "
+                    "the large circuits add 2 x state per pass"}
         log("  batched %s: %.4f s per batch" % (dt, best))
     out["c64"]["max_abs_err_over_sum_abs_c_vs_c128_batch"] = float(
         np.max(np.abs(vals["c64"] - vals["c128"]) / scale))

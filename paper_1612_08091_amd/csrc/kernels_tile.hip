@@ -587,9 +587,11 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg(typename VT<R>::T *__restr
 }
 
 // Batched form: one pass index of many states (segments of tiles, each
-// segment one state's pass with its own program and image), work items
-// taken in a fixed stride.  A workgroup reloads the image and its thread
-// parts of the layouts when its segment changes.
+// segment one state's pass with its own program and image).  Workgroup w
+// takes the contiguous items [w c, (w + 1) c), c = ceil(items / grid), so it
+// mostly stays within one segment; it finds its first segment by binary
+// search, steps to the next one when its items cross a segment's end, and
+// reloads the image and its thread parts of the layouts at each change.
 template <typename R, int RB, int TB, bool DG>
 __global__ __launch_bounds__(1 << TB) void k_tile_reg_batch(typename VT<R>::T *__restrict__ states,
                                                         const RegSeg *__restrict__ segs, int nseg,
@@ -608,15 +610,22 @@ __global__ __launch_bounds__(1 << TB) void k_tile_reg_batch(typename VT<R>::T *_
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    int cur = -1;
-    uint64_t gl = 0, gs = 0;
-    for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
-        int lo = 0, hi = nseg - 1;
+    const uint64_t per = (items + gridDim.x - 1) / gridDim.x;
+    const uint64_t it0 = (uint64_t)blockIdx.x * per;
+    const uint64_t it1 = it0 + per < items ? it0 + per : items;
+    int lo = 0;
+    if (it0 < it1) {
+        int hi = nseg - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (segs[mid].first <= it) lo = mid;
+            if (segs[mid].first <= it0) lo = mid;
             else hi = mid - 1;
         }
+    }
+    int cur = -1;
+    uint64_t gl = 0, gs = 0;
+    for (uint64_t it = it0; it < it1; ++it) {
+        while (lo + 1 < nseg && segs[lo + 1].first <= it) ++lo;
         const RegSeg sg = segs[lo];
         const TileArgs &ta = tas[sg.ta];
         if (lo != cur) {
