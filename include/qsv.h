@@ -400,7 +400,8 @@ qsv_status qsv_adjoint_gradient(qsv_sim *sim, const qsv_circuit *circ,
 /* Batched expectation values: circuit b (gates only RX/RY/RZ/fixed matrices
  * on <= 2 qubits) and its Pauli sum give out[b] = <0|U_b^dag H_b U_b|0>.
  * A plan uploads the circuits once and holds an instantiated HIP graph of
- * the persistent launch; qsv_batch_run replays it. */
+ * its launches (a persistent launch for the circuits whose state fits in
+ * LDS, pass-major launches for the larger ones); qsv_batch_run replays it. */
 typedef struct qsv_batch qsv_batch;
 
 typedef struct qsv_batch_options {

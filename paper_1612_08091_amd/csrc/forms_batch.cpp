@@ -1,11 +1,14 @@
 // Batched form: many small circuits, each with its own Pauli sum, evaluated
-// by one persistent kernel launch that is captured once in a HIP graph and
-// replayed.
+// by launches that are captured once in a HIP graph and replayed.
 //
 // At creation every circuit is canonicalised, fused and planned into LDS-tile
-// passes for a tile of min(n, mb) bits; circuits are ordered by decreasing
-// estimated cost (longest-processing-time first) so that the persistent
-// workgroups finish together.  The tile bits mb and the fusion width are
+// passes for a tile of min(n, mb) bits.  Circuits whose state fits in LDS
+// (n <= mb) run in one persistent launch, ordered by decreasing estimated
+// cost (longest-processing-time first) so that its workgroups finish
+// together.  Larger ones run pass-major: one launch per pass index over the
+// tiles of all of them (circuits of at least 13 qubits on the register-tile
+// kernel, planned and lowered as a single state is), then their Pauli sums
+// in chunks.  The tile bits mb and the fusion width are
 // picked by timing candidate plans on the device (autotune) and remembered in
 // a JSON cache keyed by device, dtype and the circuit-size histogram.
 #include <hip/hip_runtime_api.h>

@@ -1,11 +1,12 @@
 // Batched expectation values: many small circuits, each with its own Pauli
-// sum, evaluated by one persistent launch.  Every workgroup repeatedly takes
-// the next circuit from an atomic counter (circuits are ordered longest
-// first), simulates it alone and writes <H>.  A state of at most MB qubits
-// lives in LDS for its whole life; a larger one lives in a per-workgroup
-// slot of global memory and is updated by LDS-tile passes planned on the
-// host.  No workgroup ever waits for another, so the grid drains as soon as
-// the counter passes the number of circuits.
+// sum.  k_batch is a persistent launch: every workgroup repeatedly takes the
+// next circuit from an atomic counter (circuits are ordered longest first),
+// simulates it alone and writes <H>.  A state of at most MB qubits lives in
+// LDS for its whole life; a larger one given to k_batch lives in a
+// per-workgroup slot of global memory and is updated by LDS-tile passes
+// planned on the host.  No workgroup ever waits for another, so the grid
+// drains as soon as the counter passes the number of circuits.  The
+// pass-major kernels further down serve the larger circuits otherwise.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

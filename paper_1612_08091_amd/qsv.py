@@ -618,8 +618,9 @@ def math_table(func, widths: Sequence[int]) -> np.ndarray:
 
 
 class Batch:
-    """Many small circuits with their Pauli sums, evaluated by one persistent
-    launch (replayed from a HIP graph)."""
+    """Many small circuits with their Pauli sums, evaluated by one HIP-graph
+    replay: circuits that fit in LDS in one persistent launch, larger ones
+    pass-major (big_per_workgroup=True: each on one workgroup instead)."""
 
     def __init__(self, circuits, hams, dtype="c64", autotune=True, tile_bits=0,
                  use_graph=True, stream=None, tune_cache=None, big_per_workgroup=False):

@@ -1,5 +1,6 @@
 """Batched form on the GPU: many HEA circuits of uneven size, each with its
-own Pauli sum, in one persistent launch replayed from a HIP graph.
+own Pauli sum, evaluated by one HIP-graph replay (circuits that fit in LDS
+in one persistent launch, larger ones pass-major).
 
 Bars: complex128 batches within 1e-12 * sum|c| of the oracle; complex64
 batches within 1e-5 * sum|c| (the FP32 tolerance on reductions).  Graph
