@@ -231,7 +231,10 @@ struct PauliGroup {
 hipError_t pauli_expectation(int dtype, const void *psi, int nq, int ngroups,
                              const PauliGroup *groups_host, const uint64_t *z_dev,
                              const double *coef_dev, const int32_t *ny_dev, int nterms,
-                             double *ws, size_t ws_bytes, double *out_dev, hipStream_t s);
+                             double *ws, size_t ws_bytes, double *out_dev, hipStream_t s,
+                             const uint64_t *z_host = nullptr);   // z masks on the host (same
+                                                                  // order): enables the one-read
+                                                                  // tiled path
 size_t pauli_workspace_bytes(int nq, int ngroups, int nterms);
 
 // ---------------------------------------------------------------- adjoint

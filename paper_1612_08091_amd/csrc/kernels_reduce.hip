@@ -384,16 +384,207 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_finish(const double *part
     }
 }
 
+// A Pauli sum whose X letters all lie on few qubits, in one read of the
+// state: a workgroup takes tiles of 2^m amplitudes whose positions hold every
+// qubit with an X letter (and the lowest positions, for contiguous reads),
+// reads each tile into LDS once and forms every term's share from it: both
+// members of each pair (j, j ^ x) lie in the tile.  Signs split into the part
+// from the tile's base index and the part from the local index.  Per-thread
+// sums over all tiles, then one block sum per term, the blocks added in order
+// by k_pauli_tiled_finish.
+constexpr int kPauliTiledTerms = 16;
+// bit i of l placed at position tpos[i], i < m
+__device__ __forceinline__ uint64_t pdeposit(uint32_t l, const uint32_t *tpos, int m) {
+    uint64_t out = 0;
+    for (int i = 0; i < m; ++i) out |= (uint64_t)((l >> i) & 1u) << tpos[i];
+    return out;
+}
+struct PauliTiled {
+    int32_t m, nt;
+    uint32_t tpos[16];                 // tile positions, ascending
+    uint32_t xl[kPauliTiledTerms];     // X mask on local bits
+    uint32_t zl[kPauliTiledTerms];     // Z mask on local bits
+    uint64_t zo[kPauliTiledTerms];     // Z mask outside the tile
+    int32_t hb[kPauliTiledTerms];      // highest bit of xl, -1 for none
+};
+
+template <typename R>
+__global__ __launch_bounds__(kRedThreads) void k_pauli_tiled(const typename V2r<R>::T *psi, int nq,
+                                                             const PauliTiled pt,
+                                                             double *partial) {
+    using T = typename V2r<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_p[];
+    T *ch = reinterpret_cast<T *>(smem_p);
+    __shared__ double sh[16];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tsize = 1u << pt.m;
+    const uint64_t ntiles = 1ull << (nq - pt.m);
+    const uint64_t dep_tid = pdeposit(tid, pt.tpos, 8);
+    double ar[kPauliTiledTerms], ai[kPauliTiledTerms];
+#pragma unroll
+    for (int t = 0; t < kPauliTiledTerms; ++t) ar[t] = ai[t] = 0.0;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint64_t base = tile;
+        for (int i = 0; i < pt.m; ++i) {
+            const uint64_t lowm = (1ull << pt.tpos[i]) - 1;
+            base = ((base & ~lowm) << 1) | (base & lowm);
+        }
+        // local index tid + 256 k: the low 8 bits from the thread, the rest
+        // uniform per k
+        for (uint32_t k = 0; k < (tsize >> 8); ++k)
+            ch[tid + (k << 8)] = psi[base | dep_tid | pdeposit(k << 8, pt.tpos, pt.m)];
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kPauliTiledTerms; ++t) {
+            if (t >= pt.nt) continue;
+            const double sb = (__popcll(base & pt.zo[t]) & 1) ? -1.0 : 1.0;
+            const uint32_t zl = pt.zl[t];
+            if (pt.hb[t] < 0) {
+                double acc = 0.0;
+                for (uint32_t l = tid; l < tsize; l += kRedThreads) {
+                    const T a = ch[l];
+                    const double p = (double)a.x * a.x + (double)a.y * a.y;
+                    acc += (__popc(l & zl) & 1) ? -p : p;
+                }
+                ar[t] += sb * acc;
+            } else {
+                const uint32_t xl = pt.xl[t];
+                const uint32_t lowm = (1u << pt.hb[t]) - 1;
+                double sr = 0.0, si = 0.0;
+                for (uint32_t g = tid; g < (tsize >> 1); g += kRedThreads) {
+                    const uint32_t l = ((g & ~lowm) << 1) | (g & lowm);
+                    const uint32_t l2 = l ^ xl;
+                    const T a = ch[l], b = ch[l2];
+                    const double u = (double)b.x * a.x + (double)b.y * a.y;
+                    const double v = (double)b.x * a.y - (double)b.y * a.x;
+                    const double s1 = (__popc(l & zl) & 1) ? -1.0 : 1.0;
+                    const double s2 = (__popc(l2 & zl) & 1) ? -1.0 : 1.0;
+                    sr += (s1 + s2) * u;
+                    si += (s1 - s2) * v;
+                }
+                ar[t] += sb * sr;
+                ai[t] += sb * si;
+            }
+        }
+        __syncthreads();   // the tile is rewritten next
+    }
+    double *out = partial + (size_t)blockIdx.x * 2 * kPauliTiledTerms;
+#pragma unroll
+    for (int t = 0; t < kPauliTiledTerms; ++t) {
+        if (t >= pt.nt) continue;
+        const double r = block_sum(ar[t], sh);
+        const double i = block_sum(ai[t], sh);
+        if (tid == 0) {
+            out[2 * t] = r;
+            out[2 * t + 1] = i;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_pauli_tiled_finish(const double *partial,
+                                                                    int nblocks, int nt,
+                                                                    const double *coef,
+                                                                    const int32_t *ny,
+                                                                    double *out) {
+    __shared__ double sh[16];
+    double tr = 0.0, ti = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        double sr = 0.0, si = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+            sr += partial[(size_t)b * 2 * kPauliTiledTerms + 2 * t];
+            si += partial[(size_t)b * 2 * kPauliTiledTerms + 2 * t + 1];
+        }
+        sr = block_sum(sr, sh);
+        si = block_sum(si, sh);
+        if (threadIdx.x == 0) {
+            double vr = sr, vi = si;   // multiply by i^{ny}
+            switch (ny[t] & 3) {
+            case 1: { double tmp = vr; vr = -vi; vi = tmp; } break;
+            case 2: vr = -vr; vi = -vi; break;
+            case 3: { double tmp = vr; vr = vi; vi = -tmp; } break;
+            default: break;
+            }
+            tr += coef[t] * vr;
+            ti += coef[t] * vi;
+        }
+    }
+    if (threadIdx.x == 0) {
+        out[0] = tr;
+        out[1] = ti;
+    }
+}
+
+constexpr int kPauliTiledBlocks = 2048;
+
 size_t pauli_workspace_bytes(int, int nchunks, int) {
-    return sizeof(double) * 2 * kPauliChunk * (size_t)kPauliBlocks * nchunks +
-           sizeof(PauliChunk) * nchunks + 256;
+    const size_t chunked = sizeof(double) * 2 * kPauliChunk * (size_t)kPauliBlocks * nchunks +
+                           sizeof(PauliChunk) * nchunks + 256;
+    const size_t tiled = sizeof(double) * 2 * kPauliTiledTerms * (size_t)kPauliTiledBlocks + 256;
+    return chunked > tiled ? chunked : tiled;
+}
+
+// The tiled plan when every term's X letters fit in a tile of m bits (with
+// the lowest positions filling the rest) and there are at most 16 terms:
+// then one read of the state serves the whole sum.
+static bool pauli_tiled_plan(int dtype, int nq, int ngroups, const PauliGroup *groups,
+                             const uint64_t *z_host, int nterms, PauliTiled &pt) {
+    const int m = dtype == 0 ? 11 : 12;   // 32 KiB of LDS
+    if (z_host == nullptr || nterms < 1 || nterms > kPauliTiledTerms || nq < m + 1) return false;
+    uint64_t u = 0;
+    for (int g = 0; g < ngroups; ++g) u |= groups[g].x;
+    if (__builtin_popcountll(u) > m - 3) return false;
+    uint64_t tile = u;
+    for (int b = 0; b < nq && __builtin_popcountll(tile) < m; ++b) tile |= 1ull << b;
+    pt = PauliTiled{};
+    pt.m = m;
+    pt.nt = nterms;
+    int loc[64];
+    int c = 0;
+    for (int b = 0; b < 64; ++b) {
+        loc[b] = -1;
+        if ((tile >> b) & 1) {
+            loc[b] = c;
+            pt.tpos[c++] = (uint32_t)b;
+        }
+    }
+    auto to_local = [&](uint64_t mask) {
+        uint32_t r = 0;
+        for (int b = 0; b < 64; ++b)
+            if (((mask >> b) & 1) && loc[b] >= 0) r |= 1u << loc[b];
+        return r;
+    };
+    for (int g = 0; g < ngroups; ++g)
+        for (int k = 0; k < groups[g].count; ++k) {
+            const int t = groups[g].first + k;
+            pt.xl[t] = to_local(groups[g].x);
+            pt.zl[t] = to_local(z_host[t]);
+            pt.zo[t] = z_host[t] & ~tile;
+            pt.hb[t] = pt.xl[t] ? 31 - __builtin_clz(pt.xl[t]) : -1;
+        }
+    return true;
 }
 
 hipError_t pauli_expectation(int dtype, const void *psi, int nq, int ngroups,
                              const PauliGroup *groups, const uint64_t *z_dev,
                              const double *coef_dev, const int32_t *ny_dev, int nterms,
-                             double *ws, size_t ws_bytes, double *out_dev, hipStream_t s) {
-    (void)nterms;
+                             double *ws, size_t ws_bytes, double *out_dev, hipStream_t s,
+                             const uint64_t *z_host) {
+    PauliTiled pt;
+    if (pauli_tiled_plan(dtype, nq, ngroups, groups, z_host, nterms, pt)) {
+        const uint64_t ntiles = 1ull << (nq - pt.m);
+        const unsigned nb = (unsigned)(ntiles < kPauliTiledBlocks ? ntiles : kPauliTiledBlocks);
+        if (sizeof(double) * 2 * kPauliTiledTerms * nb > ws_bytes) return hipErrorInvalidValue;
+        const size_t lds = (dtype == 0 ? 16 : 8) << pt.m;
+        if (dtype == 0)
+            hipLaunchKernelGGL(k_pauli_tiled<double>, dim3(nb), dim3(kRedThreads), lds, s,
+                               (const double2 *)psi, nq, pt, ws);
+        else
+            hipLaunchKernelGGL(k_pauli_tiled<float>, dim3(nb), dim3(kRedThreads), lds, s,
+                               (const float2 *)psi, nq, pt, ws);
+        hipLaunchKernelGGL(k_pauli_tiled_finish, dim3(1), dim3(kRedThreads), 0, s, ws, (int)nb,
+                           nterms, coef_dev, ny_dev, out_dev);
+        return hipGetLastError();
+    }
     // split groups into chunks of <= 8 terms
     std::size_t nch = 0;
     for (int g = 0; g < ngroups; ++g) nch += (groups[g].count + kPauliChunk - 1) / kPauliChunk;

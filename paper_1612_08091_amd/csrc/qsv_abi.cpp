@@ -1181,7 +1181,7 @@ static qsv_status expectation_positions(qsv_sim *s, const void *psi, int nq, int
     const int tok = tbegin(s);
     QSV_HIP(s, qsv::dev::pauli_expectation(s->opt.dtype, psi, nq, (int)groups.size(), groups.data(),
                                            dz, dc, dny, nterms, ws, s->ws_bytes - meta,
-                                           s->d_small, s->stream));
+                                           s->d_small, s->stream, zs.data()));
     tend(s, tok, QSV_K_REDUCE, (double)nchunks * (double)(1ull << nq) * s->elem());
     double h[2];
     QSV_HIP(s, hipMemcpyAsync(h, s->d_small, sizeof(h), hipMemcpyDeviceToHost, s->stream));

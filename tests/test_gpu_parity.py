@@ -334,6 +334,50 @@ def test_expectation(dtype):
         s.close()
 
 
+def local_x_hamiltonian(n, terms, rng, xq):
+    """Terms whose X and Y letters sit on the qubits xq only; Z letters
+    anywhere; a Z-only term and two terms sharing an X mask included."""
+    strings = []
+    for t in range(terms):
+        p = ["I"] * n
+        for q in rng.choice(n, size=3, replace=False):
+            p[int(q)] = "Z"
+        if t % 5 != 0:
+            for q in rng.choice(xq, size=int(rng.integers(1, 4)), replace=False):
+                p[int(q)] = "XY"[int(rng.integers(0, 2))]
+        strings.append("".join(p))
+    strings.append(strings[1].replace("Z", "I"))
+    return W.PauliSum.from_strings(strings, rng.standard_normal(len(strings)))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_expectation_local_x_terms(dtype):
+    """Pauli sums of at most 16 terms whose X letters lie on at most 8 qubits
+    take one read of the state (tiles holding every such qubit); against the
+    oracle, at sizes with one and with many tiles, X letters low and high,
+    and against the chunked path (the same sum with a 17th term)."""
+    rng = np.random.default_rng(13)
+    for n, xq in [(13, [0, 5, 12]), (20, [0, 2, 4, 6, 11, 13, 15, 17]), (22, [3, 9, 20, 21])]:
+        circ = random_circuit(rng, n, 60)
+        ham = local_x_hamiltonian(n, 15, rng, xq)
+        assert len(ham) == 16
+        s = make(n, dtype=dtype)
+        s.run(circ)
+        got = s.expectation(ham)
+        re, im = s.get_expectation_complex(ham.xmask, ham.zmask, ham.coeff)
+        want, _ = oracle.expectation(oracle.run(circ), ham)
+        scale = max(1.0, float(np.sum(np.abs(ham.coeff))))
+        tol = 1e-12 * scale if dtype == "c128" else 1e-5 * scale
+        assert abs(got - want) <= tol, (n, got, want)
+        assert abs(im) <= tol, (n, im)
+        # a 17th term (zero coefficient) sends the sum to the chunked path
+        big = W.PauliSum(np.append(ham.xmask, np.uint64(1 << (n - 1))),
+                         np.append(ham.zmask, np.uint64(0)), np.append(ham.coeff, 0.0))
+        other = s.expectation(big)
+        assert abs(other - got) <= tol, (n, other, got)
+        s.close()
+
+
 def test_probability_masks():
     rng = np.random.default_rng(12)
     n = 14
