@@ -561,10 +561,20 @@ std::vector<Op> pass_ops_in_qubit_order(const std::vector<Pass> &passes, int n) 
 double plan_cost(const std::vector<Pass> &passes, int page_bit) {
     // relative time of a pass whose tile spans 2^h pages (measured on
     // 12-bit tiles of a 30-qubit complex128 state: flat up to 32 pages,
-    // 1.2 x at 64, 2.3-4.7 x at 256)
+    // 1.2 x at 64, 2.3-4.7 x at 256), and of a pass that carries more fused
+    // ops than its memory traffic hides (measured on the same tiles: a pass
+    // reads and writes the state in about the time of 16 fused 2-qubit ops;
+    // beyond that it grows with the ops; a diagonal op, one factor per
+    // amplitude from a table, counts a quarter)
     static const double kCost[11] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.05, 1.2, 1.6, 2.5, 3.5, 4.7};
+    constexpr double kOpsPerPass = 16.0;
     double c = 0.0;
-    for (const Pass &p : passes) c += kCost[std::min(10, popc(page_bit >= 64 ? 0 : p.tile >> page_bit))];
+    for (const Pass &p : passes) {
+        double w = 0.0;
+        for (const Op &o : p.ops) w += o.mixing() ? 1.0 : 0.25;
+        c += kCost[std::min(10, popc(page_bit >= 64 ? 0 : p.tile >> page_bit))] *
+             std::max(1.0, w / kOpsPerPass);
+    }
     return c;
 }
 
@@ -573,17 +583,20 @@ std::vector<Pass> plan_tiled(const std::vector<Op> &ops, int n, int m, int k_max
     std::vector<Op> fused = fuse_impl(ops, k_max, ~0ull, kMaxK);
     std::vector<Pass> best = plan_passes(fused, n, m, 3, k_max, kMaxK);
     if (!relabel || n <= m) return best;
-    // the greedy grouping reacts to the cap unevenly: plan with several caps
-    // and keep the cheapest plan (positions fixed included)
+    // the greedy grouping reacts to the caps unevenly: plan with several page
+    // caps and caps on the ops a pass takes, and keep the cheapest plan
+    // (positions fixed included)
     double best_cost = plan_cost(best, page_bit);
-    for (int cap : {2, 3, 4, 5, 8}) {
-        std::vector<Pass> c = plan_passes_relabel(fused, n, m, 3, k_max, kMaxK, page_bit, cap);
-        const double cost = plan_cost(c, page_bit);
-        if (cost < best_cost - 1e-9) {
-            best_cost = cost;
-            best.swap(c);
+    for (int op_cap : {1 << 30, 40, 32})
+        for (int cap : {2, 3, 4, 5, 8}) {
+            std::vector<Pass> c =
+                plan_passes_relabel(fused, n, m, 3, k_max, kMaxK, page_bit, cap, op_cap);
+            const double cost = plan_cost(c, page_bit);
+            if (cost < best_cost - 1e-9) {
+                best_cost = cost;
+                best.swap(c);
+            }
         }
-    }
     return best;
 }
 }  // namespace qsv

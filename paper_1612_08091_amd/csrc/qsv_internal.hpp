@@ -130,14 +130,15 @@ std::vector<Op> pass_ops_in_qubit_order(const std::vector<Pass> &passes, int n);
 
 // Estimated time of a plan in passes over the state, each weighted by the
 // number of 2 MiB pages its tile spans (a tile spread over 2^h pages reads
-// far slower once h passes about 5).
+// far slower once h passes about 5) and by its ops beyond what its memory
+// traffic hides (about 16 fused 2-qubit ops; a diagonal op counts a quarter).
 double plan_cost(const std::vector<Pass> &passes, int page_bit);
 
 // Whole-queue fusion to k_max first (diagonal runs to kMaxK qubits), then
 // pass planning of the fused ops (blocks are not cut at pass boundaries);
 // three low bits stay in every tile for contiguous HBM runs.  relabel: also
-// plan with plan_passes_relabel under several page caps and keep the plan of
-// least plan_cost (page_bit: the amplitude index bit of a 2 MiB page, 17 for
+// plan with plan_passes_relabel under several page caps and caps on the ops
+// per pass (none, 40, 32) and keep the plan of least plan_cost (page_bit: the amplitude index bit of a 2 MiB page, 17 for
 // complex128 and 18 for complex64).
 std::vector<Pass> plan_tiled(const std::vector<Op> &ops, int n, int m, int k_max,
                              int page_bit = 64, bool relabel = false);
