@@ -8,8 +8,10 @@
 // order of execution only across operations that commute, and they multiply
 // matrices exactly (up to rounding), so the result is the per-gate result.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "qsv_internal.hpp"
 
@@ -586,16 +588,40 @@ std::vector<Pass> plan_tiled(const std::vector<Op> &ops, int n, int m, int k_max
     // the greedy grouping reacts to the caps unevenly: plan with several page
     // caps and caps on the ops a pass takes, and keep the cheapest plan
     // (positions fixed included)
-    double best_cost = plan_cost(best, page_bit);
+    // The candidates are independent: large queues plan them on several host
+    // threads (the GPU waits for the plan), the choice is the same as in order.
+    struct Cand {
+        int op_cap, cap;
+        std::vector<Pass> plan;
+        double cost = 0.0;
+    };
+    std::vector<Cand> cands;
     for (int op_cap : {1 << 30, 40, 32})
-        for (int cap : {2, 3, 4, 5, 8}) {
-            std::vector<Pass> c =
-                plan_passes_relabel(fused, n, m, 3, k_max, kMaxK, page_bit, cap, op_cap);
-            const double cost = plan_cost(c, page_bit);
-            if (cost < best_cost - 1e-9) {
-                best_cost = cost;
-                best.swap(c);
-            }
+        for (int cap : {2, 3, 4, 5, 8}) cands.push_back({op_cap, cap, {}, 0.0});
+    auto work = [&](size_t i) {
+        cands[i].plan = plan_passes_relabel(fused, n, m, 3, k_max, kMaxK, page_bit, cands[i].cap,
+                                            cands[i].op_cap);
+        cands[i].cost = plan_cost(cands[i].plan, page_bit);
+    };
+    const unsigned hw = std::thread::hardware_concurrency();
+    const size_t nth = fused.size() < 64 ? 1 : std::min<size_t>(cands.size(), std::min(8u, std::max(1u, hw)));
+    if (nth <= 1) {
+        for (size_t i = 0; i < cands.size(); ++i) work(i);
+    } else {
+        std::atomic<size_t> next{0};
+        std::vector<std::thread> th;
+        th.reserve(nth);
+        for (size_t t = 0; t < nth; ++t)
+            th.emplace_back([&]() {
+                for (size_t i; (i = next.fetch_add(1)) < cands.size();) work(i);
+            });
+        for (std::thread &x : th) x.join();
+    }
+    double best_cost = plan_cost(best, page_bit);
+    for (Cand &c : cands)
+        if (c.cost < best_cost - 1e-9) {
+            best_cost = c.cost;
+            best.swap(c.plan);
         }
     return best;
 }

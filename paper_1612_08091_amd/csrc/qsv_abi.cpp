@@ -9,6 +9,8 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -393,10 +395,36 @@ qsv_status run_tile_passes(qsv_sim *s, const std::vector<Pass> &passes) {
     std::vector<double> mats;
     std::vector<qsv::TileProgram> progs(passes.size());
     size_t n_rops = 0, n_lops = 0;
-    for (size_t pi = 0; pi < passes.size(); ++pi) {
-        qsv::compile_pass(passes[pi], rb, mats, progs[pi], (int)s->elem());
-        n_rops += progs[pi].rops.size();
-        n_lops += progs[pi].lops.size();
+    {
+        // Passes lower independently, on several host threads when there
+        // are many (the GPU waits for the programs): each into its own
+        // matrix list, then the lists are joined and the LDS ops' matrix
+        // offsets moved by their pass's start.
+        std::vector<std::vector<double>> pm(passes.size());
+        auto work = [&](size_t pi) {
+            qsv::compile_pass(passes[pi], rb, pm[pi], progs[pi], (int)s->elem());
+        };
+        const unsigned hw = std::thread::hardware_concurrency();
+        const size_t nth = passes.size() < 4 ? 1 : std::min<size_t>(passes.size(), std::min(8u, std::max(1u, hw)));
+        if (nth <= 1) {
+            for (size_t pi = 0; pi < passes.size(); ++pi) work(pi);
+        } else {
+            std::atomic<size_t> next{0};
+            std::vector<std::thread> th;
+            th.reserve(nth);
+            for (size_t t = 0; t < nth; ++t)
+                th.emplace_back([&]() {
+                    for (size_t i; (i = next.fetch_add(1)) < passes.size();) work(i);
+                });
+            for (std::thread &x : th) x.join();
+        }
+        for (size_t pi = 0; pi < passes.size(); ++pi) {
+            const int64_t base = (int64_t)(mats.size() / 2);
+            for (qsv::dev::TileOp &t : progs[pi].lops) t.mat += base;
+            mats.insert(mats.end(), pm[pi].begin(), pm[pi].end());
+            n_rops += progs[pi].rops.size();
+            n_lops += progs[pi].lops.size();
+        }
     }
     // pool: [RegOp array][TileOp array][one zeroed tile counter per pass]
     //       [matrices in the state dtype][LDS images of the register passes]
