@@ -413,6 +413,9 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_tiled(const typename V2r<
                                                              const PauliTiled pt,
                                                              double *partial) {
     using T = typename V2r<R>::T;
+    // tiles of 2^m amplitudes, m = 11 (complex128) or 12 (complex64): 2^m /
+    // 256 loads per thread
+    constexpr int KL = sizeof(R) == 8 ? 8 : 16;
     extern __shared__ __align__(16) unsigned char smem_p[];
     T *ch = reinterpret_cast<T *>(smem_p);
     __shared__ double sh[16];
@@ -430,9 +433,12 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_tiled(const typename V2r<
             base = ((base & ~lowm) << 1) | (base & lowm);
         }
         // local index tid + 256 k: the low 8 bits from the thread, the rest
-        // uniform per k
-        for (uint32_t k = 0; k < (tsize >> 8); ++k)
-            ch[tid + (k << 8)] = psi[base | dep_tid | pdeposit(k << 8, pt.tpos, pt.m)];
+        // uniform per k; all of a thread's loads go out before any LDS write
+        T v[KL];
+#pragma unroll
+        for (int k = 0; k < KL; ++k) v[k] = psi[base | dep_tid | pdeposit((uint32_t)k << 8, pt.tpos, pt.m)];
+#pragma unroll
+        for (int k = 0; k < KL; ++k) ch[tid + ((uint32_t)k << 8)] = v[k];
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < kPauliTiledTerms; ++t) {
@@ -528,7 +534,7 @@ size_t pauli_workspace_bytes(int, int nchunks, int) {
 // then one read of the state serves the whole sum.
 static bool pauli_tiled_plan(int dtype, int nq, int ngroups, const PauliGroup *groups,
                              const uint64_t *z_host, int nterms, PauliTiled &pt) {
-    const int m = dtype == 0 ? 11 : 12;   // 32 KiB of LDS
+    const int m = dtype == 0 ? 11 : 12;   // 32 KiB of LDS (the kernel assumes these sizes)
     if (z_host == nullptr || nterms < 1 || nterms > kPauliTiledTerms || nq < m + 1) return false;
     uint64_t u = 0;
     for (int g = 0; g < ngroups; ++g) u |= groups[g].x;
