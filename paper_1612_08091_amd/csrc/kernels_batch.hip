@@ -347,7 +347,18 @@ __global__ __launch_bounds__(kNT) void k_batch_pauli(const BatchSeg *__restrict_
         const uint64_t k = it - sg.first;
         const uint64_t j0 = k << cl;
         const T *st = states + sg.state_off;
-        for (uint32_t l = tid; l < C; l += kNT) ch[l] = st[j0 + l];
+        {
+            // U loads of a thread out together before their LDS writes
+            uint32_t l = tid;
+            for (; l + (U - 1) * kNT < C; l += U * kNT) {
+                T v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[u] = st[j0 + l + u * kNT];
+#pragma unroll
+                for (int u = 0; u < U; ++u) ch[l + u * kNT] = v[u];
+            }
+            for (; l < C; l += kNT) ch[l] = st[j0 + l];
+        }
         __syncthreads();
         double acc = 0.0;
         for (int t = 0; t < bc.term_count; ++t) {
