@@ -406,6 +406,7 @@ struct PauliTiled {
     uint32_t zl[kPauliTiledTerms];     // Z mask on local bits
     uint64_t zo[kPauliTiledTerms];     // Z mask outside the tile
     int32_t hb[kPauliTiledTerms];      // highest bit of xl, -1 for none
+    uint32_t zterms;                   // bit t: term t has no X letter
 };
 
 template <typename R>
@@ -440,20 +441,28 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_tiled(const typename V2r<
 #pragma unroll
         for (int k = 0; k < KL; ++k) ch[tid + ((uint32_t)k << 8)] = v[k];
         __syncthreads();
+        // the strings of Z letters together, one read of the tile: sign bit
+        // of term t = parity of (l & zl[t]) ^ bit t of sbits (the base part)
+        if (pt.zterms) {
+            uint32_t sbits = 0;
+#pragma unroll
+            for (int t = 0; t < kPauliTiledTerms; ++t)
+                if ((pt.zterms >> t) & 1u) sbits |= (uint32_t)(__popcll(base & pt.zo[t]) & 1) << t;
+            for (uint32_t l = tid; l < tsize; l += kRedThreads) {
+                const T a = ch[l];
+                const double p = (double)a.x * a.x + (double)a.y * a.y;
+#pragma unroll
+                for (int t = 0; t < kPauliTiledTerms; ++t)
+                    if ((pt.zterms >> t) & 1u)
+                        ar[t] += ((__popc(l & pt.zl[t]) ^ (sbits >> t)) & 1) ? -p : p;
+            }
+        }
 #pragma unroll
         for (int t = 0; t < kPauliTiledTerms; ++t) {
-            if (t >= pt.nt) continue;
+            if (t >= pt.nt || pt.hb[t] < 0) continue;
             const double sb = (__popcll(base & pt.zo[t]) & 1) ? -1.0 : 1.0;
             const uint32_t zl = pt.zl[t];
-            if (pt.hb[t] < 0) {
-                double acc = 0.0;
-                for (uint32_t l = tid; l < tsize; l += kRedThreads) {
-                    const T a = ch[l];
-                    const double p = (double)a.x * a.x + (double)a.y * a.y;
-                    acc += (__popc(l & zl) & 1) ? -p : p;
-                }
-                ar[t] += sb * acc;
-            } else {
+            {
                 const uint32_t xl = pt.xl[t];
                 const uint32_t lowm = (1u << pt.hb[t]) - 1;
                 double sr = 0.0, si = 0.0;
@@ -566,6 +575,7 @@ static bool pauli_tiled_plan(int dtype, int nq, int ngroups, const PauliGroup *g
             pt.zl[t] = to_local(z_host[t]);
             pt.zo[t] = z_host[t] & ~tile;
             pt.hb[t] = pt.xl[t] ? 31 - __builtin_clz(pt.xl[t]) : -1;
+            if (pt.hb[t] < 0) pt.zterms |= 1u << t;
         }
     return true;
 }
